@@ -1,0 +1,217 @@
+"""ctypes shim over the C oracle (``mbpcg_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline of the benchmark load this module.  It never touches the GPU
+library and the GPU library never touches it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mbpcg_oracle.c")
+LIB = os.path.join(HERE, "libmbpcg_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "mbpcg_oracle.h"))):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class OrMatrix(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dense", C.c_int), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p), ("vals", C.c_void_p), ("a", C.c_void_p),
+                ("lda", C.c_int64)]
+
+
+class OrParams(C.Structure):
+    _fields_ = [("s", C.c_int), ("tol", C.c_double), ("tol_initial", C.c_double),
+                ("max_iter", C.c_int64), ("jacobi", C.c_int), ("seed", C.c_uint64),
+                ("U", C.c_void_p), ("tau", C.c_double), ("ls_scaled", C.c_int),
+                ("history", C.c_void_p), ("X_out", C.c_void_p), ("R_out", C.c_void_p),
+                ("prop1_gap", C.c_void_p)]
+
+
+class OrInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int64), ("best_column", C.c_int),
+                ("final_width", C.c_int), ("deflations", C.c_int), ("used_fallback", C.c_int),
+                ("rel_res_best", C.c_double), ("rel_res_ls", C.c_double),
+                ("rel_res_true", C.c_double), ("seconds", C.c_double),
+                ("seconds_setup", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        vp, i64, dbl = C.c_void_p, C.c_int64, C.c_double
+        L.or_set_summation.argtypes = [C.c_int]
+        L.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.or_splitmix64.restype = C.c_uint64
+        L.or_uniform_block.argtypes = [C.c_uint64, i64, C.c_int, vp]
+        L.or_matmul_block.argtypes = [vp, C.c_int, vp, vp]
+        L.or_gram.argtypes = [i64, C.c_int, vp, C.c_int, vp, vp]
+        L.or_cholesky.argtypes = [C.c_int, vp, vp]
+        L.or_spd_inverse.argtypes = [C.c_int, vp, vp]
+        L.or_cholqr_deflate.argtypes = [i64, C.c_int, vp, dbl, vp, vp, vp]
+        L.or_lstsq.argtypes = [i64, C.c_int, vp, vp, vp]
+        L.or_mbpcg_solve.argtypes = [vp, vp, vp, vp, vp]
+        L.or_hs_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, vp, vp, vp]
+        L.or_cg_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+class Matrix:
+    """Keeps the numpy arrays alive behind an OrMatrix."""
+
+    def __init__(self, A):
+        if isinstance(A, np.ndarray):
+            self.a = np.asfortranarray(A, dtype=np.float64)
+            self.s = OrMatrix(A.shape[0], 1, None, None, None, self.a.ctypes.data, A.shape[0])
+        else:
+            self.rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+            self.colind = np.ascontiguousarray(A.colind, dtype=np.int32)
+            self.vals = np.ascontiguousarray(A.vals, dtype=np.float64)
+            self.s = OrMatrix(A.n, 0, self.rowptr.ctypes.data, self.colind.ctypes.data,
+                              self.vals.ctypes.data, None, 0)
+        self.n = int(self.s.n)
+
+
+def set_summation(mode: int):
+    lib().or_set_summation(int(mode))
+
+
+def splitmix64(seed: int, k: int) -> int:
+    return int(lib().or_splitmix64(seed, k))
+
+
+def uniform_block(seed: int, n: int, s: int) -> np.ndarray:
+    U = np.empty((n, s))
+    lib().or_uniform_block(seed, n, s, U.ctypes.data)
+    return U
+
+
+def matmul_block(A, X):
+    M = A if isinstance(A, Matrix) else Matrix(A)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    k = 1 if X.ndim == 1 else X.shape[1]
+    Y = np.empty((M.n, k))
+    lib().or_matmul_block(C.byref(M.s), k, X.ctypes.data, Y.ctypes.data)
+    return Y.reshape(X.shape)
+
+
+def gram(X, Y):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    Cm = np.empty((X.shape[1], Y.shape[1]))
+    lib().or_gram(X.shape[0], X.shape[1], X.ctypes.data, Y.shape[1], Y.ctypes.data, Cm.ctypes.data)
+    return Cm
+
+
+def cholesky(Cm):
+    Cm = np.ascontiguousarray(Cm, dtype=np.float64)
+    L = np.empty_like(Cm)
+    rc = lib().or_cholesky(Cm.shape[0], Cm.ctypes.data, L.ctypes.data)
+    return rc, L
+
+
+def spd_inverse(L):
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    Xi = np.empty_like(L)
+    lib().or_spd_inverse(L.shape[0], L.ctypes.data, Xi.ctypes.data)
+    return Xi
+
+
+def cholqr_deflate(V, tau=1e-12):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    n, m = V.shape
+    W = np.empty(n * m)
+    Z = np.empty(m * m)
+    keep = np.zeros(m, dtype=np.int32)
+    k = lib().or_cholqr_deflate(n, m, V.ctypes.data, tau, W.ctypes.data, Z.ctypes.data,
+                                keep.ctypes.data)
+    return W[: n * k].reshape(n, k), Z[: k * m].reshape(k, m), keep.astype(bool)
+
+
+def lstsq(B, b):
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    c = np.zeros(B.shape[1])
+    rc = lib().or_lstsq(B.shape[0], B.shape[1], B.ctypes.data, b.ctypes.data, c.ctypes.data)
+    return rc, c
+
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -2: "NOT_SPD", -3: "BREAKDOWN", -4: "NONFINITE"}
+
+
+def mbpcg_solve(A, b, s, tol=1e-8, tol_initial=0.0, max_iter=100000, jacobi=True, seed=0,
+                U=None, tau=1e-12, ls_scaled=False, want_history=False, want_X=False,
+                want_prop1=False):
+    """Run Algorithm 1 on the CPU.  Returns (x, info dict, extras dict)."""
+    M = A if isinstance(A, Matrix) else Matrix(A)
+    n = M.n
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(n)
+    hist = np.full(max_iter, np.nan) if want_history else None
+    Xo = np.zeros((n, s)) if want_X else None
+    Ro = np.zeros((n, s)) if want_X else None
+    gap = np.full(max_iter, np.nan) if want_prop1 else None
+    Uc = None if U is None else np.ascontiguousarray(U, dtype=np.float64)
+    p = OrParams(s, tol, tol_initial, max_iter, int(bool(jacobi)), seed, _p(Uc), tau,
+                 int(bool(ls_scaled)), _p(hist), _p(Xo), _p(Ro), _p(gap))
+    info = OrInfo()
+    lib().or_mbpcg_solve(C.byref(M.s), b.ctypes.data, C.byref(p), x.ctypes.data, C.byref(info))
+    d = info.as_dict()
+    it = int(d["iterations"])
+    extra = {}
+    if want_history:
+        extra["history"] = hist[:it]
+    if want_X:
+        extra["X"] = Xo
+        extra["R"] = Ro
+    if want_prop1:
+        extra["prop1_gap"] = gap[:it]
+    return x, d, extra
+
+
+def _cg(fn, A, b, x0, tol, max_iter, jacobi, want_history):
+    M = A if isinstance(A, Matrix) else Matrix(A)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(M.n)
+    hist = np.full(max_iter, np.nan) if want_history else None
+    x0c = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+    info = OrInfo()
+    fn(C.byref(M.s), b.ctypes.data, _p(x0c), tol, max_iter, int(bool(jacobi)), x.ctypes.data,
+       _p(hist), C.byref(info))
+    d = info.as_dict()
+    return x, d, (hist[: int(d["iterations"])] if want_history else None)
+
+
+def hs_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=False):
+    return _cg(lib().or_hs_cg, A, b, x0, tol, max_iter, jacobi, want_history)
+
+
+def cg_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=False):
+    return _cg(lib().or_cg_cg, A, b, x0, tol, max_iter, jacobi, want_history)

@@ -1,0 +1,338 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: each check holds an oracle
+routine to a textbook library routine on a special case, to a closed form,
+to a published value, or to an invariant of the method (finite termination
+of block CG, Proposition 1, s = 1 reducing to CG).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle import oracle as O
+from paper_2608_07327_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build()
+    O.set_summation(0)
+    yield
+    O.set_summation(0)
+
+
+# ---------------------------------------------------------------- generator
+def test_splitmix64_published_vectors():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    for k, v in rows:
+        assert O.splitmix64(0, int(k)) == int(v, 16)
+
+
+def test_uniform_block_is_exact_dyadic_in_open_interval():
+    U = O.uniform_block(1234, 5000, 3)
+    assert U.min() >= -1.0 and U.max() < 1.0
+    assert abs(U.mean()) < 0.03 and abs(U.var() - 1.0 / 3.0) < 0.02
+    # every value is an integer multiple of 2^-52 (2u - 1 with u on a 2^-53 grid)
+    assert np.all(np.ldexp(U, 52) == np.round(np.ldexp(U, 52)))
+    # counter layout: entry (r, j) uses stream element j*n + r
+    z = O.splitmix64(1234, 2 * 5000 + 17)
+    assert U[17, 2] == 2.0 * ((z >> 11) * 2.0 ** -53) - 1.0
+
+
+# ---------------------------------------------------------- block kernels
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_csr_block_product_matches_scipy(k):
+    A = W.diffusion3d(9)
+    X = np.random.default_rng(1).standard_normal((A.n, k))
+    Y = O.matmul_block(A, X)
+    ref = A.to_scipy() @ X
+    assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("k", [1, 5])
+def test_dense_block_product_matches_numpy(k):
+    A = W.dense_spd(64, tag=(3, 1))
+    X = np.random.default_rng(2).standard_normal((64, k))
+    Y = O.matmul_block(A, X)
+    assert np.allclose(Y, A @ X, rtol=0, atol=1e-13 * np.abs(A @ X).max())
+
+
+def test_gram_matches_numpy():
+    rng = np.random.default_rng(3)
+    X, Y = rng.standard_normal((777, 4)), rng.standard_normal((777, 6))
+    assert np.allclose(O.gram(X, Y), X.T @ Y, rtol=1e-13, atol=1e-12)
+
+
+def test_cholesky_and_inverse_match_numpy():
+    rng = np.random.default_rng(4)
+    for m in (1, 2, 5, 16, 32):
+        G = rng.standard_normal((m + 3, m))
+        Cm = G.T @ G + 0.1 * np.eye(m)
+        rc, L = O.cholesky(Cm)
+        assert rc == 0
+        assert np.allclose(L, np.linalg.cholesky(Cm), rtol=1e-12, atol=1e-13)
+        Xi = O.spd_inverse(L)
+        assert np.allclose(Xi, np.linalg.inv(Cm), rtol=1e-10, atol=1e-12)
+    rc, _ = O.cholesky(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    assert rc == -1
+
+
+def test_cholesky_reads_lower_triangle_only():
+    Cm = np.array([[4.0, 99.0], [2.0, 5.0]])
+    _, L = O.cholesky(Cm)
+    assert np.allclose(L, np.linalg.cholesky(np.array([[4.0, 2.0], [2.0, 5.0]])))
+
+
+# ------------------------------------------------------------ Cholesky QR
+def test_cholqr_full_rank_matches_householder_qr():
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal((300, 6)) @ np.diag([1, 10, 0.1, 3, 1e3, 1])
+    Wm, Z, keep = O.cholqr_deflate(V)
+    assert keep.all() and Wm.shape == (300, 6)
+    q, r = np.linalg.qr(V)
+    sgn = np.sign(np.diag(r))
+    r = sgn[:, None] * r
+    assert np.allclose(Z, r, rtol=1e-9, atol=1e-9 * np.abs(r).max())
+    assert np.linalg.norm(Wm.T @ Wm - np.eye(6)) < 1e-9
+    assert np.linalg.norm(V - Wm @ Z) <= 1e-13 * np.linalg.norm(V)
+
+
+def test_cholqr_drops_dependent_and_zero_columns():
+    rng = np.random.default_rng(6)
+    a = rng.standard_normal((200, 3))
+    V = np.column_stack([a[:, 0], a[:, 1], a[:, 0] * 2.0 - a[:, 1], np.zeros(200), a[:, 2]])
+    Wm, Z, keep = O.cholqr_deflate(V)
+    assert keep.tolist() == [True, True, False, False, True]
+    assert Wm.shape == (200, 3) and Z.shape == (3, 5)
+    # V = W Z reproduces every column, dropped ones included
+    assert np.linalg.norm(V - Wm @ Z) <= 1e-12 * np.linalg.norm(V)
+    assert np.linalg.norm(Wm.T @ Wm - np.eye(3)) < 1e-12
+    # Z is upper trapezoidal in the kept rows
+    assert Z[1, 0] == 0 and Z[2, :4].tolist() == [0, 0, 0, 0]
+
+
+# --------------------------------------------------------- least squares
+def test_lstsq_matches_numpy():
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((500, 5))
+    b = rng.standard_normal(500)
+    rc, c = O.lstsq(B, b)
+    ref = np.linalg.lstsq(B, b, rcond=None)[0]
+    assert rc == 0 and np.allclose(c, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_lstsq_on_nearly_parallel_columns_keeps_the_residual():
+    # the termination step's shape: columns b - R_j with tiny, independent R_j
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(2000)
+    R = 1e-8 * rng.standard_normal((2000, 4))
+    B = b[:, None] - R
+    rc, c = O.lstsq(B, b)
+    r = b - B @ c
+    ref = np.linalg.lstsq(B, b, rcond=None)[0]
+    rref = b - B @ ref
+    assert rc == 0
+    assert abs(np.linalg.norm(r) - np.linalg.norm(rref)) <= 1e-6 * np.linalg.norm(rref)
+    # never worse than the best single column (c = e_h gives r = R_h)
+    assert np.linalg.norm(r) <= np.linalg.norm(R, axis=0).min() * (1 + 1e-6)
+
+
+# ------------------------------------------------------------ whole method
+def test_s1_equals_textbook_cg_from_the_same_start():
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    U = O.uniform_block(11, A.n, 1)
+    x, info, ex = O.mbpcg_solve(A, b, 1, U=U, want_history=True)
+    # X0 = gamma U with ||A~ X0|| = ||B~||; recompute it to start CG there
+    d = np.sqrt(A.to_scipy().diagonal())
+    As = (A.to_scipy().multiply(1.0 / d[:, None]).multiply(1.0 / d[None, :])).tocsr()
+    bbar = b / d
+    gamma = np.linalg.norm(bbar) / np.linalg.norm(As @ U[:, 0])
+    x0 = gamma * U[:, 0] / d
+    xh, ih, hh = O.hs_cg(A, b, x0=x0, want_history=True)
+    assert info["iterations"] == ih["iterations"]
+    h1 = ex["history"][:100]
+    assert np.max(np.abs(h1 - hh[:100]) / hh[:100]) < 1e-10
+    assert np.linalg.norm(x - xh) <= 1e-9 * np.linalg.norm(xh)
+
+
+def test_chronopoulos_gear_tracks_textbook_cg():
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    _, ic, hc = O.cg_cg(A, b, want_history=True)
+    _, ih, hh = O.hs_cg(A, b, want_history=True)
+    assert abs(ic["iterations"] - ih["iterations"]) <= 2
+    k = min(len(hc), len(hh))
+    assert np.max(np.abs(np.log10(hc[:k]) - np.log10(hh[:k]))) < 0.05
+    assert ic["rel_res_true"] < 2e-8
+
+
+@pytest.mark.parametrize("n,s,cond", [(12, 1, 30.0), (12, 2, 100.0), (12, 3, 1e3), (12, 4, 10.0),
+                                      (10, 3, 100.0), (16, 5, 1e3), (9, 9, 1e3), (16, 16, 100.0)])
+def test_finite_termination_in_ceil_n_over_s_steps(n, s, cond):
+    # block CG spans the whole space after ceil(n/s) block steps, so the
+    # residual collapses at exactly that step (up to rounding)
+    A = W.tiny_spd(n, cond, tag=(90, n, s))
+    b = W.rng_for((91, n)).standard_normal(n)
+    k = math.ceil(n / s)
+    x, info, ex = O.mbpcg_solve(A, b, s, tol=1e-14, max_iter=k, jacobi=False, seed=5,
+                                want_history=True)
+    h = ex["history"]
+    assert len(h) == k
+    assert h[k - 1] < 1e-6
+    if k > 1:
+        assert h[k - 2] > 1e-4
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-4 * np.linalg.norm(xs)
+
+
+def test_non_dividing_width_deflates_exactly():
+    n, s = 10, 3
+    A = W.tiny_spd(n, 50.0, tag=(92,))
+    b = W.rng_for((93,)).standard_normal(n)
+    x, info, ex = O.mbpcg_solve(A, b, s, tol=1e-14, max_iter=4, jacobi=False, seed=9,
+                                want_history=True)
+    # after 3 block steps only one direction is left: two columns drop, and
+    # the fourth step finishes the solve
+    assert ex["history"][3] < 1e-6 < ex["history"][2]
+    assert info["deflations"] == s - n % s
+    assert info["final_width"] == n % s
+
+
+def test_proposition1_and_best_column_bound():
+    A = W.poisson2d(32)
+    b = W.rhs(A.n, 41)
+    x, info, ex = O.mbpcg_solve(A, b, 4, seed=3, want_prop1=True, want_X=True, want_history=True)
+    assert info["status"] == 0
+    assert np.nanmax(ex["prop1_gap"]) < 1e-12
+    # the accepted combination is never worse than the best column, and its
+    # residual equals numpy's least-squares residual on B^ = B - D R
+    d = np.sqrt(A.to_scipy().diagonal())
+    Bh = b[:, None] - d[:, None] * ex["R"]
+    c = np.linalg.lstsq(Bh, b, rcond=None)[0]
+    assert info["rel_res_ls"] <= info["rel_res_best"] * (1 + 1e-9)
+    rel = np.linalg.norm(b - Bh @ c) / np.linalg.norm(b)
+    assert abs(info["rel_res_ls"] - rel) <= 1e-3 * rel
+    # Proposition 1 in the original space: A (D^-1 X) = B - D R
+    Xo = ex["X"] / d[:, None]
+    gap = np.linalg.norm(A.to_scipy() @ Xo - Bh) / np.linalg.norm(b)
+    assert gap < 1e-12
+
+
+def test_solution_matches_direct_solve():
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    xs = spla.spsolve(A.to_scipy().tocsc(), b)
+    for s in (2, 4, 8):
+        x, info, _ = O.mbpcg_solve(A, b, s, seed=W.uniform_block_seed(1, s))
+        assert info["status"] == 0 and info["rel_res_true"] < 2e-8
+        kappa = 1.7e3
+        assert np.linalg.norm(x - xs) <= kappa * 1e-8 * np.linalg.norm(xs)
+
+
+def test_dense_system_matches_direct_solve():
+    A = W.dense_spd(192, tag=(3, 2))
+    b = W.rng_for((3, 3)).standard_normal(192)
+    xs = np.linalg.solve(A, b)
+    for s in (1, 4, 8):
+        x, info, _ = O.mbpcg_solve(A, b, s, jacobi=False, seed=s)
+        assert info["status"] == 0 and info["rel_res_true"] < 2e-8
+        assert np.linalg.norm(x - xs) <= np.linalg.cond(A) * 2e-8 * np.linalg.norm(xs)
+
+
+def test_iterations_fall_as_width_grows():
+    # Sec. 5: more duplicate copies reduce the iteration count
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    its = [O.mbpcg_solve(A, b, s, seed=W.uniform_block_seed(1, s))[1]["iterations"]
+           for s in (1, 2, 4, 8)]
+    assert its == sorted(its, reverse=True) and its[-1] < its[0]
+
+
+def test_summation_order_noise_floor_is_small():
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    x0, i0, _ = O.mbpcg_solve(A, b, 4, seed=4004)
+    O.set_summation(1)
+    try:
+        x1, i1, _ = O.mbpcg_solve(A, b, 4, seed=4004)
+    finally:
+        O.set_summation(0)
+    assert i0["iterations"] == i1["iterations"]
+    assert np.linalg.norm(x1 - x0) <= 1e-9 * np.linalg.norm(x0)
+
+
+# -------------------------------------------------------------- edge cases
+def test_zero_rhs_returns_zero():
+    A = W.poisson2d(8)
+    x, info, _ = O.mbpcg_solve(A, np.zeros(A.n), 4)
+    assert info["status"] == 0 and info["iterations"] == 0 and not x.any()
+
+
+def test_nonpositive_diagonal_is_not_spd():
+    A = W.poisson2d(8)
+    A.vals = A.vals.copy()
+    A.vals[A.colind == 0] = -1.0
+    _, info, _ = O.mbpcg_solve(A, np.ones(A.n), 2)
+    assert info["status"] == -2
+
+
+def test_indefinite_matrix_is_reported():
+    a = np.diag([1.0, 2.0, -3.0, 4.0, 5.0])
+    _, info, _ = O.mbpcg_solve(a, np.ones(5), 2, jacobi=False, seed=1)
+    assert info["status"] in (-2, 1)
+
+
+def test_nan_rhs_is_nonfinite():
+    A = W.poisson2d(8)
+    b = np.ones(A.n)
+    b[3] = np.nan
+    _, info, _ = O.mbpcg_solve(A, b, 2)
+    assert info["status"] == -4
+
+
+def test_initial_block_normalisation():
+    # Alg. 1, line X^0: ||A X0||_F = ||B||_F (in the scaled system)
+    A = W.diffusion3d(10)
+    b = W.rhs(A.n, 12)
+    s = 3
+    U = O.uniform_block(5, A.n, s)
+    _, info, ex = O.mbpcg_solve(A, b, s, U=U, max_iter=0, want_X=True)
+    assert info["status"] == 1 and info["iterations"] == 0
+    d = np.sqrt(A.to_scipy().diagonal())
+    As = (A.to_scipy().multiply(1.0 / d[:, None]).multiply(1.0 / d[None, :])).tocsr()
+    X0 = ex["X"]
+    assert np.allclose(X0 / U, (X0 / U)[0, 0], rtol=1e-15)
+    assert abs(np.linalg.norm(As @ X0) - math.sqrt(s) * np.linalg.norm(b / d)) <= \
+        1e-13 * np.linalg.norm(As @ X0)
+    # R0 = B - A X0 (Alg. 1, lines tilde_B and R^0)
+    assert np.allclose(ex["R"], (b / d)[:, None] - As @ X0, atol=1e-13)
+
+
+def test_max_iter_returns_best_column():
+    # variable diagonal, so the original-space residual D R differs from R
+    A = W.diffusion3d(12)
+    b = W.rhs(A.n, 5)
+    x, info, ex = O.mbpcg_solve(A, b, 4, max_iter=7, seed=1, want_X=True, want_history=True)
+    assert info["status"] == 1 and info["iterations"] == 7 and info["used_fallback"] == 1
+    d = np.sqrt(A.to_scipy().diagonal())
+    h = info["best_column"]
+    assert np.allclose(x, ex["X"][:, h] / d)
+    assert abs(info["rel_res_true"] - ex["history"][-1]) <= 1e-6 * ex["history"][-1]
+
+
+def test_duplicate_initial_columns_deflate_and_converge():
+    A = W.poisson2d(16)
+    b = W.rhs(A.n, 6)
+    U = O.uniform_block(77, A.n, 4)
+    U[:, 2] = U[:, 0]
+    x, info, _ = O.mbpcg_solve(A, b, 4, U=U)
+    assert info["status"] == 0 and info["deflations"] >= 1
+    assert info["rel_res_true"] < 2e-8
