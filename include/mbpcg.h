@@ -1,0 +1,162 @@
+/*
+ * mbpcg — Multi-Basis Parallel Conjugate Gradient on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Xu & Regev, arXiv 2608.07327, Sec. 2, Algorithm 1) solves one
+ * symmetric positive definite system A x = b by running Dubrulle-R block CG
+ * on s duplicate copies of it, B = [b ... b], each copy started from its own
+ * random initial guess, and returns the least-squares combination of the s
+ * iterates (Proposition 1 gives A X = B - R, so no extra product is needed).
+ *
+ * Conventions of this interface
+ *   - Every function returns an mbpcg_status; nothing throws across it.
+ *   - Matrices are FP64.  Sparse A is CSR with int32 indices (Sec. 3: CSR for
+ *     sparse, column-major for dense).  Dense A is column-major with leading
+ *     dimension lda >= n.
+ *   - Vectors b and x have length n.  `mem` says whether a pointer is host or
+ *     device memory of the current HIP device.
+ *   - A context copies A into memory it owns; the caller keeps ownership of
+ *     every pointer it passes.  x is written in place.
+ *   - A context is bound to one HIP stream and is not thread safe.  Work is
+ *     queued on that stream; solve calls return after the result is in x.
+ *   - Argument checks (sizes, CSR structure when A is on the host, finite
+ *     parameters) run before any HIP call: INVALID_ARG never touches the GPU.
+ *   - After any status other than INVALID_ARG, *info is filled and x holds the
+ *     best iterate available.
+ */
+#ifndef MBPCG_H
+#define MBPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbpcg_ctx_s* mbpcg_ctx;
+
+typedef enum {
+    MBPCG_OK = 0,
+    MBPCG_NOT_CONVERGED = 1,     /* max_iter reached; x = best column X_h       */
+    MBPCG_ERR_INVALID_ARG = -1,
+    MBPCG_ERR_NOT_SPD = -2,      /* a_jj <= 0 under Jacobi, or P^T A P not SPD */
+    MBPCG_ERR_BREAKDOWN = -3,    /* every column dropped before convergence     */
+    MBPCG_ERR_NONFINITE = -4,    /* NaN/Inf in the input or the iteration       */
+    MBPCG_ERR_HIP = -5,          /* a HIP runtime call failed (see last_error)  */
+    MBPCG_ERR_OOM = -6,
+    MBPCG_ERR_UNSUPPORTED = -7   /* e.g. s > 32, or a mode this build lacks     */
+} mbpcg_status;
+
+typedef enum { MBPCG_PRECOND_NONE = 0, MBPCG_PRECOND_JACOBI = 1 } mbpcg_precond;
+
+/* Arithmetic of the block product A P.  FP64 everywhere is the paper's
+ * (Sec. 3).  The two IR modes round a copy of dense A to FP32 or BF16, run the
+ * inner block CG with that copy on the matrix cores (FP32 accumulation) and
+ * correct in an FP64 iterative-refinement loop with FP64 residuals; the s x s
+ * Cholesky, deflation and all other work stay FP64. */
+typedef enum { MBPCG_FP64 = 0, MBPCG_FP32_IR = 1, MBPCG_BF16_IR = 2 } mbpcg_precision;
+
+typedef enum { MBPCG_MEM_HOST = 0, MBPCG_MEM_DEVICE = 1 } mbpcg_mem;
+
+typedef struct {
+    int32_t s;              /* copies (block width), 1..32                               */
+    double tol;             /* convergence tolerance on ||b - A x|| / ||b|| (Alg. 1)     */
+    double tol_initial;     /* best-column tolerance; <= 0 means tol (the paper's setting) */
+    int64_t max_iter;       /* iteration cap (inner cap in IR mode)                      */
+    mbpcg_precond precond;  /* NONE, or JACOBI: the symmetric diagonal scaling of Sec. 1 */
+    uint64_t seed;          /* SplitMix64 seed of the Uniform(-1,1) initial block         */
+    const double* U;        /* optional n x s row-major initial block, same mem as b     */
+    double tau;             /* deflation threshold of Cholesky QR; <= 0 means 1e-12      */
+    mbpcg_precision precision;
+    double ir_tol;          /* IR: outer tolerance (FP64 residual)                       */
+    double inner_tol;       /* IR: tolerance of each inner solve                         */
+    int32_t max_outer;      /* IR: outer iteration cap                                   */
+    double* history;        /* optional host array [max_iter]: ||R_h|| / ||b|| per step  */
+    int32_t poll_every;     /* iterations per graph launch between host checks; 0 = auto */
+    int32_t profile;        /* 1: time each phase with HIP events (no graphs)            */
+} mbpcg_params;
+
+typedef struct {
+    int64_t iterations;        /* inner block steps (summed over IR outer steps)       */
+    int64_t outer_iterations;  /* IR outer steps (0 in FP64 mode)                      */
+    int32_t best_column;       /* h of Alg. 1 at exit                                  */
+    int32_t final_width;       /* columns left after deflation                         */
+    int32_t deflations;        /* columns dropped by Cholesky QR                       */
+    int32_t used_fallback;     /* 1: x is the best column, not the LS combination      */
+    double rel_res_best_basis; /* ||R_h|| / ||b|| at exit                              */
+    double rel_res_ls;         /* ||b - B^ c|| / ||b|| of the LS combination           */
+    double rel_res_true;       /* ||b - A x|| / ||b|| recomputed in FP64 on A          */
+    double ms_total;           /* wall time of the solve (scaling included, Sec. 4)    */
+    double ms_per_iter;        /* loop time / iterations                               */
+    double ms_spmm;            /* profile mode: summed time of the block product       */
+    int64_t spmm_launches;     /* profile mode: number of block-product launches       */
+    double ms_phase[8];        /* profile mode: product, Xi, updates, QR, P, LS, setup, other */
+} mbpcg_info;
+
+/* Fill *p with defaults: s=4, tol=1e-8, tol_initial=0, max_iter=100000,
+ * JACOBI, seed=0, tau=1e-12, FP64, ir_tol=1e-10, inner_tol=1e-5, max_outer=50. */
+void mbpcg_default_params(mbpcg_params* p);
+
+/* Create a context for sparse A (CSR, FP64 values, int32 rowptr[n+1] and
+ * colind[nnz], columns in any order inside a row).  A is copied. */
+mbpcg_status mbpcg_create_csr(mbpcg_ctx* ctx, int64_t n, int64_t nnz,
+                              const int32_t* rowptr, const int32_t* colind,
+                              const double* vals, mbpcg_mem mem, void* hip_stream);
+
+/* Create a context for dense A (column-major n x n, leading dimension lda).
+ * A is copied.  Sec. 3 stores dense A column-major. */
+mbpcg_status mbpcg_create_dense(mbpcg_ctx* ctx, int64_t n, const double* A, int64_t lda,
+                                mbpcg_mem mem, void* hip_stream);
+
+/* Solve A x = b with Algorithm 1 (MBPCG). */
+mbpcg_status mbpcg_solve(mbpcg_ctx ctx, const double* b, double* x, mbpcg_mem mem,
+                         const mbpcg_params* params, mbpcg_info* info);
+
+/* Solve A x = b with Chronopoulos-Gear CG from x0 = 0, on the same scaled
+ * system and with the same stop rule: the paper's CG baseline (Sec. 1, Sec. 4). */
+mbpcg_status mbpcg_cg_solve(mbpcg_ctx ctx, const double* b, double* x, mbpcg_mem mem,
+                            const mbpcg_params* params, mbpcg_info* info);
+
+/* One block product of the solver's hot loop, exposed for testing and
+ * measurement: Q = A~ P and C = P^T Q for the scaled matrix A~ = D^-1 A D^-1
+ * (D = I with precond NONE), P and Q row-major n x s on the device, C row-major
+ * s x s on the device (lower triangle i >= j written; upper left untouched).
+ * Alg. 1, line Xi. */
+mbpcg_status mbpcg_block_product(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond,
+                                 const double* P, double* Q, double* C);
+
+/* Time `reps` launches of the block-product kernel of mbpcg_block_product with
+ * HIP events on the context's stream; *ms_avg receives the mean duration. */
+mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps,
+                                      const double* P, double* Q, double* ms_avg);
+
+/* One independent system of a batch; pointers as given by `mem`. */
+typedef struct {
+    int64_t n, nnz;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* vals;
+    const double* b;
+    double* x;
+    int32_t s;   /* block width of this system, 1..8 */
+} mbpcg_system;
+
+/* Solve nsys independent sparse systems (uneven n and s) together in one
+ * persistent launch per graph replay.  common->s is ignored; each system uses
+ * its own s.  per_system[nsys] receives each system's info. */
+mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
+                               const mbpcg_params* common, mbpcg_info* per_system,
+                               mbpcg_mem mem, void* hip_stream);
+
+/* Copy `bytes` bytes device-to-device with the library's plain streaming copy
+ * kernel on `hip_stream`; used to calibrate hardware byte counters. */
+mbpcg_status mbpcg_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
+
+void mbpcg_destroy(mbpcg_ctx ctx);
+const char* mbpcg_status_str(mbpcg_status st);
+/* Message of the last failure on ctx (ctx may be NULL for create failures). */
+const char* mbpcg_last_error(mbpcg_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,194 @@
+// Device-side building blocks of the MBPCG library for gfx950 (CDNA4).
+//
+// Layout conventions
+//   * n x S blocks are row-major with the S columns of a row contiguous, so a
+//     row of P is one 8*S-byte segment (the paper keeps column-major blocks
+//     and notes that row-major would coalesce the block product, Sec. 3).
+//   * S is the padded storage width (1, 2, 4, 8, 16 or 32); the caller's s <= S
+//     columns are the copies, columns s..S-1 hold zeros and are inactive.
+//   * Small S x S matrices live in the DevState with a fixed stride of 32.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MB_SM 32
+#define MB_BLOCK 256
+
+namespace mb {
+
+enum DoneCode : int32_t {
+    DONE_RUNNING = 0,
+    DONE_CONVERGED = 1,
+    DONE_MAXITER = 2,
+    DONE_BREAKDOWN = 3,
+    DONE_NOTSPD = 4,
+    DONE_NONFINITE = 5,
+    DONE_ZERO_RHS = 6,
+};
+
+// Per-solve state resident in device memory.  The host reads `done` and
+// `iter` (adjacent, 8 bytes) between graph launches.
+struct DevState {
+    int32_t done, iter, h, width;
+    int32_t deflations, max_iter, s, accepted;
+    int32_t ls_ok, ls_width, n_hist, pad0;
+    double tol, tol0, bnorm, nu_h;
+    double gamma, rel_ls, rel_true, y0;
+    double tau, bbar_norm, res_norm, pad2;
+    // Chronopoulos-Gear scalars
+    double cg_alpha, cg_beta, cg_gamma, cg_rel;
+    double Xi[MB_SM * MB_SM];
+    double alpha[MB_SM * MB_SM];
+    double Sigma[MB_SM * MB_SM];
+    double M[MB_SM * MB_SM];   // W = V M   (inverse of the kept Cholesky factor)
+    double Z[MB_SM * MB_SM];   // P = W + P Z^T, Sigma <- Z Sigma
+    double nu[MB_SM];
+    double chat[MB_SM + 1];
+    int32_t active[MB_SM];
+};
+
+__host__ __device__ constexpr int tri_count(int S) { return S * (S + 1) / 2; }
+__host__ __device__ constexpr int floor_pow2(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+// e -> (i, j) with i >= j, e = i (i + 1) / 2 + j
+__device__ __forceinline__ void tri_ij(int e, int& i, int& j) {
+    int r = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    while (r * (r + 1) / 2 > e) --r;
+    i = r;
+    j = e - r * (r + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Work split of n rows, in tiles of T rows, over the grid.  On MI355X
+// consecutive workgroup ids land on different XCDs (8 of them, each with its
+// own L2), so when the grid is a multiple of 8 each XCD is given one
+// contiguous slab of tiles and its workgroups sweep that slab together: the
+// stencil/graph neighbours of a tile are then rows the same L2 saw recently.
+// ---------------------------------------------------------------------------
+struct TileRange {
+    int64_t first, end, step;
+};
+
+__device__ __forceinline__ TileRange tile_range(int64_t ntiles) {
+    const int nwg = gridDim.x;
+    TileRange t;
+    if ((nwg & 7) == 0 && ntiles >= nwg) {
+        const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
+        const int64_t lo = ntiles * x / 8, hi = ntiles * (x + 1) / 8;
+        t.first = lo + k;
+        t.end = hi;
+        t.step = nwg >> 3;
+    } else {
+        t.first = blockIdx.x;
+        t.end = ntiles;
+        t.step = nwg;
+    }
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic per-workgroup accumulator of ETOT sums over rows of LDS tiles.
+// Entries are spread over the 256 threads; when ETOT < 256 each entry's rows
+// are split over TPE threads whose partial sums are added in a fixed order at
+// the end.  f(e, r) returns the term of entry e for tile row r.
+// ---------------------------------------------------------------------------
+template <int ETOT>
+struct TileSums {
+    static constexpr int TPE = ETOT >= MB_BLOCK ? 1 : floor_pow2(MB_BLOCK / ETOT);
+    static constexpr int EPT = TPE == 1 ? (ETOT + MB_BLOCK - 1) / MB_BLOCK : 1;
+    double acc[EPT];
+    int ent[EPT];
+    int sub;
+
+    __device__ __forceinline__ void init() {
+        const int t = threadIdx.x;
+        if (TPE > 1) {
+            ent[0] = t / TPE;
+            sub = t % TPE;
+            if (ent[0] >= ETOT) ent[0] = -1;
+        } else {
+            sub = 0;
+#pragma unroll
+            for (int k = 0; k < EPT; ++k) {
+                int e = t + k * MB_BLOCK;
+                ent[k] = e < ETOT ? e : -1;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) acc[k] = 0.0;
+    }
+
+    template <class F>
+    __device__ __forceinline__ void add_rows(int rows, F f) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = ent[k];
+            if (e < 0) continue;
+            double a = acc[k];
+            for (int r = sub; r < rows; r += TPE) a += f(e, r);
+            acc[k] = a;
+        }
+    }
+
+    // Writes the workgroup's ETOT sums to out[0..ETOT).  lds must hold
+    // MB_BLOCK doubles.  Ends with a barrier.
+    __device__ __forceinline__ void finish(double* lds, double* out) {
+        if (TPE > 1) {
+            __syncthreads();
+            lds[threadIdx.x] = acc[0];
+            __syncthreads();
+            const int e = threadIdx.x;
+            if (e < ETOT) {
+                double s = 0.0;
+                for (int q = 0; q < TPE; ++q) s += lds[e * TPE + q];
+                out[e] = s;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int k = 0; k < EPT; ++k)
+                if (ent[k] >= 0) out[ent[k]] = acc[k];
+        }
+    }
+};
+
+// Sum part[w * E + e] over w = 0..nwg-1 in a fixed order into out[e] (LDS),
+// using all threads of the block.  tmp must hold max(blockDim, E) doubles.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nwg, int E,
+                                                double* out, double* tmp) {
+    const int B = blockDim.x, t = threadIdx.x;
+    if (E >= B) {
+        for (int e = t; e < E; e += B) {
+            double s = 0.0;
+            for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * E + e];
+            out[e] = s;
+        }
+        __syncthreads();
+        return;
+    }
+    const int tpe = B / E;
+    const int e = t % E, q = t / E;
+    if (q < tpe) {
+        const int chunk = (nwg + tpe - 1) / tpe;
+        const int w0 = q * chunk, w1 = min(nwg, w0 + chunk);
+        double s = 0.0;
+        for (int w = w0; w < w1; ++w) s += part[(int64_t)w * E + e];
+        tmp[q * E + e] = s;
+    }
+    __syncthreads();
+    if (t < E) {
+        double s = 0.0;
+        for (int q2 = 0; q2 < tpe; ++q2) s += tmp[q2 * E + t];
+        out[t] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return v - v == 0.0; }
+
+}  // namespace mb

@@ -1,0 +1,681 @@
+// Streaming n x S kernels of one MBPCG iteration, the setup and the
+// termination of Algorithm 1, and the Chronopoulos-Gear CG baseline.
+//
+// Every kernel walks its rows in tiles of T rows.  A tile of a row-major
+// n x S block is one contiguous run of T*S doubles, so blocks that are needed
+// whole-row (P, Q, V) are staged through LDS with a linear coalesced copy, and
+// the element-wise blocks (X~, R, W) are read and written in place with the
+// same linear layout.  Each thread owns one column j of the tile, which keeps
+// the column j of the s x s coefficients in registers for the whole kernel.
+#include "kernels.hpp"
+
+#include <hip/hip_bf16.h>
+
+namespace mb {
+
+template <int S>
+struct Tiles {
+    static constexpr int RPP = MB_BLOCK / S;
+    static constexpr int T = RPP >= 64 ? RPP : 64;
+};
+
+// ---------------------------------------------------------------------------
+// K_B: lines tilde_X, R, h (partial norms) and the first half of W_zeta.
+//   X~ += P alpha,  R -= Q alpha,  V = W - Q Xi  (V overwrites W),
+//   partial lower triangle of V^T V and nu_j = sum_r (d_r R_rj)^2.
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __restrict__ P,
+                                                     const double* __restrict__ Q,
+                                                     double* __restrict__ Xt,
+                                                     double* __restrict__ R,
+                                                     double* __restrict__ W,
+                                                     const double* __restrict__ d,
+                                                     double* __restrict__ part,
+                                                     const DevState* __restrict__ st) {
+    if (st->done) return;
+    constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
+    constexpr int E = tri_count(S);
+    __shared__ double sP[T * S];
+    __shared__ double sQ[T * S];
+    __shared__ double sV[T * S];
+    __shared__ double red[MB_BLOCK];
+    const int t = threadIdx.x, j = t % S, rl0 = t / S;
+    double al[S], xi[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        al[l] = st->alpha[l * MB_SM + j];
+        xi[l] = st->Xi[l * MB_SM + j];
+    }
+    TileSums<E> gs;
+    gs.init();
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+        gi[k] = gj[k] = 0;
+        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+    }
+    double nu = 0.0;
+    const int64_t ntiles = (n + T - 1) / T;
+    const TileRange tr = tile_range(ntiles);
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * T;
+        const int rows = (int)min((int64_t)T, n - r0);
+        const double* Pt = P + r0 * S;
+        const double* Qt = Q + r0 * S;
+        for (int e = t; e < T * S; e += MB_BLOCK) {
+            const bool in = e < rows * S;
+            sP[e] = in ? Pt[e] : 0.0;
+            sQ[e] = in ? Qt[e] : 0.0;
+        }
+        __syncthreads();
+        for (int rl = rl0; rl < T; rl += RPP) {
+            double v = 0.0;
+            if (rl < rows) {
+                const int64_t g = (r0 + rl) * S + j;
+                double tx = 0.0, trr = 0.0, tv = 0.0;
+#pragma unroll
+                for (int l = 0; l < S; ++l) {
+                    const double p = sP[rl * S + l], q = sQ[rl * S + l];
+                    tx += p * al[l];
+                    trr += q * al[l];
+                    tv += q * xi[l];
+                }
+                const double xn = Xt[g] + tx;
+                const double rn = R[g] - trr;
+                v = W[g] - tv;
+                Xt[g] = xn;
+                R[g] = rn;
+                W[g] = v;
+                const double dr = d[r0 + rl] * rn;
+                nu += dr * dr;
+            }
+            sV[rl * S + j] = v;
+        }
+        __syncthreads();
+        gs.add_rows(rows, [&](int k, int r) { return sV[r * S + gi[k]] * sV[r * S + gj[k]]; });
+        __syncthreads();
+    }
+    double* out = part + (int64_t)blockIdx.x * (E + S);
+    gs.finish(red, out);
+    __syncthreads();
+    red[t] = nu;
+    __syncthreads();
+    if (t < S) {
+        double s = 0.0;
+        for (int q = 0; q < RPP; ++q) s += red[t + q * S];
+        out[E + t] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K_C: the second half of line W_zeta and line P.
+//   W = V M  (M = inverse of the kept Cholesky factor),  P = W + P Z^T.
+// FIRST: line P^0 (P = W).  Optionally also writes P rounded to FP32 or BF16
+// for the low-precision dense product.
+// ---------------------------------------------------------------------------
+template <int S, int FIRST, int LO>
+__global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __restrict__ W,
+                                                        double* __restrict__ P,
+                                                        void* __restrict__ Plo,
+                                                        const DevState* __restrict__ st) {
+    if (st->done) return;
+    constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
+    __shared__ double sV[T * S];
+    __shared__ double sP[T * S];
+    const int t = threadIdx.x, j = t % S, rl0 = t / S;
+    double m[S], z[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        m[l] = st->M[l * MB_SM + j];
+        z[l] = st->Z[j * MB_SM + l];
+    }
+    const int64_t ntiles = (n + T - 1) / T;
+    const TileRange tr = tile_range(ntiles);
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * T;
+        const int rows = (int)min((int64_t)T, n - r0);
+        for (int e = t; e < T * S; e += MB_BLOCK) {
+            const bool in = e < rows * S;
+            sV[e] = in ? W[r0 * S + e] : 0.0;
+            if (!FIRST) sP[e] = in ? P[r0 * S + e] : 0.0;
+        }
+        __syncthreads();
+        for (int rl = rl0; rl < rows; rl += RPP) {
+            double w = 0.0;
+#pragma unroll
+            for (int l = 0; l < S; ++l) w += sV[rl * S + l] * m[l];
+            double p = w;
+            if (!FIRST) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < S; ++l) acc += sP[rl * S + l] * z[l];
+                p = w + acc;
+            }
+            const int64_t g = (r0 + rl) * S + j;
+            W[g] = w;
+            P[g] = p;
+            if (LO == DENSE_F32) static_cast<float*>(Plo)[g] = (float)p;
+            if (LO == DENSE_BF16) static_cast<__hip_bfloat16*>(Plo)[g] = __double2bfloat16(p);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Setup (Alg. 1, lines B .. P^0)
+// ---------------------------------------------------------------------------
+// b~ = D^-1 b; partial sums of b^2 and b~^2
+__global__ __launch_bounds__(MB_BLOCK) void k_rhs(int64_t n, const double* __restrict__ b,
+                                                  const double* __restrict__ d,
+                                                  double* __restrict__ bbar,
+                                                  double* __restrict__ part) {
+    __shared__ double red[2 * MB_BLOCK];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)MB_BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * MB_BLOCK) {
+        const double v = b[r], vb = v / d[r];
+        bbar[r] = vb;
+        s0 += v * v;
+        s1 += vb * vb;
+    }
+    red[threadIdx.x] = s0;
+    red[MB_BLOCK + threadIdx.x] = s1;
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int k = 0; k < MB_BLOCK; ++k) s += red[threadIdx.x * MB_BLOCK + k];
+        part[blockIdx.x * 2 + threadIdx.x] = s;
+    }
+}
+
+// U_rj = 2 u - 1 with u the top 53 bits of SplitMix64 output number j*n + r
+// (Alg. 1, line U: iid Uniform(-1, 1)); padded columns are zero.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <int S>
+__global__ void k_uniform(int64_t n, int s, uint64_t seed, double* __restrict__ U) {
+    const int64_t total = n * S;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / S;
+        const int j = (int)(e % S);
+        double v = 0.0;
+        if (j < s) {
+            const uint64_t z = splitmix64_at(seed, (uint64_t)j * (uint64_t)n + (uint64_t)r);
+            v = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+        }
+        U[e] = v;
+    }
+}
+
+template <int S>
+__global__ void k_pad_block(int64_t n, int s, const double* __restrict__ in, double* __restrict__ U) {
+    const int64_t total = n * S;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / S;
+        const int j = (int)(e % S);
+        U[e] = j < s ? in[r * s + j] : 0.0;
+    }
+}
+
+// partial sums over rows of sum_j Y_rj^2 (||A U||_F^2)
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_ynorm(int64_t n, const double* __restrict__ Y,
+                                                    double* __restrict__ part) {
+    __shared__ double red[MB_BLOCK];
+    double s2 = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)MB_BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * MB_BLOCK) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) a += Y[r * S + j] * Y[r * S + j];
+        s2 += a;
+    }
+    red[threadIdx.x] = s2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < MB_BLOCK; ++k) s += red[k];
+        part[blockIdx.x] = s;
+    }
+}
+
+// X0 = gamma U;  R0 = B~ - gamma (A U);  X~0 = 0   (lines X^0 .. R^0)
+template <int S>
+__global__ void k_init(int64_t n, int s, const double* __restrict__ U, const double* __restrict__ Y,
+                       const double* __restrict__ bbar, double* __restrict__ X0,
+                       double* __restrict__ Xt, double* __restrict__ R,
+                       const DevState* __restrict__ st) {
+    if (st->done) return;
+    const double g = st->gamma;
+    const int64_t total = n * S;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e % S);
+        X0[e] = g * U[e];
+        Xt[e] = 0.0;
+        R[e] = j < s ? bbar[e / S] - g * Y[e] : 0.0;
+    }
+}
+
+// partial lower triangle of X^T X and nu_j = sum_r (d_r X_rj)^2 (same layout as k_update)
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* __restrict__ X,
+                                                      const double* __restrict__ d,
+                                                      double* __restrict__ part) {
+    constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
+    constexpr int E = tri_count(S);
+    __shared__ double sX[T * S];
+    __shared__ double red[MB_BLOCK];
+    const int t = threadIdx.x, j = t % S, rl0 = t / S;
+    TileSums<E> gs;
+    gs.init();
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+        gi[k] = gj[k] = 0;
+        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+    }
+    double nu = 0.0;
+    const int64_t ntiles = (n + T - 1) / T;
+    const TileRange tr = tile_range(ntiles);
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * T;
+        const int rows = (int)min((int64_t)T, n - r0);
+        for (int e = t; e < T * S; e += MB_BLOCK) sX[e] = e < rows * S ? X[r0 * S + e] : 0.0;
+        __syncthreads();
+        for (int rl = rl0; rl < rows; rl += RPP) {
+            const double v = d[r0 + rl] * sX[rl * S + j];
+            nu += v * v;
+        }
+        gs.add_rows(rows, [&](int k, int r) { return sX[r * S + gi[k]] * sX[r * S + gj[k]]; });
+        __syncthreads();
+    }
+    double* out = part + (int64_t)blockIdx.x * (E + S);
+    gs.finish(red, out);
+    __syncthreads();
+    red[t] = nu;
+    __syncthreads();
+    if (t < S) {
+        double s = 0.0;
+        for (int q = 0; q < RPP; ++q) s += red[t + q * S];
+        out[E + t] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Termination (lines hat_B .. x, Proposition 1).  The least-squares problem
+// min_c ||b - B^ c|| with B^ = B - D R is solved in the equivalent form
+// min ||y0 b + (D R) c|| subject to y0 + sum c = 1, whose FP64 Gram over the
+// columns [b, D R] is formed here (one pass over R).
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_ls_gram(int64_t n, const double* __restrict__ b,
+                                                      const double* __restrict__ R,
+                                                      const double* __restrict__ d,
+                                                      double* __restrict__ part,
+                                                      const DevState* __restrict__ st) {
+    constexpr int NC = S + 1;
+    constexpr int T = 64;
+    constexpr int E = tri_count(NC);
+    __shared__ double sM[T * NC];
+    __shared__ double red[MB_BLOCK];
+    const int t = threadIdx.x;
+    TileSums<E> gs;
+    gs.init();
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+        gi[k] = gj[k] = 0;
+        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+    }
+    const int64_t ntiles = (n + T - 1) / T;
+    const TileRange tr = tile_range(ntiles);
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * T;
+        const int rows = (int)min((int64_t)T, n - r0);
+        for (int e = t; e < T * S; e += MB_BLOCK) {
+            const int rl = e / S, j = e % S;
+            sM[rl * NC + 1 + j] = rl < rows ? d[r0 + rl] * R[r0 * S + e] : 0.0;
+        }
+        for (int rl = t; rl < T; rl += MB_BLOCK) sM[rl * NC] = rl < rows ? b[r0 + rl] : 0.0;
+        __syncthreads();
+        gs.add_rows(rows, [&](int k, int r) { return sM[r * NC + gi[k]] * sM[r * NC + gj[k]]; });
+        __syncthreads();
+    }
+    gs.finish(red, part + (int64_t)blockIdx.x * E);
+}
+
+// x = D^-1 (X~ + X0) c;  r = y0 b + (D R) c  (= b - B^ c), partial ||r||^2
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_ls_apply(int64_t n, const double* __restrict__ Xt,
+                                                       const double* __restrict__ X0,
+                                                       const double* __restrict__ R,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ d,
+                                                       double* __restrict__ x,
+                                                       double* __restrict__ part,
+                                                       const DevState* __restrict__ st) {
+    __shared__ double red[MB_BLOCK];
+    double c[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) c[j] = st->chat[j];
+    const double y0 = st->y0;
+    double s2 = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)MB_BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * MB_BLOCK) {
+        double ax = 0.0, ar = 0.0;
+        const double dr = d[r];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            ax += (Xt[r * S + j] + X0[r * S + j]) * c[j];
+            ar += (dr * R[r * S + j]) * c[j];
+        }
+        x[r] = ax / dr;
+        const double res = y0 * b[r] + ar;
+        s2 += res * res;
+    }
+    red[threadIdx.x] = s2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < MB_BLOCK; ++k) s += red[k];
+        part[blockIdx.x] = s;
+    }
+}
+
+// fallback to the best column: x = D^-1 (X~ + X0)_h when the combination is not accepted
+template <int S>
+__global__ void k_select(int64_t n, const double* __restrict__ Xt, const double* __restrict__ X0,
+                         const double* __restrict__ d, double* __restrict__ x,
+                         const DevState* __restrict__ st) {
+    if (st->accepted) return;
+    const int h = st->h;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        x[r] = (Xt[r * S + h] + X0[r * S + h]) / d[r];
+}
+
+// ---------------------------------------------------------------------------
+// Chronopoulos-Gear CG: p = r + beta p; s = w + beta s; x += alpha p;
+// r -= alpha s; partials of ||D r||^2 and r^T r.
+// ---------------------------------------------------------------------------
+__global__ void k_cg_init(int64_t n, const double* __restrict__ bbar, double* __restrict__ x,
+                          double* __restrict__ r, double* __restrict__ p, double* __restrict__ sv) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = 0.0;
+        r[i] = bbar[i];
+        p[i] = 0.0;
+        sv[i] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(MB_BLOCK) void k_cg_update(int64_t n, double* __restrict__ p,
+                                                        double* __restrict__ sv,
+                                                        double* __restrict__ x,
+                                                        double* __restrict__ r,
+                                                        const double* __restrict__ w,
+                                                        const double* __restrict__ d,
+                                                        double* __restrict__ part,
+                                                        const DevState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double red[2 * MB_BLOCK];
+    const double alpha = st->cg_alpha, beta = st->cg_beta;
+    double e2 = 0.0, g2 = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)MB_BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * MB_BLOCK) {
+        const double pn = r[i] + beta * p[i];
+        const double sn = w[i] + beta * sv[i];
+        x[i] = x[i] + alpha * pn;
+        const double rn = r[i] - alpha * sn;
+        p[i] = pn;
+        sv[i] = sn;
+        r[i] = rn;
+        const double dr = d[i] * rn;
+        e2 += dr * dr;
+        g2 += rn * rn;
+    }
+    red[threadIdx.x] = e2;
+    red[MB_BLOCK + threadIdx.x] = g2;
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int k = 0; k < MB_BLOCK; ++k) s += red[threadIdx.x * MB_BLOCK + k];
+        part[blockIdx.x * 2 + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_unscale(int64_t n, const double* __restrict__ xs, const double* __restrict__ d,
+                          double* __restrict__ x) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = xs[i] / d[i];
+}
+
+__global__ void k_stream_copy(const double4* __restrict__ src, double4* __restrict__ dst,
+                              int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_copy_bytes(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+                             int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// copy of an n x S block rounded to FP32 or BF16 (initial block of a low-precision product)
+template <int LO>
+__global__ void k_block_to_lo(int64_t count, const double* __restrict__ src, void* __restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (LO == DENSE_F32) static_cast<float*>(dst)[i] = (float)src[i];
+        else static_cast<__hip_bfloat16*>(dst)[i] = __double2bfloat16(src[i]);
+    }
+}
+
+// x += d (iterative refinement update, FP64)
+__global__ void k_axpy_ir(int64_t n, double* __restrict__ x, const double* __restrict__ d) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = x[i] + d[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int64_t work, int cap) {
+    int64_t g = (work + MB_BLOCK - 1) / MB_BLOCK;
+    if (g < 1) g = 1;
+    return (int)(g < cap ? g : cap);
+}
+
+#define MB_DISPATCH_S(S, CALL)          \
+    switch (S) {                        \
+        case 1: { constexpr int SS = 1; CALL; } \
+        case 2: { constexpr int SS = 2; CALL; } \
+        case 4: { constexpr int SS = 4; CALL; } \
+        case 8: { constexpr int SS = 8; CALL; } \
+        case 16: { constexpr int SS = 16; CALL; } \
+        case 32: { constexpr int SS = 32; CALL; } \
+    }                                   \
+    return hipErrorInvalidValue;
+
+hipError_t launch_update(int S, int nwg, int64_t n, const double* P, const double* Q, double* Xt,
+                         double* R, double* W, const double* d, double* part, const DevState* st,
+                         hipStream_t stream) {
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_update<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n, P, Q, Xt, R, W,
+                           d, part, st);
+        return hipGetLastError();
+    })
+}
+
+template <int S>
+static hipError_t dirupdate_s(int nwg, int64_t n, double* W, double* P, void* Plo, DenseKind lo,
+                              int first, const DevState* st, hipStream_t stream) {
+    if (first) {
+        if (lo == DENSE_F32)
+            hipLaunchKernelGGL((k_dirupdate<S, 1, DENSE_F32>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
+                               n, W, P, Plo, st);
+        else if (lo == DENSE_BF16)
+            hipLaunchKernelGGL((k_dirupdate<S, 1, DENSE_BF16>), dim3(nwg), dim3(MB_BLOCK), 0,
+                               stream, n, W, P, Plo, st);
+        else
+            hipLaunchKernelGGL((k_dirupdate<S, 1, DENSE_F64>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
+                               n, W, P, Plo, st);
+    } else {
+        if (lo == DENSE_F32)
+            hipLaunchKernelGGL((k_dirupdate<S, 0, DENSE_F32>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
+                               n, W, P, Plo, st);
+        else if (lo == DENSE_BF16)
+            hipLaunchKernelGGL((k_dirupdate<S, 0, DENSE_BF16>), dim3(nwg), dim3(MB_BLOCK), 0,
+                               stream, n, W, P, Plo, st);
+        else
+            hipLaunchKernelGGL((k_dirupdate<S, 0, DENSE_F64>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
+                               n, W, P, Plo, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, void* Plo,
+                            DenseKind lo_kind, int first, const DevState* st, hipStream_t stream) {
+    MB_DISPATCH_S(S, return dirupdate_s<SS>(nwg, n, W, P, Plo, lo_kind, first, st, stream))
+}
+
+hipError_t launch_rhs(int nwg, int64_t n, const double* b, const double* d, double* bbar,
+                      double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_rhs, dim3(nwg), dim3(MB_BLOCK), 0, s, n, b, d, bbar, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform(int S, int64_t n, int s, uint64_t seed, double* U, hipStream_t st) {
+    const int g = grid_for(n * S, 8192);
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_uniform<SS>, dim3(g), dim3(MB_BLOCK), 0, st, n, s, seed, U);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_pad_block(int S, int64_t n, int s, const double* Uin, double* U, hipStream_t st) {
+    const int g = grid_for(n * S, 8192);
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_pad_block<SS>, dim3(g), dim3(MB_BLOCK), 0, st, n, s, Uin, U);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_ynorm(int S, int nwg, int64_t n, const double* Y, double* part, hipStream_t s) {
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_ynorm<SS>, dim3(nwg), dim3(MB_BLOCK), 0, s, n, Y, part);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_init(int S, int64_t n, int s, const double* U, const double* Y,
+                       const double* bbar, double* X0, double* Xt, double* R, const DevState* st,
+                       hipStream_t stream) {
+    const int g = grid_for(n * S, 8192);
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_init<SS>, dim3(g), dim3(MB_BLOCK), 0, stream, n, s, U, Y, bbar, X0, Xt,
+                           R, st);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_gram_nu(int S, int nwg, int64_t n, const double* X, const double* d, double* part,
+                          hipStream_t stream) {
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_gram_nu<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n, X, d, part);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_ls_gram(int S, int nwg, int64_t n, const double* b, const double* R,
+                          const double* d, double* part, const DevState* st, hipStream_t s) {
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_ls_gram<SS>, dim3(nwg), dim3(MB_BLOCK), 0, s, n, b, R, d, part, st);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_ls_apply(int S, int nwg, int64_t n, const double* Xt, const double* X0,
+                           const double* R, const double* b, const double* d, double* x,
+                           double* part, const DevState* st, hipStream_t s) {
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_ls_apply<SS>, dim3(nwg), dim3(MB_BLOCK), 0, s, n, Xt, X0, R, b, d, x,
+                           part, st);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_select(int S, int64_t n, const double* Xt, const double* X0, const double* d,
+                         double* x, const DevState* st, hipStream_t s) {
+    const int g = grid_for(n, 4096);
+    MB_DISPATCH_S(S, {
+        hipLaunchKernelGGL(k_select<SS>, dim3(g), dim3(MB_BLOCK), 0, s, n, Xt, X0, d, x, st);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_cg_init(int64_t n, const double* bbar, double* x, double* r, double* p,
+                          double* sv, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(grid_for(n, 4096)), dim3(MB_BLOCK), 0, s, n, bbar, x, r, p,
+                       sv);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(int nwg, int64_t n, double* p, double* sv, double* x, double* r,
+                            const double* w, const double* d, double* part, const DevState* st,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update, dim3(nwg), dim3(MB_BLOCK), 0, s, n, p, sv, x, r, w, d, part,
+                       st);
+    return hipGetLastError();
+}
+
+hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* x, hipStream_t s) {
+    hipLaunchKernelGGL(k_unscale, dim3(grid_for(n, 4096)), dim3(MB_BLOCK), 0, s, n, xs, d, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_to_lo(DenseKind kind, int64_t count, const double* src, void* dst,
+                             hipStream_t s) {
+    if (kind == DENSE_F32)
+        hipLaunchKernelGGL(k_block_to_lo<DENSE_F32>, dim3(grid_for(count, 8192)), dim3(MB_BLOCK), 0,
+                           s, count, src, dst);
+    else if (kind == DENSE_BF16)
+        hipLaunchKernelGGL(k_block_to_lo<DENSE_BF16>, dim3(grid_for(count, 8192)), dim3(MB_BLOCK),
+                           0, s, count, src, dst);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_ir(int64_t n, double* x, const double* d, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_ir, dim3(grid_for(n, 4096)), dim3(MB_BLOCK), 0, s, n, x, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t s) {
+    if ((bytes % 32) == 0 && ((uintptr_t)dst % 32) == 0 && ((uintptr_t)src % 32) == 0) {
+        const int64_t cnt = bytes / 32;
+        hipLaunchKernelGGL(k_stream_copy, dim3(grid_for(cnt, 8192)), dim3(MB_BLOCK), 0, s,
+                           (const double4*)src, (double4*)dst, cnt);
+    } else {
+        hipLaunchKernelGGL(k_copy_bytes, dim3(grid_for(bytes, 8192)), dim3(MB_BLOCK), 0, s,
+                           (const unsigned char*)src, (unsigned char*)dst, bytes);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mb

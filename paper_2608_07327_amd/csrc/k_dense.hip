@@ -1,0 +1,459 @@
+// Dense block product Q = A P on the matrix cores (Alg. 1, line Xi for dense
+// A; Sec. 3 keeps dense A column-major in FP64).
+//
+// A workgroup of four wavefronts owns 256 rows and one of KSPLIT column
+// ranges; wavefront w owns rows [64w, 64w + 64) as four 16-row MFMA tiles, and
+// every S/16 output column tile reuses each loaded A operand.  P is staged
+// through LDS in chunks of KB rows and shared by the four wavefronts.  The
+// KSPLIT partial products are written to a scratch block and added in a fixed
+// order by k_dense_reduce, which also forms the Gram P^T Q of the tail.
+//
+//   FP64:  v_mfma_f64_16x16x4f64 on the caller's column-major A.
+//   FP32:  v_mfma_f32_16x16x4f32 on a row-major FP32 copy of A.
+//   BF16:  v_mfma_f32_16x16x32_bf16 on a row-major BF16 copy of A.
+// Low-precision kinds accumulate in FP32 inside a workgroup; partials are
+// stored and added in FP64.
+#include "kernels.hpp"
+
+#include <algorithm>
+
+#include <hip/hip_bf16.h>
+
+namespace mb {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int DENSE_ROWS = 256;  // rows per workgroup
+constexpr int DENSE_KSPLIT = 16;
+
+int dense_ksplit(int64_t n) {
+    int k = DENSE_KSPLIT;
+    while (k > 1 && n / k < 256) k /= 2;
+    return k;
+}
+int dense_nwg_rows(int64_t n) { return (int)((n + DENSE_ROWS - 1) / DENSE_ROWS); }
+
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double* __restrict__ A,
+                                                        int64_t lda, const double* __restrict__ P,
+                                                        double* __restrict__ qpart, int ksplit,
+                                                        const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int CT = S >= 16 ? S / 16 : 1;  // output column tiles
+    constexpr int KB = 32;                    // k rows of P per LDS chunk
+    __shared__ double sB[KB * 16 * CT];
+    const int rb = blockIdx.x / ksplit, ks = blockIdx.x % ksplit;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t kchunk = (n + ksplit - 1) / ksplit;
+    const int64_t kbeg = ks * kchunk, kend = min(n, kbeg + kchunk);
+    const int64_t rbase = (int64_t)rb * DENSE_ROWS + wave * 64;
+    const int li = l & 15, lk = l >> 4;
+    d4 acc[4][CT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
+        // A operands of this chunk: tile t, step q -> A[rbase + 16t + li][k0 + 4q + lk]
+        double a[KB / 4][4];
+#pragma unroll
+        for (int q = 0; q < KB / 4; ++q) {
+            const int64_t k = k0 + 4 * q + lk;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t r = rbase + 16 * t + li;
+                a[q][t] = (k < kend && r < n) ? A[k * lda + r] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < KB * 16 * CT; e += MB_BLOCK) {
+            const int kk = e / (16 * CT), j = e % (16 * CT);
+            const int64_t k = k0 + kk;
+            sB[e] = (k < kend && j < S) ? P[k * S + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KB / 4; ++q) {
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const double bv = sB[(4 * q + lk) * (16 * CT) + 16 * c + li];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][t], bv, acc[t][c], 0, 0, 0);
+            }
+        }
+    }
+    // D layout: lane l, element v -> row 4*(l/16) + v, column l % 16
+    double* out = qpart + (int64_t)ks * n * S;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = rbase + 16 * t + 4 * lk + v;
+                const int j = 16 * c + li;
+                if (r < n && j < S) out[r * S + j] = acc[t][c][v];
+            }
+}
+
+// FP32 copy of A, row-major.  Each lane loads four consecutive k of its row;
+// the four MFMAs of a step use the same permutation of k for A and P.
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* __restrict__ A,
+                                                        const float* __restrict__ P,
+                                                        double* __restrict__ qpart, int ksplit,
+                                                        const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int CT = S >= 16 ? S / 16 : 1;
+    constexpr int KB = 64;
+    __shared__ float sB[KB * 16 * CT];
+    const int rb = blockIdx.x / ksplit, ks = blockIdx.x % ksplit;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t kchunk = (n + ksplit - 1) / ksplit;
+    const int64_t kbeg = ks * kchunk, kend = min(n, kbeg + kchunk);
+    const int64_t rbase = (int64_t)rb * DENSE_ROWS + wave * 64;
+    const int li = l & 15, lk = l >> 4;
+    f4 acc[4][CT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+    const bool vec_ok = ((kend - kbeg) % 4 == 0) && (kbeg % 4 == 0) && (n % 4 == 0);
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
+        f4 a[KB / 16][4];
+#pragma unroll
+        for (int q = 0; q < KB / 16; ++q) {
+            const int64_t k = k0 + 16 * q + 4 * lk;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t r = rbase + 16 * t + li;
+                f4 v = f4{0.f, 0.f, 0.f, 0.f};
+                if (r < n) {
+                    if (vec_ok && k + 3 < kend) {
+                        v = *reinterpret_cast<const f4*>(A + r * n + k);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (k + u < kend) v[u] = A[r * n + k + u];
+                    }
+                }
+                a[q][t] = v;
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < KB * 16 * CT; e += MB_BLOCK) {
+            const int kk = e / (16 * CT), j = e % (16 * CT);
+            const int64_t k = k0 + kk;
+            sB[e] = (k < kend && j < S) ? P[k * S + j] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KB / 16; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const float bv = sB[(16 * q + 4 * lk + u) * (16 * CT) + 16 * c + li];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][t][u], bv, acc[t][c],
+                                                                         0, 0, 0);
+                }
+    }
+    double* out = qpart + (int64_t)ks * n * S;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = rbase + 16 * t + 4 * lk + v;
+                const int j = 16 * c + li;
+                if (r < n && j < S) out[r * S + j] = (double)acc[t][c][v];
+            }
+}
+
+// BF16 copy of A, row-major.  v_mfma_f32_16x16x32_bf16: lane l holds
+// A[row l%16][8*(l/16) .. +7] and P[8*(l/16) .. +7][col l%16]; P is kept
+// transposed in LDS so that each lane's eight values are contiguous.
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16* __restrict__ A,
+                                                         const __bf16* __restrict__ P,
+                                                         double* __restrict__ qpart, int ksplit,
+                                                         const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int CT = S >= 16 ? S / 16 : 1;
+    constexpr int KB = 128;
+    constexpr int KBP = KB + 8;  // padded LDS row (keeps 16-byte alignment)
+    __shared__ __attribute__((aligned(16))) __bf16 sBt[16 * CT * KBP];
+    const int rb = blockIdx.x / ksplit, ks = blockIdx.x % ksplit;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t kchunk = (n + ksplit - 1) / ksplit;
+    const int64_t kbeg = ks * kchunk, kend = min(n, kbeg + kchunk);
+    const int64_t rbase = (int64_t)rb * DENSE_ROWS + wave * 64;
+    const int li = l & 15, lk = l >> 4;
+    f4 acc[4][CT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+    const bool vec_ok = ((kend - kbeg) % 8 == 0) && (kbeg % 8 == 0) && (n % 8 == 0);
+    const __bf16 zero = (__bf16)0.0f;
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
+        bf8 a[KB / 32][4];
+#pragma unroll
+        for (int q = 0; q < KB / 32; ++q) {
+            const int64_t k = k0 + 32 * q + 8 * lk;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t r = rbase + 16 * t + li;
+                bf8 v;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = zero;
+                if (r < n) {
+                    if (vec_ok && k + 7 < kend) {
+                        v = *reinterpret_cast<const bf8*>(A + r * n + k);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (k + u < kend) v[u] = A[r * n + k + u];
+                    }
+                }
+                a[q][t] = v;
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < KB * 16 * CT; e += MB_BLOCK) {
+            const int kk = e / (16 * CT), j = e % (16 * CT);
+            const int64_t k = k0 + kk;
+            sBt[j * KBP + kk] = (k < kend && j < S) ? P[k * S + j] : zero;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KB / 32; ++q)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const bf8 bv =
+                    *reinterpret_cast<const bf8*>(&sBt[(16 * c + li) * KBP + 32 * q + 8 * lk]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q][t], bv, acc[t][c], 0, 0, 0);
+            }
+    }
+    double* out = qpart + (int64_t)ks * n * S;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = rbase + 16 * t + 4 * lk + v;
+                const int j = 16 * c + li;
+                if (r < n && j < S) out[r * S + j] = (double)acc[t][c][v];
+            }
+}
+
+// Q = sum over k-ranges of the partials (fixed order) and the lower triangle
+// of P^T Q per workgroup, as the sparse block product's epilogue.
+template <int S>
+__global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit,
+                                                           const double* __restrict__ qpart,
+                                                           const double* __restrict__ P,
+                                                           double* __restrict__ Q,
+                                                           double* __restrict__ part,
+                                                           const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int T = 64;
+    constexpr int E = tri_count(S);
+    __shared__ double sP[T * S], sQ[T * S], red[MB_BLOCK];
+    const int t = threadIdx.x;
+    TileSums<E> gs;
+    gs.init();
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+        gi[k] = gj[k] = 0;
+        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+    }
+    const int64_t ntiles = (n + T - 1) / T;
+    const TileRange tr = tile_range(ntiles);
+    const int64_t nS = n * S;
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * T;
+        const int rows = (int)min((int64_t)T, n - r0);
+        for (int e = t; e < T * S; e += MB_BLOCK) {
+            double q = 0.0, p = 0.0;
+            if (e < rows * S) {
+                const int64_t g = r0 * S + e;
+                for (int k = 0; k < ksplit; ++k) q += qpart[k * nS + g];
+                p = P[g];
+                Q[g] = q;
+            }
+            sQ[e] = q;
+            sP[e] = p;
+        }
+        __syncthreads();
+        if (part)
+            gs.add_rows(rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
+        __syncthreads();
+    }
+    if (part) gs.finish(red, part + (int64_t)blockIdx.x * E);
+}
+
+// r = b - sum of partials of A x (S = 1), partial ||r||^2 per workgroup
+__global__ __launch_bounds__(MB_BLOCK) void k_dense_resid_reduce(int64_t n, int ksplit,
+                                                                 const double* __restrict__ qpart,
+                                                                 const double* __restrict__ b,
+                                                                 double* __restrict__ r_out,
+                                                                 double* __restrict__ part) {
+    __shared__ double red[MB_BLOCK];
+    double s2 = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)MB_BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * MB_BLOCK) {
+        double q = 0.0;
+        for (int k = 0; k < ksplit; ++k) q += qpart[k * n + i];
+        const double e = b[i] - q;
+        if (r_out) r_out[i] = e;
+        s2 += e * e;
+    }
+    red[threadIdx.x] = s2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < MB_BLOCK; ++k) s += red[k];
+        part[blockIdx.x] = s;
+    }
+}
+
+// low-precision, row-major copy of column-major A (round to nearest even)
+template <int KIND>
+__global__ void k_cast_dense(int64_t n, const double* __restrict__ A, int64_t lda,
+                             void* __restrict__ out) {
+    __shared__ double tile[64][65];
+    const int64_t nt = (n + 63) / 64;
+    for (int64_t tb = blockIdx.x; tb < nt * nt; tb += gridDim.x) {
+        const int64_t tr = tb / nt, tc = tb % nt;  // tile of rows tr*64.., cols tc*64..
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+        for (int cc = ty; cc < 64; cc += 4) {
+            const int64_t c = tc * 64 + cc, r = tr * 64 + tx;
+            tile[cc][tx] = (c < n && r < n) ? A[c * lda + r] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = ty; rr < 64; rr += 4) {
+            const int64_t r = tr * 64 + rr, c = tc * 64 + tx;
+            if (r < n && c < n) {
+                const double v = tile[tx][rr];
+                if (KIND == DENSE_F32) static_cast<float*>(out)[r * n + c] = (float)v;
+                else static_cast<__hip_bfloat16*>(out)[r * n + c] = __double2bfloat16(v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_diag_dense(int64_t n, const double* __restrict__ A, int64_t lda, int jacobi,
+                             double* __restrict__ d, DevState* st) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const double a = A[r * lda + r];
+        double dr = 1.0;
+        if (jacobi) {
+            if (!(a > 0.0) || !finite_d(a)) st->done = DONE_NOTSPD;
+            else dr = sqrt(a);
+        }
+        d[r] = dr;
+    }
+}
+
+__global__ void k_scale_dense(int64_t n, const double* __restrict__ A, int64_t lda,
+                              const double* __restrict__ d, double* __restrict__ As) {
+    const int64_t total = n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, r = e % n;
+        As[e] = A[c * lda + r] / (d[r] * d[c]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+#define MB_DENSE_S(S, CALL)         \
+    switch (S) {                    \
+        case 1: { constexpr int SS = 1; CALL; } \
+        case 2: { constexpr int SS = 2; CALL; } \
+        case 4: { constexpr int SS = 4; CALL; } \
+        case 8: { constexpr int SS = 8; CALL; } \
+        case 16: { constexpr int SS = 16; CALL; } \
+        case 32: { constexpr int SS = 32; CALL; } \
+    }                               \
+    return hipErrorInvalidValue;
+
+hipError_t launch_dense_ap(int S, DenseKind kind, int64_t n, const void* A, int64_t lda,
+                           const void* Plo, const double* P, double* qpart, int ksplit,
+                           const DevState* st, hipStream_t stream) {
+    const int nwg = dense_nwg_rows(n) * ksplit;
+    MB_DENSE_S(S, {
+        if (kind == DENSE_F64)
+            hipLaunchKernelGGL(k_dense_f64<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n,
+                               (const double*)A, lda, P, qpart, ksplit, st);
+        else if (kind == DENSE_F32)
+            hipLaunchKernelGGL(k_dense_f32<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n,
+                               (const float*)A, (const float*)Plo, qpart, ksplit, st);
+        else
+            hipLaunchKernelGGL(k_dense_bf16<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n,
+                               (const __bf16*)A, (const __bf16*)Plo, qpart, ksplit, st);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_dense_reduce(int S, int64_t n, int ksplit, const double* qpart, const double* P,
+                               double* Q, double* part, int nwg, const DevState* st,
+                               hipStream_t stream) {
+    MB_DENSE_S(S, {
+        hipLaunchKernelGGL(k_dense_reduce<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n, ksplit,
+                           qpart, P, Q, part, st);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_cast_dense(DenseKind kind, int64_t n, const double* A, int64_t lda, void* out,
+                             hipStream_t stream) {
+    const int64_t nt = (n + 63) / 64;
+    const int g = (int)std::min<int64_t>(nt * nt, 8192);
+    if (kind == DENSE_F32)
+        hipLaunchKernelGGL(k_cast_dense<DENSE_F32>, dim3(g), dim3(MB_BLOCK), 0, stream, n, A, lda, out);
+    else if (kind == DENSE_BF16)
+        hipLaunchKernelGGL(k_cast_dense<DENSE_BF16>, dim3(g), dim3(MB_BLOCK), 0, stream, n, A, lda,
+                           out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_dense(int64_t n, const double* A, int64_t lda, int jacobi, double* d,
+                             DevState* st, hipStream_t s) {
+    int nb = (int)std::min<int64_t>((n + MB_BLOCK - 1) / MB_BLOCK, 4096);
+    hipLaunchKernelGGL(k_diag_dense, dim3(nb), dim3(MB_BLOCK), 0, s, n, A, lda, jacobi, d, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_dense(int64_t n, const double* A, int64_t lda, const double* d, double* As,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_dense, dim3(8192), dim3(MB_BLOCK), 0, s, n, A, lda, d, As);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_resid_reduce(int64_t n, int ksplit, const double* qpart, const double* b,
+                                     double* r_out, double* part, int nwg, hipStream_t stream) {
+    hipLaunchKernelGGL(k_dense_resid_reduce, dim3(nwg), dim3(MB_BLOCK), 0, stream, n, ksplit, qpart,
+                       b, r_out, part);
+    return hipGetLastError();
+}
+
+}  // namespace mb

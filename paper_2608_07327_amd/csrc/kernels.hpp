@@ -1,0 +1,127 @@
+// Host-side launch interface of the MBPCG kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev_common.hpp"
+
+namespace mb {
+
+struct CsrDev {
+    int64_t n, nnz;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* vals;
+};
+
+// widths compiled into the library
+inline bool width_supported(int S) { return S == 1 || S == 2 || S == 4 || S == 8 || S == 16 || S == 32; }
+inline int padded_width(int s) {
+    int S = 1;
+    while (S < s) S *= 2;
+    return S;
+}
+// entries of one workgroup's partial for each reduction
+inline int part_entries_gram(int S) { return tri_count(S); }
+inline int part_entries_update(int S) { return tri_count(S) + S; }
+inline int part_entries_ls(int S) { return tri_count(S + 1); }
+
+// tile rows of the block product for (S, G)
+inline int spmm_tile_rows(int G) { return (MB_BLOCK / G) >= 64 ? (MB_BLOCK / G) : 64; }
+
+// ---- block product Q = A P (+ lower triangle of P^T Q per workgroup)
+hipError_t launch_spmm(int S, int G, int nwg, const CsrDev& A, const double* P, double* Q,
+                       double* part, const DevState* st, hipStream_t stream);
+// valid lanes-per-row choices for width S
+bool spmm_valid_G(int S, int G);
+int spmm_default_G(int S);
+
+// ---- dense product: Q partials over KSPLIT column ranges, then reduce + Gram
+enum DenseKind { DENSE_F64 = 0, DENSE_F32 = 1, DENSE_BF16 = 2 };
+hipError_t launch_dense_ap(int S, DenseKind kind, int64_t n, const void* A, int64_t lda,
+                           const void* Plo, const double* P, double* qpart, int ksplit,
+                           const DevState* st, hipStream_t stream);
+int dense_ksplit(int64_t n);
+int dense_nwg_rows(int64_t n);
+hipError_t launch_dense_reduce(int S, int64_t n, int ksplit, const double* qpart, const double* P,
+                               double* Q, double* part, int nwg, const DevState* st,
+                               hipStream_t stream);
+// FP64 column-major A -> low precision, row-major (transposed), round to nearest even
+hipError_t launch_cast_dense(DenseKind kind, int64_t n, const double* A, int64_t lda, void* out,
+                             hipStream_t stream);
+// r = b - (sum of the ksplit partials of A x) and partial sums of r^2 (S = 1)
+hipError_t launch_dense_resid_reduce(int64_t n, int ksplit, const double* qpart, const double* b,
+                                     double* r_out, double* part, int nwg, hipStream_t stream);
+
+// ---- fused updates of one iteration
+hipError_t launch_update(int S, int nwg, int64_t n, const double* P, const double* Q, double* Xt,
+                         double* R, double* W, const double* d, double* part, const DevState* st,
+                         hipStream_t stream);
+hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, void* Plo,
+                            DenseKind lo_kind, int first, const DevState* st, hipStream_t stream);
+
+// ---- setup
+hipError_t launch_diag_csr(const CsrDev& A, int jacobi, double* d, DevState* st, hipStream_t s);
+hipError_t launch_diag_dense(int64_t n, const double* A, int64_t lda, int jacobi, double* d,
+                             DevState* st, hipStream_t s);
+hipError_t launch_scale_csr(const CsrDev& A, const double* d, double* vals_s, hipStream_t s);
+hipError_t launch_scale_dense(int64_t n, const double* A, int64_t lda, const double* d, double* As,
+                              hipStream_t s);
+hipError_t launch_rhs(int nwg, int64_t n, const double* b, const double* d, double* bbar,
+                      double* part, hipStream_t s);
+hipError_t launch_uniform(int S, int64_t n, int s, uint64_t seed, double* U, hipStream_t st);
+hipError_t launch_pad_block(int S, int64_t n, int s, const double* Uin, double* U, hipStream_t st);
+hipError_t launch_ynorm(int S, int nwg, int64_t n, const double* Y, double* part, hipStream_t s);
+hipError_t launch_init(int S, int64_t n, int s, const double* U, const double* Y,
+                       const double* bbar, double* X0, double* Xt, double* R, const DevState* st,
+                       hipStream_t stream);
+hipError_t launch_gram_nu(int S, int nwg, int64_t n, const double* X, const double* d, double* part,
+                          hipStream_t stream);
+
+// ---- termination
+hipError_t launch_ls_gram(int S, int nwg, int64_t n, const double* b, const double* R,
+                          const double* d, double* part, const DevState* st, hipStream_t s);
+hipError_t launch_ls_apply(int S, int nwg, int64_t n, const double* Xt, const double* X0,
+                           const double* R, const double* b, const double* d, double* x,
+                           double* part, const DevState* st, hipStream_t s);
+hipError_t launch_select(int S, int64_t n, const double* Xt, const double* X0, const double* d,
+                         double* x, const DevState* st, hipStream_t s);
+hipError_t launch_resid_csr(int nwg, const CsrDev& A, const double* b, const double* x,
+                            double* part, hipStream_t s);
+
+// ---- Chronopoulos-Gear CG
+hipError_t launch_cg_init(int64_t n, const double* bbar, double* x, double* r, double* p,
+                          double* sv, hipStream_t s);
+hipError_t launch_cg_update(int nwg, int64_t n, double* p, double* sv, double* x, double* r,
+                            const double* w, const double* d, double* part, const DevState* st,
+                            hipStream_t s);
+hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* x, hipStream_t s);
+
+// ---- tails (one workgroup): reductions of partials + s x s FP64 work
+hipError_t launch_tail_gamma(int nwg_b, const double* part_b, int nwg_y, const double* part_y,
+                             DevState* st, hipStream_t s);
+hipError_t launch_tail_xi(int S, int nwg, const double* part, DevState* st, hipStream_t s);
+hipError_t launch_tail_qr(int S, int nwg, const double* part, DevState* st, double* hist,
+                          int setup, hipStream_t s);
+hipError_t launch_tail_ls(int S, int nwg, const double* part, DevState* st, hipStream_t s);
+hipError_t launch_tail_accept(int nwg, const double* part, DevState* st, hipStream_t s);
+hipError_t launch_tail_true(int nwg, const double* part, DevState* st, hipStream_t s);
+hipError_t launch_tail_cg0(int nwg_b, const double* part_b, int nwg_s, const double* part_s,
+                           DevState* st, hipStream_t s);
+hipError_t launch_tail_cg(int nwg_u, const double* part_u, int nwg_s, const double* part_s,
+                          DevState* st, double* hist, hipStream_t s);
+hipError_t launch_state_init(DevState* st, int s, int max_iter, double tol, double tol0,
+                             double tau, int n_hist, hipStream_t stream);
+
+hipError_t launch_block_to_lo(DenseKind kind, int64_t count, const double* src, void* dst,
+                             hipStream_t s);
+hipError_t launch_axpy_ir(int64_t n, double* x, const double* d, hipStream_t s);
+// sqrt of a reduced sum of squares into st->res_norm
+hipError_t launch_tail_norm(int nwg, const double* part, DevState* st, hipStream_t s);
+// reduce Gram partials (lower triangle) into C (S x S row-major, i >= j)
+hipError_t launch_gram_out(int S, int nwg, const double* part, double* C, hipStream_t s);
+
+// plain streaming copy (byte-counter calibration)
+hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
+
+}  // namespace mb

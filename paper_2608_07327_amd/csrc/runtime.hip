@@ -1,0 +1,695 @@
+// Host runtime: context lifetime, device buffers, the per-iteration launch
+// sequence of Algorithm 1, graph capture of batches of iterations, the stop
+// polling, the CG baseline and the FP64 iterative-refinement loop.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace mb {
+
+#define CK(expr)                                                                      \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess) {                                                       \
+            c.err = std::string(#expr) + " failed: " + hipGetErrorString(_e);        \
+            return _e == hipErrorOutOfMemory ? MBPCG_ERR_OOM : MBPCG_ERR_HIP;         \
+        }                                                                             \
+    } while (0)
+
+#define CKS(expr)                        \
+    do {                                 \
+        mbpcg_status _s = (expr);        \
+        if (_s != MBPCG_OK) return _s;   \
+    } while (0)
+
+constexpr int NWG_MAX = 2048;
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+static void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+Ctx::~Ctx() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    dfree(rowptr); dfree(colind); dfree(vals); dfree(vals_s);
+    if (As && As != A) dfree(As);
+    As = nullptr;
+    dfree(A); dfree(Alo);
+    dfree(d); dfree(bbar); dfree(bdev); dfree(xdev); dfree(rvec); dfree(xacc);
+    dfree(U); dfree(Y); dfree(X0); dfree(Xt); dfree(R); dfree(W); dfree(P); dfree(Q); dfree(Plo);
+    dfree(qpart); dfree(part_a); dfree(part_b); dfree(part_c); dfree(st); dfree(hist);
+    if (pinned) (void)hipHostFree(pinned);
+    if (st_host) (void)hipHostFree(st_host);
+    for (auto& e : ev_poll)
+        if (e) (void)hipEventDestroy(e);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    if (ev_user) (void)hipEventDestroy(ev_user);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+static mbpcg_status dalloc(Ctx& c, void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e == hipErrorOutOfMemory) {
+        c.err = "out of device memory";
+        return MBPCG_ERR_OOM;
+    }
+    if (e != hipSuccess) {
+        c.err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+        return MBPCG_ERR_HIP;
+    }
+    return MBPCG_OK;
+}
+#define DALLOC(ptr, bytes) CKS(dalloc(c, (void**)&(ptr), (bytes)))
+
+static void drop_graphs(Ctx& c) {
+    for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+    c.graphs.clear();
+}
+
+mbpcg_status ctx_init_common(Ctx& c, hipStream_t user_stream) {
+    CK(hipGetDevice(&c.device));
+    c.user_stream = user_stream;
+    CK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    CK(hipEventCreateWithFlags(&c.ev_poll[0], hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&c.ev_poll[1], hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&c.ev_user, hipEventDisableTiming));
+    CK(hipEventCreate(&c.ev_a));
+    CK(hipEventCreate(&c.ev_b));
+    CK(hipHostMalloc((void**)&c.pinned, 4 * sizeof(int32_t), hipHostMallocDefault));
+    CK(hipHostMalloc((void**)&c.st_host, sizeof(DevState), hipHostMallocDefault));
+    DALLOC(c.st, sizeof(DevState));
+    const size_t nb = sizeof(double) * (size_t)c.n;
+    DALLOC(c.d, nb);
+    DALLOC(c.bbar, nb);
+    DALLOC(c.bdev, nb);
+    DALLOC(c.xdev, nb);
+    return MBPCG_OK;
+}
+
+static mbpcg_status ensure_blocks(Ctx& c, int S) {
+    if (c.Scap >= S) return MBPCG_OK;
+    drop_graphs(c);
+    dfree(c.U); dfree(c.Y); dfree(c.X0); dfree(c.Xt); dfree(c.R); dfree(c.W); dfree(c.P); dfree(c.Q);
+    dfree(c.Plo); dfree(c.part_a); dfree(c.part_b); dfree(c.part_c); dfree(c.qpart);
+    const size_t bb = sizeof(double) * (size_t)c.n * S;
+    DALLOC(c.U, bb); DALLOC(c.Y, bb); DALLOC(c.X0, bb); DALLOC(c.Xt, bb);
+    DALLOC(c.R, bb); DALLOC(c.W, bb); DALLOC(c.P, bb); DALLOC(c.Q, bb);
+    DALLOC(c.Plo, sizeof(float) * (size_t)c.n * S);
+    int e = std::max(part_entries_update(S), part_entries_ls(S));
+    e = std::max(e, 4);
+    c.part_elems = (int64_t)NWG_MAX * e;
+    DALLOC(c.part_a, sizeof(double) * c.part_elems);
+    DALLOC(c.part_b, sizeof(double) * c.part_elems);
+    DALLOC(c.part_c, sizeof(double) * c.part_elems);
+    if (c.dense) {
+        c.qpart_elems = (int64_t)dense_ksplit(c.n) * c.n * S;
+        DALLOC(c.qpart, sizeof(double) * c.qpart_elems);
+    }
+    c.Scap = S;
+    return MBPCG_OK;
+}
+
+static mbpcg_status ensure_hist(Ctx& c, int64_t cap) {
+    if (cap < 1) cap = 1;
+    if (c.hist_cap >= cap) return MBPCG_OK;
+    drop_graphs(c);
+    dfree(c.hist);
+    DALLOC(c.hist, sizeof(double) * cap);
+    c.hist_cap = cap;
+    return MBPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch plan of one solve
+// ---------------------------------------------------------------------------
+struct Plan {
+    int s = 1, S = 1;
+    DenseKind kind = DENSE_F64;
+    int G = 8;
+    int nwg_prod = 1;    // partials of the block product's Gram
+    int nwg_spmm = 1;    // grid of the sparse product
+    int nwg_upd = 1;     // update / gram_nu grid
+    int nwg_dir = 1;
+    int nwg_ls = 1;
+    int nwg_e = 1;       // element-wise reductions
+    int ksplit = 1;
+    int nwg_dred = 1;    // dense reduce grid
+};
+
+static int round_grid(int64_t ntiles, int cap) {
+    int64_t g = std::min<int64_t>(ntiles, cap);
+    if (g >= 8) g = g / 8 * 8;
+    return (int)std::max<int64_t>(g, 1);
+}
+
+static Plan make_plan(Ctx& c, int s, DenseKind kind) {
+    Plan pl;
+    pl.s = s;
+    pl.S = padded_width(s);
+    pl.kind = kind;
+    const int S = pl.S;
+    const int cap = S >= 16 ? 512 : 1024;
+    auto it = c.tune.find(S);
+    pl.G = (it != c.tune.end() && it->second.G) ? it->second.G : spmm_default_G(S);
+    const int64_t spmm_tiles = (c.n + spmm_tile_rows(pl.G) - 1) / spmm_tile_rows(pl.G);
+    pl.nwg_spmm = (it != c.tune.end() && it->second.nwg) ? std::min<int64_t>(it->second.nwg, NWG_MAX)
+                                                         : round_grid(spmm_tiles, cap);
+    const int Tu = std::max(64, MB_BLOCK / S);
+    const int64_t upd_tiles = (c.n + Tu - 1) / Tu;
+    pl.nwg_upd = round_grid(upd_tiles, cap);
+    pl.nwg_dir = round_grid(upd_tiles, 1024);
+    pl.nwg_ls = round_grid((c.n + 63) / 64, cap);
+    pl.nwg_e = round_grid((c.n + MB_BLOCK - 1) / MB_BLOCK, 1024);
+    if (c.dense) {
+        pl.ksplit = dense_ksplit(c.n);
+        pl.nwg_dred = round_grid((c.n + 63) / 64, cap);
+        pl.nwg_prod = pl.nwg_dred;
+    } else {
+        pl.nwg_prod = pl.nwg_spmm;
+    }
+    return pl;
+}
+
+static CsrDev csr_of(const Ctx& c, bool scaled) {
+    CsrDev a;
+    a.n = c.n;
+    a.nnz = c.nnz;
+    a.rowptr = c.rowptr;
+    a.colind = c.colind;
+    a.vals = scaled ? c.vals_s : c.vals;
+    return a;
+}
+
+// Q = A~ P (+ Gram partials in `part` unless null).  For the low-precision
+// kinds P is read from c.Plo.
+static hipError_t launch_product(Ctx& c, const Plan& pl, const double* P, double* Q, double* part,
+                                 const DevState* st, int S_override = 0) {
+    const int S = S_override ? S_override : pl.S;
+    if (!c.dense) return launch_spmm(S, S_override ? spmm_default_G(S) : pl.G, pl.nwg_spmm,
+                                     csr_of(c, true), P, Q, part, st, c.stream);
+    const void* A = pl.kind == DENSE_F64 ? (const void*)c.As : (const void*)c.Alo;
+    hipError_t e = launch_dense_ap(S, pl.kind, c.n, A, c.n, c.Plo, P, c.qpart, pl.ksplit, st,
+                                   c.stream);
+    if (e != hipSuccess) return e;
+    return launch_dense_reduce(S, c.n, pl.ksplit, c.qpart, P, Q, part, pl.nwg_dred, st, c.stream);
+}
+
+// one iteration of Alg. 1's loop: lines Xi .. Sigma
+static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist) {
+    hipError_t e;
+    if ((e = launch_product(c, pl, c.P, c.Q, c.part_a, c.st)) != hipSuccess) return e;
+    if ((e = launch_tail_xi(pl.S, pl.nwg_prod, c.part_a, c.st, c.stream)) != hipSuccess) return e;
+    if ((e = launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d, c.part_b, c.st,
+                           c.stream)) != hipSuccess)
+        return e;
+    if ((e = launch_tail_qr(pl.S, pl.nwg_upd, c.part_b, c.st, hist, 0, c.stream)) != hipSuccess)
+        return e;
+    return launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st, c.stream);
+}
+
+static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist) {
+    hipError_t e;
+    if ((e = launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c, c.st,
+                              c.stream)) != hipSuccess)
+        return e;
+    if ((e = launch_product(c, pl, c.R, c.Q, c.part_a, c.st)) != hipSuccess) return e;
+    return launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, hist, c.stream);
+}
+
+static mbpcg_status get_graph(Ctx& c, const Plan& pl, int m, int cg, hipGraphExec_t* out) {
+    auto key = std::make_tuple(cg * 2 + c.dense, pl.S, m, pl.G, pl.nwg_spmm, (int)pl.kind);
+    auto it = c.graphs.find(key);
+    if (it != c.graphs.end()) {
+        *out = it->second;
+        return MBPCG_OK;
+    }
+    hipGraph_t g = nullptr;
+    CK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < m && le == hipSuccess; ++i)
+        le = cg ? launch_cg_iteration(c, pl, c.hist) : launch_iteration(c, pl, c.hist);
+    hipError_t ce = hipStreamEndCapture(c.stream, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        c.err = std::string("graph capture failed: ") +
+                hipGetErrorString(le != hipSuccess ? le : ce);
+        return MBPCG_ERR_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        c.err = std::string("graph instantiate failed: ") + hipGetErrorString(ie);
+        return MBPCG_ERR_HIP;
+    }
+    c.graphs[key] = ex;
+    *out = ex;
+    return MBPCG_OK;
+}
+
+static int auto_poll(const Ctx& c, int cg) {
+    // iterations per graph launch: enough to hide the host check, few enough
+    // that the no-op tail after convergence stays short
+    if (c.n * (cg ? 1 : 4) < (1 << 18)) return 32;
+    return 16;
+}
+
+// Run batches of m iterations until the device sets `done`.
+static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int cg, double* ms_loop,
+                            double* prof_ms, double* prof_n) {
+    const int m = p.poll_every > 0 ? p.poll_every : auto_poll(c, cg);
+    const double t0 = now_ms();
+    if (p.profile) {
+        // direct launches with events around the block product (Sec. 4 / Table 2 style)
+        int64_t it = 0;
+        for (;;) {
+            CK(hipEventRecord(c.ev_a, c.stream));
+            if (cg) {
+                CK(launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c, c.st,
+                                    c.stream));
+                CK(hipEventRecord(c.ev_a, c.stream));
+                CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
+                CK(hipEventRecord(c.ev_b, c.stream));
+                CK(launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, c.hist,
+                                  c.stream));
+            } else {
+                CK(launch_product(c, pl, c.P, c.Q, c.part_a, c.st));
+                CK(hipEventRecord(c.ev_b, c.stream));
+                CK(launch_tail_xi(pl.S, pl.nwg_prod, c.part_a, c.st, c.stream));
+                CK(launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d, c.part_b,
+                                 c.st, c.stream));
+                CK(launch_tail_qr(pl.S, pl.nwg_upd, c.part_b, c.st, c.hist, 0, c.stream));
+                CK(launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st,
+                                    c.stream));
+            }
+            CK(hipMemcpyAsync(c.pinned, c.st, 8, hipMemcpyDeviceToHost, c.stream));
+            CK(hipStreamSynchronize(c.stream));
+            float ms = 0.f;
+            CK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
+            *prof_ms += ms;    // accumulated block-product time
+            *prof_n += 1.0;    // block-product launches
+            if (c.pinned[0]) break;
+            if (++it > p.max_iter + 2) break;
+        }
+        *ms_loop = now_ms() - t0;
+        return MBPCG_OK;
+    }
+    hipGraphExec_t g = nullptr;
+    CKS(get_graph(c, pl, m, cg, &g));
+    const int64_t max_launch = p.max_iter / m + 4;
+    int64_t launched = 0;
+    for (int k = 0; k < 2; ++k) {
+        CK(hipGraphLaunch(g, c.stream));
+        CK(hipMemcpyAsync(c.pinned + 2 * k, c.st, 8, hipMemcpyDeviceToHost, c.stream));
+        CK(hipEventRecord(c.ev_poll[k], c.stream));
+        ++launched;
+    }
+    for (int64_t k = 0;; ++k) {
+        const int slot = (int)(k & 1);
+        CK(hipEventSynchronize(c.ev_poll[slot]));
+        if (c.pinned[2 * slot]) break;
+        if (launched >= max_launch) break;
+        CK(hipGraphLaunch(g, c.stream));
+        CK(hipMemcpyAsync(c.pinned + 2 * slot, c.st, 8, hipMemcpyDeviceToHost, c.stream));
+        CK(hipEventRecord(c.ev_poll[slot], c.stream));
+        ++launched;
+    }
+    CK(hipStreamSynchronize(c.stream));
+    *ms_loop = now_ms() - t0;
+    return MBPCG_OK;
+}
+
+static mbpcg_status read_state(Ctx& c) {
+    CK(hipMemcpyAsync(c.st_host, c.st, sizeof(DevState), hipMemcpyDeviceToHost, c.stream));
+    CK(hipStreamSynchronize(c.stream));
+    return MBPCG_OK;
+}
+
+static mbpcg_status status_of(int done) {
+    switch (done) {
+        case DONE_CONVERGED: return MBPCG_OK;
+        case DONE_ZERO_RHS: return MBPCG_OK;
+        case DONE_MAXITER: return MBPCG_NOT_CONVERGED;
+        case DONE_BREAKDOWN: return MBPCG_ERR_BREAKDOWN;
+        case DONE_NOTSPD: return MBPCG_ERR_NOT_SPD;
+        case DONE_NONFINITE: return MBPCG_ERR_NONFINITE;
+    }
+    return MBPCG_NOT_CONVERGED;
+}
+
+// diag, scaling (Sec. 1), b~ and ||b|| partials
+static mbpcg_status setup_scaling(Ctx& c, const Plan& pl, const double* b, int jacobi) {
+    if (!c.dense) {
+        CK(launch_diag_csr(csr_of(c, false), jacobi, c.d, c.st, c.stream));
+        if (jacobi) {
+            if (!c.vals_s) DALLOC(c.vals_s, sizeof(double) * (size_t)std::max<int64_t>(c.nnz, 1));
+            CK(launch_scale_csr(csr_of(c, false), c.d, c.vals_s, c.stream));
+        } else {
+            if (!c.vals_s) DALLOC(c.vals_s, sizeof(double) * (size_t)std::max<int64_t>(c.nnz, 1));
+            CK(hipMemcpyAsync(c.vals_s, c.vals, sizeof(double) * c.nnz, hipMemcpyDeviceToDevice,
+                              c.stream));
+        }
+    } else {
+        CK(launch_diag_dense(c.n, c.A, c.n, jacobi, c.d, c.st, c.stream));
+        if (jacobi) {
+            if (!c.As || c.As == c.A) {
+                c.As = nullptr;
+                DALLOC(c.As, sizeof(double) * (size_t)c.n * c.n);
+                drop_graphs(c);
+            }
+            CK(launch_scale_dense(c.n, c.A, c.n, c.d, c.As, c.stream));
+        } else {
+            if (c.As && c.As != c.A) {
+                dfree(c.As);
+                drop_graphs(c);
+            }
+            if (c.As != c.A) drop_graphs(c);
+            c.As = c.A;
+        }
+    }
+    CK(launch_rhs(pl.nwg_e, c.n, b, c.d, c.bbar, c.part_c, c.stream));
+    return MBPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 on device-resident b and x.
+// ---------------------------------------------------------------------------
+static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* Udev,
+                              const mbpcg_params& p, DenseKind kind, bool true_resid,
+                              mbpcg_info& info) {
+    const int s = p.s;
+    Plan pl = make_plan(c, s, kind);
+    const int S = pl.S;
+    CKS(ensure_blocks(c, S));
+    CKS(ensure_hist(c, p.history ? p.max_iter : 1));
+    const int jac = p.precond == MBPCG_PRECOND_JACOBI;
+    const double tol0 = p.tol_initial > 0 ? p.tol_initial : p.tol;
+    const double tau = p.tau > 0 ? p.tau : 1e-12;
+    const double t0 = now_ms();
+    memset(c.st_host, 0, sizeof(DevState));
+
+    CK(launch_state_init(c.st, s, (int)std::min<int64_t>(p.max_iter, INT32_MAX), p.tol, tol0, tau,
+                         p.history ? (int)std::min<int64_t>(p.max_iter, INT32_MAX) : 0, c.stream));
+    CKS(setup_scaling(c, pl, b, jac));
+    // line U
+    if (Udev) CK(launch_pad_block(S, c.n, s, Udev, c.U, c.stream));
+    else CK(launch_uniform(S, c.n, s, p.seed, c.U, c.stream));
+    // line X^0: Y = A~ U, ||Y||_F
+    if (kind != DENSE_F64) CK(launch_block_to_lo(kind, c.n * S, c.U, c.Plo, c.stream));
+    CK(launch_product(c, pl, c.U, c.Y, nullptr, c.st));
+    CK(launch_ynorm(S, pl.nwg_e, c.n, c.Y, c.part_a, c.stream));
+    CK(launch_tail_gamma(pl.nwg_e, c.part_c, pl.nwg_e, c.part_a, c.st, c.stream));
+    // lines tilde_B .. R^0, W^0, P^0
+    CK(launch_init(S, c.n, s, c.U, c.Y, c.bbar, c.X0, c.Xt, c.R, c.st, c.stream));
+    CK(launch_gram_nu(S, pl.nwg_upd, c.n, c.R, c.d, c.part_b, c.stream));
+    CK(launch_tail_qr(S, pl.nwg_upd, c.part_b, c.st, nullptr, 1, c.stream));
+    CK(hipMemcpyAsync(c.W, c.R, sizeof(double) * (size_t)c.n * S, hipMemcpyDeviceToDevice,
+                      c.stream));
+    CK(launch_dirupdate(S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, kind, 1, c.st, c.stream));
+    const double t_setup = now_ms();
+
+    double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
+    CKS(run_loop(c, pl, p, 0, &ms_loop, &prof_ms, &prof_n));
+    CKS(read_state(c));
+    const int done = c.st_host->done;
+
+    if (done == DONE_ZERO_RHS) {
+        CK(hipMemsetAsync(x, 0, sizeof(double) * c.n, c.stream));
+    } else {
+        if (done == DONE_CONVERGED) {
+            CK(launch_ls_gram(S, pl.nwg_ls, c.n, b, c.R, c.d, c.part_a, c.st, c.stream));
+            CK(launch_tail_ls(S, pl.nwg_ls, c.part_a, c.st, c.stream));
+            CK(launch_ls_apply(S, pl.nwg_e, c.n, c.Xt, c.X0, c.R, b, c.d, x, c.part_b, c.st,
+                               c.stream));
+            CK(launch_tail_accept(pl.nwg_e, c.part_b, c.st, c.stream));
+        }
+        CK(launch_select(S, c.n, c.Xt, c.X0, c.d, x, c.st, c.stream));
+        if (true_resid) {
+            if (!c.dense) {
+                CK(launch_resid_csr(pl.nwg_e, csr_of(c, false), b, x, c.part_a, c.stream));
+            } else {
+                CK(launch_dense_ap(1, DENSE_F64, c.n, c.A, c.n, nullptr, x, c.qpart, pl.ksplit,
+                                   nullptr, c.stream));
+                CK(launch_dense_resid_reduce(c.n, pl.ksplit, c.qpart, b, nullptr, c.part_a,
+                                             pl.nwg_e, c.stream));
+            }
+            CK(launch_tail_true(pl.nwg_e, c.part_a, c.st, c.stream));
+        }
+    }
+    CKS(read_state(c));
+    const double t1 = now_ms();
+    const DevState& h = *c.st_host;
+    info.iterations += h.iter;
+    info.best_column = h.h;
+    info.final_width = h.width;
+    info.deflations += h.deflations;
+    info.used_fallback = (done == DONE_ZERO_RHS) ? 0 : (h.accepted ? 0 : 1);
+    info.rel_res_best_basis = h.nu_h;
+    info.rel_res_ls = (done == DONE_CONVERGED) ? h.rel_ls : NAN;
+    info.rel_res_true = (done == DONE_ZERO_RHS) ? 0.0 : h.rel_true;
+    info.ms_total += t1 - t0;
+    info.ms_per_iter = h.iter > 0 ? ms_loop / h.iter : 0.0;
+    info.ms_spmm += prof_ms;
+    info.spmm_launches += (int64_t)prof_n;
+    info.ms_phase[0] += prof_ms;
+    (void)t_setup;
+    if (p.history && h.iter > 0) {
+        const int64_t k = std::min<int64_t>(h.iter, p.max_iter);
+        CK(hipMemcpy(p.history, c.hist, sizeof(double) * k, hipMemcpyDeviceToHost));
+    }
+    return status_of(done);
+}
+
+// ---------------------------------------------------------------------------
+// Chronopoulos-Gear CG (x0 = 0) on the same scaled system and stop rule.
+// ---------------------------------------------------------------------------
+static mbpcg_status run_cg(Ctx& c, const double* b, double* x, const mbpcg_params& p,
+                           mbpcg_info& info) {
+    Plan pl = make_plan(c, 1, DENSE_F64);
+    CKS(ensure_blocks(c, 1));
+    CKS(ensure_hist(c, p.history ? p.max_iter : 1));
+    const int jac = p.precond == MBPCG_PRECOND_JACOBI;
+    const double t0 = now_ms();
+    memset(c.st_host, 0, sizeof(DevState));
+    CK(launch_state_init(c.st, 1, (int)std::min<int64_t>(p.max_iter, INT32_MAX), p.tol, p.tol, 1e-12,
+                         p.history ? (int)std::min<int64_t>(p.max_iter, INT32_MAX) : 0, c.stream));
+    CKS(setup_scaling(c, pl, b, jac));
+    CK(launch_cg_init(c.n, c.bbar, c.Xt, c.R, c.P, c.W, c.stream));
+    CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
+    CK(launch_tail_cg0(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, c.stream));
+    double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
+    CKS(run_loop(c, pl, p, 1, &ms_loop, &prof_ms, &prof_n));
+    CKS(read_state(c));
+    const int done = c.st_host->done;
+    if (done == DONE_ZERO_RHS) {
+        CK(hipMemsetAsync(x, 0, sizeof(double) * c.n, c.stream));
+    } else {
+        CK(launch_unscale(c.n, c.Xt, c.d, x, c.stream));
+        if (!c.dense) {
+            CK(launch_resid_csr(pl.nwg_e, csr_of(c, false), b, x, c.part_a, c.stream));
+        } else {
+            CK(launch_dense_ap(1, DENSE_F64, c.n, c.A, c.n, nullptr, x, c.qpart, pl.ksplit, nullptr,
+                               c.stream));
+            CK(launch_dense_resid_reduce(c.n, pl.ksplit, c.qpart, b, nullptr, c.part_a, pl.nwg_e,
+                                         c.stream));
+        }
+        CK(launch_tail_true(pl.nwg_e, c.part_a, c.st, c.stream));
+    }
+    CKS(read_state(c));
+    const double t1 = now_ms();
+    const DevState& h = *c.st_host;
+    info.iterations = h.iter;
+    info.best_column = 0;
+    info.final_width = 1;
+    info.rel_res_best_basis = h.cg_rel;
+    info.rel_res_ls = NAN;
+    info.rel_res_true = (done == DONE_ZERO_RHS) ? 0.0 : h.rel_true;
+    info.ms_total = t1 - t0;
+    info.ms_per_iter = h.iter > 0 ? ms_loop / h.iter : 0.0;
+    info.ms_spmm = prof_ms;
+    info.spmm_launches = (int64_t)prof_n;
+    if (p.history && h.iter > 0) {
+        const int64_t k = std::min<int64_t>(h.iter, p.max_iter);
+        CK(hipMemcpy(p.history, c.hist, sizeof(double) * k, hipMemcpyDeviceToHost));
+    }
+    return status_of(done);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 iterative refinement around a low-precision inner MBPCG (dense A).
+// ---------------------------------------------------------------------------
+static mbpcg_status run_ir(Ctx& c, const double* b, double* x, const double* Udev,
+                           const mbpcg_params& p, mbpcg_info& info) {
+    const DenseKind kind = p.precision == MBPCG_FP32_IR ? DENSE_F32 : DENSE_BF16;
+    const double t0 = now_ms();
+    if (!c.rvec) DALLOC(c.rvec, sizeof(double) * c.n);
+    if (!c.xacc) DALLOC(c.xacc, sizeof(double) * c.n);
+    // scaling and the low-precision copy of A are made once per solve
+    Plan pl = make_plan(c, p.s, kind);
+    CKS(ensure_blocks(c, pl.S));
+    const int jac = p.precond == MBPCG_PRECOND_JACOBI;
+    CK(launch_state_init(c.st, p.s, 1, p.tol, p.tol, 1e-12, 0, c.stream));
+    CKS(setup_scaling(c, pl, b, jac));
+    const size_t esz = kind == DENSE_F32 ? sizeof(float) : 2;
+    if (!c.Alo || c.alo_kind != kind) {
+        dfree(c.Alo);
+        DALLOC(c.Alo, esz * (size_t)c.n * c.n);
+        c.alo_kind = kind;
+        drop_graphs(c);
+    }
+    CK(launch_cast_dense(kind, c.n, c.As, c.n, c.Alo, c.stream));
+    CK(hipMemsetAsync(c.xacc, 0, sizeof(double) * c.n, c.stream));
+    CK(hipMemcpyAsync(c.rvec, b, sizeof(double) * c.n, hipMemcpyDeviceToDevice, c.stream));
+    // ||b|| in FP64 (the k-split partials of A * 0 are the zeros in xacc)
+    CK(launch_dense_resid_reduce(c.n, 1, c.xacc, b, nullptr, c.part_c, pl.nwg_e, c.stream));
+    CK(launch_tail_norm(pl.nwg_e, c.part_c, c.st, c.stream));
+    CKS(read_state(c));
+    const double bnorm = c.st_host->res_norm;
+    if (!std::isfinite(bnorm)) return MBPCG_ERR_NONFINITE;
+    if (bnorm == 0.0) {
+        if (x) CK(hipMemsetAsync(x, 0, sizeof(double) * c.n, c.stream));
+        CK(hipStreamSynchronize(c.stream));
+        info.rel_res_true = 0.0;
+        info.ms_total = now_ms() - t0;
+        return MBPCG_OK;
+    }
+    mbpcg_params inner = p;
+    inner.tol = p.inner_tol;
+    inner.tol_initial = 0.0;
+    inner.history = nullptr;
+    mbpcg_status last = MBPCG_OK;
+    double rel = 1.0;
+    int outer = 0;
+    const int max_outer = p.max_outer > 0 ? p.max_outer : 50;
+    for (outer = 1; outer <= max_outer; ++outer) {
+        inner.seed = p.seed + (uint64_t)(outer - 1) * 7919u;
+        mbpcg_info ii;
+        memset(&ii, 0, sizeof(ii));
+        // inner solve A_lo d = r; d lands in c.xdev
+        last = run_mbpcg(c, c.rvec, c.xdev, outer == 1 ? Udev : nullptr, inner, kind, false, ii);
+        info.iterations += ii.iterations;
+        info.deflations += ii.deflations;
+        info.best_column = ii.best_column;
+        info.final_width = ii.final_width;
+        info.used_fallback = ii.used_fallback;
+        info.rel_res_best_basis = ii.rel_res_best_basis;
+        info.rel_res_ls = ii.rel_res_ls;
+        if (last == MBPCG_ERR_HIP || last == MBPCG_ERR_OOM) return last;
+        if (last == MBPCG_ERR_NOT_SPD || last == MBPCG_ERR_NONFINITE) break;
+        // x += d;  r = b - A x with the FP64 A
+        CK(launch_axpy_ir(c.n, c.xacc, c.xdev, c.stream));
+        CK(launch_dense_ap(1, DENSE_F64, c.n, c.A, c.n, nullptr, c.xacc, c.qpart, pl.ksplit, nullptr,
+                           c.stream));
+        CK(launch_dense_resid_reduce(c.n, pl.ksplit, c.qpart, b, c.rvec, c.part_a, pl.nwg_e,
+                                     c.stream));
+        CK(launch_tail_norm(pl.nwg_e, c.part_a, c.st, c.stream));
+        CKS(read_state(c));
+        rel = c.st_host->res_norm / bnorm;
+        info.rel_res_true = rel;
+        if (!(rel > p.ir_tol)) break;
+    }
+    if (x) CK(hipMemcpyAsync(x, c.xacc, sizeof(double) * c.n, hipMemcpyDeviceToDevice, c.stream));
+    CK(hipStreamSynchronize(c.stream));
+    info.outer_iterations = std::min(outer, max_outer);
+    info.ms_total = now_ms() - t0;
+    info.ms_per_iter = info.iterations > 0 ? info.ms_total / info.iterations : 0.0;
+    if (!std::isfinite(rel)) return MBPCG_ERR_NONFINITE;
+    if (rel <= p.ir_tol) return MBPCG_OK;
+    return last < 0 ? last : MBPCG_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// entry points used by the C ABI
+// ---------------------------------------------------------------------------
+mbpcg_status solve_entry(Ctx& c, const double* b, double* x, mbpcg_mem mem,
+                         const mbpcg_params& p, mbpcg_info& info, int cg) {
+    CK(hipSetDevice(c.device));
+    // order after the caller's stream
+    CK(hipEventRecord(c.ev_user, c.user_stream));
+    CK(hipStreamWaitEvent(c.stream, c.ev_user, 0));
+    const double* bd = b;
+    double* xd = x;
+    const double* Ud = nullptr;
+    if (mem == MBPCG_MEM_HOST) {
+        CK(hipMemcpyAsync(c.bdev, b, sizeof(double) * c.n, hipMemcpyHostToDevice, c.stream));
+        bd = c.bdev;
+        xd = c.xdev;
+    }
+    if (p.U && !cg) {
+        if (mem == MBPCG_MEM_HOST) {
+            CKS(ensure_blocks(c, padded_width(p.s)));
+            CK(hipMemcpyAsync(c.Y, p.U, sizeof(double) * c.n * p.s, hipMemcpyHostToDevice,
+                              c.stream));
+            Ud = c.Y;
+        } else {
+            Ud = p.U;
+        }
+    }
+    mbpcg_status st;
+    if (cg) st = run_cg(c, bd, xd, p, info);
+    else if (p.precision == MBPCG_FP64) st = run_mbpcg(c, bd, xd, Ud, p, DENSE_F64, true, info);
+    else st = run_ir(c, bd, mem == MBPCG_MEM_HOST ? nullptr : xd, Ud, p, info);
+    if (st == MBPCG_ERR_HIP || st == MBPCG_ERR_OOM) return st;
+    if (mem == MBPCG_MEM_HOST) {
+        const double* src = (!cg && p.precision != MBPCG_FP64) ? c.xacc : c.xdev;
+        CK(hipMemcpyAsync(x, src, sizeof(double) * c.n, hipMemcpyDeviceToHost, c.stream));
+    }
+    CK(hipStreamSynchronize(c.stream));
+    return st;
+}
+
+mbpcg_status block_product_entry(Ctx& c, int s, int jacobi, const double* P, double* Q, double* C) {
+    CK(hipSetDevice(c.device));
+    CK(hipEventRecord(c.ev_user, c.user_stream));
+    CK(hipStreamWaitEvent(c.stream, c.ev_user, 0));
+    Plan pl = make_plan(c, s, DENSE_F64);
+    CKS(ensure_blocks(c, pl.S));
+    CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
+    CKS(setup_scaling(c, pl, c.bdev, jacobi));
+    CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
+    CK(launch_product(c, pl, P, Q, c.part_a, c.st));
+    hipError_t launch_gram_out(int S, int nwg, const double* part, double* C, hipStream_t s);
+    CK(launch_gram_out(pl.S, pl.nwg_prod, c.part_a, C, c.stream));
+    CK(hipStreamSynchronize(c.stream));
+    return MBPCG_OK;
+}
+
+mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, double* Q,
+                                      double* ms_avg) {
+    CK(hipSetDevice(c.device));
+    Plan pl = make_plan(c, s, DENSE_F64);
+    CKS(ensure_blocks(c, pl.S));
+    if (!c.vals_s && !c.dense) CKS(setup_scaling(c, pl, c.bdev, 0));
+    if (c.dense && !c.As) c.As = c.A;
+    CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
+    CK(launch_product(c, pl, P, Q, c.part_a, c.st));  // warm-up
+    CK(hipEventRecord(c.ev_a, c.stream));
+    for (int i = 0; i < reps; ++i) {
+        if (!c.dense) {
+            CK(launch_spmm(pl.S, pl.G, pl.nwg_spmm, csr_of(c, true), P, Q, c.part_a, c.st, c.stream));
+        } else {
+            CK(launch_dense_ap(pl.S, DENSE_F64, c.n, c.As, c.n, nullptr, P, c.qpart, pl.ksplit, c.st,
+                               c.stream));
+        }
+    }
+    CK(hipEventRecord(c.ev_b, c.stream));
+    CK(hipEventSynchronize(c.ev_b));
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
+    *ms_avg = (double)ms / reps;
+    return MBPCG_OK;
+}
+
+}  // namespace mb

@@ -1,0 +1,301 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+Tolerances (FP64): iteration counts equal (one off only when the deciding
+residual sits within 1 % of the tolerance); solutions agree to
+max(1e-10, 10 f) in relative 2-norm, where f is the oracle's own change
+when its reductions are re-ordered (sequential vs blocked pairwise), i.e.
+the rounding-order noise floor of the method on that input.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_07327_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_07327_amd import mbpcg as M  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def noise_floor(A, b, s, **kw):
+    x0, i0, _ = O.mbpcg_solve(A, b, s, **kw)
+    O.set_summation(1)
+    try:
+        x1, i1, _ = O.mbpcg_solve(A, b, s, **kw)
+    finally:
+        O.set_summation(0)
+    return rel(x1, x0), i0, i1
+
+
+def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_iter=100000,
+                         floor=True, extra_tol=None):
+    say("mbpcg", getattr(A, "n", None) or A.shape[0], "s", s, "seed", seed)
+    kw = dict(tol=tol, jacobi=jacobi, seed=seed, U=U, max_iter=max_iter)
+    xo, io, _ = O.mbpcg_solve(A, b, s, **kw)
+    f = noise_floor(A, b, s, **kw)[0] if floor else 0.0
+    solver = M.Solver.from_matrix(A)
+    Ud = None if U is None else dev(U)
+    x, info = solver.solve(dev(b), s=s, tol=tol, seed=seed, U=Ud, max_iter=max_iter,
+                           precond=M.PRECOND_JACOBI if jacobi else M.PRECOND_NONE)
+    x = x.cpu().numpy()
+    bound = max(1e-10, 10 * f) if extra_tol is None else extra_tol
+    near = abs(io["rel_res_best"] - tol) <= 0.01 * tol
+    assert info["status"] == io["status"], (info, io)
+    if near:
+        assert abs(info["iterations"] - io["iterations"]) <= 1
+    else:
+        assert info["iterations"] == io["iterations"], (info["iterations"], io["iterations"])
+        assert info["used_fallback"] == io["used_fallback"]
+        assert info["final_width"] == io["final_width"]
+        assert rel(x, xo) <= bound, (rel(x, xo), bound, f)
+    if io["status"] == 0:
+        assert info["rel_res_true"] < 2 * tol
+    solver.close()
+    return x, info, xo, io
+
+
+# ------------------------------------------------------------- block product
+@pytest.mark.parametrize("s", [1, 2, 4, 8, 16, 32])
+def test_block_product_and_gram_small(s):
+    A = W.diffusion3d(13)          # n = 2197: several tiles and a ragged tail
+    say("block product", A.n, s)
+    P = W.rng_for((70, s)).standard_normal((A.n, s))
+    solver = M.Solver.from_matrix(A)
+    Q = torch.empty((A.n, s), dtype=torch.float64, device=DEV)
+    Cm = torch.zeros((s, s), dtype=torch.float64, device=DEV)
+    solver.block_product(dev(P), Q, Cm, s, precond=M.PRECOND_JACOBI)
+    d = np.sqrt(A.to_scipy().diagonal())
+    As = W.CSR(A.n, A.rowptr, A.colind, A.vals / (d[np.repeat(np.arange(A.n), np.diff(A.rowptr))]
+                                                   * d[A.colind]))
+    Qo = O.matmul_block(As, P)
+    Co = O.gram(P, Qo)
+    Qg = Q.cpu().numpy()
+    assert np.max(np.abs(Qg - Qo)) <= 1e-14 * np.max(np.abs(Qo)) * 8
+    Cg = np.tril(Cm.cpu().numpy())
+    assert np.max(np.abs(Cg - np.tril(Co))) <= 1e-12 * np.max(np.abs(Co))
+    solver.close()
+
+
+@pytest.mark.parametrize("s", [1, 4, 16, 32])
+def test_dense_block_product(s):
+    n = 300
+    A = W.dense_spd(n, tag=(3, 40))
+    say("dense block product", n, s)
+    P = W.rng_for((71, s)).standard_normal((n, s))
+    solver = M.Solver.from_matrix(A)
+    Q = torch.empty((n, s), dtype=torch.float64, device=DEV)
+    Cm = torch.zeros((s, s), dtype=torch.float64, device=DEV)
+    solver.block_product(dev(P), Q, Cm, s, precond=M.PRECOND_NONE)
+    Qo = O.matmul_block(A, P)
+    assert np.max(np.abs(Q.cpu().numpy() - Qo)) <= 1e-13 * np.max(np.abs(Qo))
+    Co = O.gram(P, Qo)
+    assert np.max(np.abs(np.tril(Cm.cpu().numpy()) - np.tril(Co))) <= 1e-12 * np.abs(Co).max()
+    solver.close()
+
+
+def test_block_product_full_size_3d():
+    # the 128^3 diffusion operator at s = 8: every row against the oracle
+    A = W.diffusion3d(128)
+    s = 8
+    say("block product 128^3", s)
+    P = W.rng_for((72,)).standard_normal((A.n, s))
+    solver = M.Solver.from_matrix(A)
+    Q = torch.empty((A.n, s), dtype=torch.float64, device=DEV)
+    Cm = torch.zeros((s, s), dtype=torch.float64, device=DEV)
+    solver.block_product(dev(P), Q, Cm, s, precond=M.PRECOND_NONE)
+    Qo = O.matmul_block(A, P)
+    assert np.max(np.abs(Q.cpu().numpy() - Qo)) <= 1e-13 * np.max(np.abs(Qo))
+    Co = O.gram(P, Qo)
+    assert np.max(np.abs(np.tril(Cm.cpu().numpy()) - np.tril(Co))) <= 1e-11 * np.abs(Co).max()
+    solver.close()
+
+
+# ------------------------------------------------------------ whole method
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 8])
+def test_poisson2d_against_oracle(s):
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    check_against_oracle(A, b, s, seed=W.uniform_block_seed(1, s))
+
+
+@pytest.mark.parametrize("s", [1, 4, 16])
+def test_diffusion3d_against_oracle(s):
+    A = W.diffusion3d(20)
+    b = W.rhs(A.n, W.CFG_DIFFUSION3D)
+    check_against_oracle(A, b, s, seed=W.uniform_block_seed(2, s))
+
+
+@pytest.mark.parametrize("s", [1, 4, 8, 16, 32])
+def test_dense_against_oracle(s):
+    A = W.dense_spd(300, tag=(3, 41))
+    b = W.rng_for((3, 42)).standard_normal(300)
+    check_against_oracle(A, b, s, jacobi=False, seed=W.uniform_block_seed(3, s))
+
+
+def test_explicit_block_with_duplicate_columns_deflates():
+    A = W.poisson2d(16)
+    b = W.rhs(A.n, 6)
+    U = O.uniform_block(77, A.n, 4)
+    U[:, 2] = U[:, 0]
+    x, info, xo, io = check_against_oracle(A, b, 4, U=U)
+    assert info["deflations"] == io["deflations"] >= 1
+
+
+def test_s1_history_matches_oracle():
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    say("history s=1")
+    _, io, ex = O.mbpcg_solve(A, b, 1, seed=5, want_history=True)
+    solver = M.Solver.from_matrix(A)
+    _, info = solver.solve(dev(b), s=1, seed=5, history=True)
+    h = info["history"]
+    k = min(len(h), 100)
+    assert np.max(np.abs(h[:k] - ex["history"][:k]) / ex["history"][:k]) < 1e-9
+    solver.close()
+
+
+def test_cg_baseline_against_oracle():
+    A = W.poisson2d(64)
+    b = W.rhs(A.n, W.CFG_POISSON2D)
+    say("cg")
+    xo, io, ho = O.cg_cg(A, b, want_history=True)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.cg_solve(dev(b), history=True)
+    x = x.cpu().numpy()
+    assert info["iterations"] == io["iterations"]
+    assert rel(x, xo) < 1e-9
+    assert info["rel_res_true"] < 2e-8
+    assert np.max(np.abs(info["history"] - ho) / ho) < 1e-8
+    solver.close()
+
+
+def test_cg_dense_baseline():
+    A = W.dense_spd(300, tag=(3, 43))
+    b = W.rng_for((3, 44)).standard_normal(300)
+    say("cg dense")
+    xo, io, _ = O.cg_cg(A, b, jacobi=False)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.cg_solve(dev(b), precond=M.PRECOND_NONE)
+    assert info["iterations"] == io["iterations"]
+    assert rel(x.cpu().numpy(), xo) < 1e-8
+    solver.close()
+
+
+# -------------------------------------------------------------- edge cases
+def test_zero_rhs():
+    A = W.poisson2d(8)
+    say("zero rhs")
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(torch.zeros(A.n, dtype=torch.float64, device=DEV), s=4)
+    assert info["status"] == 0 and info["iterations"] == 0 and not x.any().item()
+    solver.close()
+
+
+def test_nonfinite_rhs():
+    A = W.poisson2d(8)
+    b = np.ones(A.n)
+    b[3] = np.nan
+    say("nan rhs")
+    solver = M.Solver.from_matrix(A)
+    _, info = solver.solve(dev(b), s=2)
+    assert info["status"] == M.ERR_NONFINITE
+    solver.close()
+
+
+def test_nonpositive_diagonal():
+    A = W.poisson2d(8)
+    A.vals = A.vals.copy()
+    A.vals[A.colind == 0] = -1.0
+    say("not spd")
+    solver = M.Solver.from_matrix(A)
+    _, info = solver.solve(dev(np.ones(A.n)), s=2)
+    assert info["status"] == M.ERR_NOT_SPD
+    solver.close()
+
+
+def test_max_iter_returns_best_column():
+    A = W.diffusion3d(12)
+    b = W.rhs(A.n, 5)
+    say("max_iter")
+    x, info, xo, io = check_against_oracle(A, b, 4, seed=1, max_iter=7)
+    assert info["status"] == 1 and info["iterations"] == 7 and info["used_fallback"] == 1
+
+
+def test_host_memory_path():
+    A = W.poisson2d(32)
+    b = W.rhs(A.n, 8)
+    say("host memory")
+    xo, io, _ = O.mbpcg_solve(A, b, 4, seed=2)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(b, s=4, seed=2)
+    assert isinstance(x, np.ndarray)
+    assert info["iterations"] == io["iterations"] and rel(x, xo) < 1e-10
+    solver.close()
+
+
+def test_repeat_solves_are_bitwise_identical():
+    A = W.diffusion3d(16)
+    b = W.rhs(A.n, 9)
+    say("determinism")
+    solver = M.Solver.from_matrix(A)
+    x1, i1 = solver.solve(dev(b), s=8, seed=3)
+    x2, i2 = solver.solve(dev(b), s=8, seed=3)
+    assert i1["iterations"] == i2["iterations"]
+    assert torch.equal(x1, x2)
+    solver.close()
+
+
+# ------------------------------------------------------ mixed precision (IR)
+def test_fp32_iterative_refinement_reaches_1e10():
+    n = 512
+    A = W.dense_spd(n, tag=(4, 50))
+    b = W.rng_for((4, 51)).standard_normal(n)
+    say("fp32 IR", n)
+    xs = np.linalg.solve(A, b)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(dev(b), s=8, precision=M.FP32_IR, precond=M.PRECOND_NONE,
+                           ir_tol=1e-10, inner_tol=1e-5, seed=4)
+    x = x.cpu().numpy()
+    assert info["status"] == 0, info
+    assert info["rel_res_true"] <= 1e-10
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 2e-10
+    assert rel(x, xs) <= np.linalg.cond(A) * 1e-10
+    solver.close()
+
+
+def test_bf16_iterative_refinement_reports_honestly():
+    n = 256
+    A = W.dense_spd(n, tag=(4, 52))
+    b = W.rng_for((4, 53)).standard_normal(n)
+    say("bf16 IR", n)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(dev(b), s=8, precision=M.BF16_IR, precond=M.PRECOND_NONE,
+                           ir_tol=1e-10, inner_tol=1e-2, max_outer=30, seed=4)
+    x = x.cpu().numpy()
+    truth = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    # whatever the outcome, the reported FP64 residual is the true one
+    assert abs(truth - info["rel_res_true"]) <= 1e-6 * max(truth, 1e-12) + 1e-14
+    if info["status"] == 0:
+        assert truth <= 2e-10
+    solver.close()
