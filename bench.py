@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the MBPCG hot path on one MI355X.
+
+Workload: the 3-D 7-point variable-coefficient diffusion operator on a
+128^3 grid (n = 2,097,152, nnz = 14,581,760), log-normal(sigma = 1) cell
+coefficients, b ~ N(0, 1), Jacobi (symmetric diagonal) scaling, tolerance
+1e-8 -- synthetic, seeded stand-in for the paper's sparse SPD matrices.
+
+One step = one complete solve through the C ABI: scaling, random initial
+block, the block-CG loop and the least-squares termination, with A and b
+already resident in HBM.  The metric is time-to-solution; the same solve
+with the plain Chronopoulos-Gear CG on the same GPU is timed beside it.
+
+The block-product kernel's average duration is measured with HIP events on
+the library's stream inside the timed solves (profile mode), and its
+algorithmic bytes per launch are 12 nnz + 4 (n + 1) + 16 n S (values and
+column indices, row pointers, one read of P and one write of Q, S = padded
+block width).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DEFAULT_S = 4
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_sparse.hip", "dev_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2608_07327_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(s: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "spmm_diffusion3d_128_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("per_s", {}).get(str(s))
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def cpu_baseline(A, b, s, seed, iters_gpu, budget_s):
+    """The oracle (single thread) on a bounded sample of the same solve: it is
+    run for 1, 3 and 3 + k iterations, the per-iteration time and the fixed
+    cost are fitted, and the time-to-solution is projected to the GPU's
+    iteration count."""
+    from oracle import oracle as O
+    M = O.Matrix(A)
+    t = {}
+    for it in (1, 3):
+        _, info, _ = O.mbpcg_solve(M, b, s, seed=seed, max_iter=it)
+        t[it] = info["seconds"]
+    per = max((t[3] - t[1]) / 2.0, 1e-6)
+    k = int(max(0, min(iters_gpu, (budget_s - t[1] - t[3]) / per)))
+    if k > 0:
+        _, info, _ = O.mbpcg_solve(M, b, s, seed=seed, max_iter=3 + k)
+        per = max((info["seconds"] - t[1]) / (2 + k), 1e-6)
+    fixed = max(t[1] - per, 0.0)
+    return {
+        "value": fixed + per * iters_gpu,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle MBPCG on the same 128^3 system, s={s}: runs of 1, 3 and {3 + k} "
+                   f"iterations; fixed cost {fixed:.2f} s + {per:.3f} s/iteration, projected to "
+                   f"the GPU's {iters_gpu} iterations"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--s", type=int, default=DEFAULT_S)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-sweep", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2608_07327_amd import mbpcg as M
+    from paper_2608_07327_amd import workloads as W
+
+    A = W.diffusion3d(args.grid)
+    b = W.rhs(A.n, W.CFG_DIFFUSION3D)
+    s = args.s
+    S = 1
+    while S < s:
+        S *= 2
+    seed = W.uniform_block_seed(W.CFG_DIFFUSION3D, s)
+    dev = torch.device("cuda:0")
+    solver = M.Solver.from_matrix(A)
+    bd = torch.as_tensor(b, device=dev)
+    x = torch.empty_like(bd)
+
+    def run(fn, **kw):
+        _, info = fn(bd, x=x, **kw)
+        if info["status"] != 0:
+            raise RuntimeError(f"solve failed: {info}")
+        return info
+
+    for _ in range(args.warmup):
+        run(solver.solve, s=s, seed=seed, profile=1)
+        run(solver.cg_solve, profile=1)
+
+    # timed region: MBPCG solves
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [run(solver.solve, s=s, seed=seed, profile=1) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+
+    # same system with plain CG
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    cg_infos = [run(solver.cg_solve, profile=1) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    c1 = time.perf_counter()
+    cg_sec = (c1 - c0) / args.steps
+
+    # graph-mode (no per-kernel events) time of the same solve, for reference
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(args.steps):
+        run(solver.solve, s=s, seed=seed)
+    torch.cuda.synchronize()
+    sec_graph = (time.perf_counter() - g0) / args.steps
+
+    spmm_ms = sum(i["ms_spmm"] for i in infos) / max(1, sum(i["spmm_launches"] for i in infos))
+    bytes_alg = 12 * A.nnz + 4 * (A.n + 1) + 16 * A.n * S
+    achieved = bytes_alg / (spmm_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(S)
+    it = infos[-1]["iterations"]
+    phases = [v / max(1, it) for v in infos[-1]["ms_phase"][:5]]
+
+    sweep = None
+    if not args.no_sweep:
+        sweep = {}
+        for sw in (1, 2, 4, 8, 16):
+            inf = run(solver.solve, s=sw, seed=W.uniform_block_seed(W.CFG_DIFFUSION3D, sw),
+                      profile=1)
+            Sw = 1
+            while Sw < sw:
+                Sw *= 2
+            ms = inf["ms_spmm"] / max(1, inf["spmm_launches"])
+            sweep[str(sw)] = {
+                "iterations": inf["iterations"],
+                "seconds": round(inf["ms_total"] / 1e3, 5),
+                "ms_per_iter": round(inf["ms_per_iter"], 4),
+                "spmm_ms": round(ms, 5),
+                "spmm_GBps": round((12 * A.nnz + 4 * (A.n + 1) + 16 * A.n * Sw) / (ms * 1e-3) / 1e9, 1),
+                "rel_res_true": inf["rel_res_true"],
+            }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(A, b, s, seed, it, args.cpu_seconds)
+
+    out = {
+        "metric": "time-to-solution at rel.res 1e-8 (MBPCG; plain CG on the same GPU beside it)",
+        "value": round(sec, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"diffusion3d {args.grid}^3 7-point, lognormal(sigma=1) coefficients, "
+                        f"b~N(0,1), Jacobi scaling, tol 1e-8, MBPCG s={s}",
+            "n": A.n, "nnz": A.nnz, "s": s,
+        },
+        "iterations": it,
+        "rel_res_true": infos[-1]["rel_res_true"],
+        "cg_seconds": round(cg_sec, 6),
+        "cg_iterations": cg_infos[-1]["iterations"],
+        "speedup_vs_cg": round(cg_sec / sec, 4),
+        "seconds_graph_mode": round(sec_graph, 6),
+        "ms_per_iter_phases": dict(zip(["product", "xi", "update", "qr", "dir"],
+                                       [round(v, 4) for v in phases])),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": f"k_spmm<S={S}> (block product + Gram epilogue)",
+            "avg_ms": round(spmm_ms, 5),
+            "bytes_per_launch": bytes_alg,
+        },
+        "cpu_baseline": cpu,
+        "sweep": sweep,
+    }
+    solver.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -90,6 +90,8 @@ typedef struct {
     double ms_spmm;            /* profile mode: summed time of the block product       */
     int64_t spmm_launches;     /* profile mode: number of block-product launches       */
     double ms_phase[8];        /* profile mode: product, Xi, updates, QR, P, LS, setup, other */
+    int32_t status;            /* mbpcg_status of this solve (per system in a batch)   */
+    int32_t reserved;
 } mbpcg_info;
 
 /* Fill *p with defaults: s=4, tol=1e-8, tol_initial=0, max_iter=100000,

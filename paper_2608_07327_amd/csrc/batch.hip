@@ -1,15 +1,997 @@
-// Batched solve of many independent systems (placeholder until the
-// persistent batched kernel lands).
+// Batched MBPCG: many independent sparse SPD systems of uneven n and block
+// width s (1..8) solved together by ONE persistent kernel, launched through a
+// hipGraph.  The kernel walks the whole of Algorithm 1 -- scaling, initial
+// block, the iteration loop and the least-squares termination -- for every
+// system at once.  Each phase spreads its work over the grid: row phases take
+// (system, 128-row tile) items, s x s phases take one system per workgroup.
+// Phases are separated by a software grid barrier; every barrier wait is
+// bounded, so a grid that is not co-resident ends with an error instead of a
+// hang.  Systems that finish drop out of the item loops; the loop ends when
+// none is active.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
 #include <string>
+#include <vector>
 
+#include "dev_sxs.hpp"
 #include "runtime.hpp"
 
 namespace mb {
 
-mbpcg_status batch_entry(int32_t, const mbpcg_system*, const mbpcg_params&, mbpcg_info*, mbpcg_mem,
-                         hipStream_t, std::string& err) {
-    err = "batched solve not built";
-    return MBPCG_ERR_UNSUPPORTED;
+constexpr int BT = 128;        // rows per item
+constexpr int PSTRIDE = 48;    // doubles of partial sums per item
+constexpr int BSM = 3 * BT * 8 + MB_BLOCK;  // LDS doubles of the persistent kernel
+
+struct BSys {
+    int64_t n, rp_off, nz_off, vec_off, blk_off;
+    int32_t s, S, G, ntile, item_off, pad;
+};
+
+struct BCtl {
+    unsigned bar_count, bar_gen;
+    int abort, active;
+    int loops, pad0, pad1, pad2;
+};
+
+struct BArgs {
+    int nsys, total_items, max_iter, jacobi;
+    double tol, tau;
+    uint64_t seed;
+    long long spin_limit;
+    const BSys* sys;
+    DevState* st;
+    BCtl* ctl;
+    const int32_t* item_sys;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* vals;
+    double* vals_s;
+    const double* b;
+    double* x;
+    double* d;
+    double* bbar;
+    double *U, *Y, *X0, *Xt, *R, *W, *P, *Q;
+    double* part;
+};
+
+// ---------------------------------------------------------------------------
+// software grid barrier (sense by generation counter), bounded wait
+// ---------------------------------------------------------------------------
+__device__ bool grid_sync(BCtl* ctl, long long spin_limit, int* flag) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned nb = gridDim.x;
+        const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nb - 1) {
+            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long spins = 0;
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(8);
+                if (++spins > spin_limit) {
+                    __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            }
+        }
+        *flag = __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    __threadfence();
+    const int ab = *flag;
+    __syncthreads();
+    return ab == 0;
+}
+
+// block-wide fixed-order sum of one value per thread (result valid in thread 0)
+__device__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < MB_BLOCK; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+struct Item {
+    int sys;
+    int64_t r0;
+    int rows;
+};
+
+__device__ __forceinline__ Item item_of(const BArgs& a, int it) {
+    Item m;
+    m.sys = a.item_sys[it];
+    const BSys& y = a.sys[m.sys];
+    m.r0 = (int64_t)(it - y.item_off) * BT;
+    m.rows = (int)min((int64_t)BT, y.n - m.r0);
+    return m;
+}
+
+#define FOR_ITEMS for (int it_ = blockIdx.x; it_ < a.total_items; it_ += gridDim.x)
+#define FOR_SYS for (int sy_ = blockIdx.x; sy_ < a.nsys; sy_ += gridDim.x)
+#define DISPATCH_S(Sv, CALL)                          \
+    switch (Sv) {                                     \
+        case 1: { constexpr int SS = 1; CALL; } break; \
+        case 2: { constexpr int SS = 2; CALL; } break; \
+        case 4: { constexpr int SS = 4; CALL; } break; \
+        case 8: { constexpr int SS = 8; CALL; } break; \
+    }
+
+// ---------------------------------------------------------------------------
+// row phases (one 128-row tile of one system)
+// ---------------------------------------------------------------------------
+// D = diag(sqrt(a_jj)) (Sec. 1), b~ = D^-1 b, partial ||b||^2 and ||b~||^2
+__device__ void ph_diag(const BArgs& a, const Item& m, double* sm) {
+    const BSys& y = a.sys[m.sys];
+    DevState* st = a.st + m.sys;
+    const int32_t* rp = a.rowptr + y.rp_off;
+    const int32_t* ci = a.colind + y.nz_off;
+    const double* va = a.vals + y.nz_off;
+    double s0 = 0.0, s1 = 0.0;
+    for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK) {
+        const int64_t r = m.r0 + rl;
+        double diag = 0.0;
+        for (int k = rp[r]; k < rp[r + 1]; ++k)
+            if (ci[k] == r) diag += va[k];
+        double dr = 1.0;
+        if (a.jacobi) {
+            if (!(diag > 0.0) || !finite_d(diag)) st->done = DONE_NOTSPD;
+            else dr = sqrt(diag);
+        }
+        a.d[y.vec_off + r] = dr;
+        const double bv = a.b[y.vec_off + r];
+        const double bb = bv / dr;
+        a.bbar[y.vec_off + r] = bb;
+        s0 += bv * bv;
+        s1 += bb * bb;
+    }
+    const int64_t it = y.item_off + m.r0 / BT;
+    const double t0 = block_sum(s0, sm);
+    const double t1 = block_sum(s1, sm);
+    if (threadIdx.x == 0) {
+        a.part[it * PSTRIDE + 0] = t0;
+        a.part[it * PSTRIDE + 1] = t1;
+    }
+}
+
+__device__ __forceinline__ uint64_t splitmix64_at_b(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// scaled values a_rc / (d_r d_c) and the Uniform(-1,1) block U (Alg. 1, line U)
+template <int S>
+__device__ void ph_scale_u(const BArgs& a, const Item& m) {
+    const BSys& y = a.sys[m.sys];
+    const int32_t* rp = a.rowptr + y.rp_off;
+    const int32_t* ci = a.colind + y.nz_off;
+    const double* va = a.vals + y.nz_off;
+    double* vs = a.vals_s + y.nz_off;
+    const double* d = a.d + y.vec_off;
+    for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK) {
+        const int64_t r = m.r0 + rl;
+        const double dr = d[r];
+        for (int k = rp[r]; k < rp[r + 1]; ++k) vs[k] = va[k] / (dr * d[ci[k]]);
+    }
+    const uint64_t seed = a.seed + (uint64_t)m.sys;
+    double* U = a.U + y.blk_off;
+    for (int e = threadIdx.x; e < m.rows * S; e += MB_BLOCK) {
+        const int64_t r = m.r0 + e / S;
+        const int j = e % S;
+        double v = 0.0;
+        if (j < y.s) {
+            const uint64_t z = splitmix64_at_b(seed, (uint64_t)j * (uint64_t)y.n + (uint64_t)r);
+            v = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+        }
+        U[r * S + j] = v;
+    }
+}
+
+// Q = A~ P for the tile (lanes per row G); optional lower-triangle Gram P^T Q
+// into part[0..E) and/or sum of Q^2 into part[2]
+template <int S, int G>
+__device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double* Qb, bool gram,
+                        bool qsq, double* sm) {
+    constexpr int RPP = MB_BLOCK / G;
+    constexpr int PASSES = (BT + RPP - 1) / RPP;
+    constexpr int SLOTS = G / S;
+    constexpr int E = tri_count(S);
+    const BSys& y = a.sys[m.sys];
+    const int32_t* rp = a.rowptr + y.rp_off;
+    const int32_t* ci = a.colind + y.nz_off;
+    const double* va = a.vals_s + y.nz_off;
+    const double* P = Pb + y.blk_off;
+    double* Q = Qb + y.blk_off;
+    double* sP = sm;
+    double* sQ = sm + BT * S;
+    double* red = sm + 2 * BT * S;
+    const int tid = threadIdx.x;
+    const int grp = tid / G, lane = tid % G, slot = lane / S, j = lane % S;
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+        const int rl = p * RPP + grp;
+        double acc = 0.0;
+        if (rl < m.rows) {
+            const int64_t r = m.r0 + rl;
+            const int kb = rp[r], ke = rp[r + 1];
+            for (int k = kb + slot; k < ke; k += SLOTS) acc += va[k] * P[(int64_t)ci[k] * S + j];
+        }
+#pragma unroll
+        for (int off = S; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        if (slot == 0 && rl < BT) sQ[rl * S + j] = acc;
+    }
+    if (gram)
+        for (int e = tid; e < BT * S; e += MB_BLOCK) sP[e] = e < m.rows * S ? P[m.r0 * S + e] : 0.0;
+    __syncthreads();
+    double q2 = 0.0;
+    for (int e = tid; e < m.rows * S; e += MB_BLOCK) {
+        const double q = sQ[e];
+        Q[m.r0 * S + e] = q;
+        q2 += q * q;
+    }
+    const int64_t it = y.item_off + m.r0 / BT;
+    double* out = a.part + it * PSTRIDE;
+    if (gram) {
+        TileSums<E> gs;
+        gs.init();
+        int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+        for (int k = 0; k < TileSums<E>::EPT; ++k) {
+            gi[k] = gj[k] = 0;
+            if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+        }
+        gs.add_rows(m.rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
+        gs.finish(red, out);
+    }
+    if (qsq) {
+        const double t = block_sum(q2, red);
+        if (tid == 0) out[2] = t;
+    }
+    __syncthreads();
+}
+
+template <int S>
+__device__ void ph_spmm_dispatch(const BArgs& a, const Item& m, const double* P, double* Q,
+                                 bool gram, bool qsq, double* sm) {
+    const int G = a.sys[m.sys].G;
+    switch (G) {
+#define BG(g) \
+    case g:   \
+        if constexpr (g >= S) ph_spmm<S, g>(a, m, P, Q, gram, qsq, sm); \
+        break;
+        BG(1) BG(2) BG(4) BG(8) BG(16) BG(32) BG(64)
+#undef BG
+    }
+}
+
+// X0 = gamma U, X~ = 0, R = B~ - gamma Y; Gram of R and nu (setup QR partials)
+template <int S>
+__device__ void ph_init(const BArgs& a, const Item& m, double* sm) {
+    constexpr int E = tri_count(S);
+    const BSys& y = a.sys[m.sys];
+    const DevState* st = a.st + m.sys;
+    const double g = st->gamma;
+    double* sR = sm;
+    double* red = sm + BT * S;
+    const int64_t base = y.blk_off + m.r0 * S;
+    const double* bb = a.bbar + y.vec_off + m.r0;
+    const double* d = a.d + y.vec_off + m.r0;
+    const int t = threadIdx.x;
+    for (int e = t; e < BT * S; e += MB_BLOCK) {
+        double r = 0.0;
+        if (e < m.rows * S) {
+            const int j = e % S;
+            a.X0[base + e] = g * a.U[base + e];
+            a.Xt[base + e] = 0.0;
+            r = j < y.s ? bb[e / S] - g * a.Y[base + e] : 0.0;
+            a.R[base + e] = r;
+        }
+        sR[e] = r;
+    }
+    __syncthreads();
+    TileSums<E> gs;
+    gs.init();
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+        gi[k] = gj[k] = 0;
+        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+    }
+    gs.add_rows(m.rows, [&](int k, int r) { return sR[r * S + gi[k]] * sR[r * S + gj[k]]; });
+    const int64_t it = y.item_off + m.r0 / BT;
+    double* out = a.part + it * PSTRIDE;
+    gs.finish(red, out);
+    for (int j = 0; j < S; ++j) {
+        double v = 0.0;
+        for (int rl = t; rl < m.rows; rl += MB_BLOCK) {
+            const double w = d[rl] * sR[rl * S + j];
+            v += w * w;
+        }
+        const double tot = block_sum(v, red);
+        if (t == 0) out[E + j] = tot;
+    }
+    __syncthreads();
+}
+
+// lines tilde_X, R and V = W - Q Xi, with Gram of V and nu partials
+template <int S>
+__device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
+    constexpr int RPP = MB_BLOCK / S;
+    constexpr int E = tri_count(S);
+    const BSys& y = a.sys[m.sys];
+    const DevState* st = a.st + m.sys;
+    double* sP = sm;
+    double* sQ = sm + BT * S;
+    double* sV = sm + 2 * BT * S;
+    double* red = sm + 3 * BT * S;
+    const int t = threadIdx.x, j = t % S, rl0 = t / S;
+    double al[S], xi[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        al[l] = st->alpha[l * MB_SM + j];
+        xi[l] = st->Xi[l * MB_SM + j];
+    }
+    const int64_t base = y.blk_off + m.r0 * S;
+    for (int e = t; e < BT * S; e += MB_BLOCK) {
+        const bool in = e < m.rows * S;
+        sP[e] = in ? a.P[base + e] : 0.0;
+        sQ[e] = in ? a.Q[base + e] : 0.0;
+    }
+    __syncthreads();
+    const double* d = a.d + y.vec_off + m.r0;
+    double nu = 0.0;
+    for (int rl = rl0; rl < BT; rl += RPP) {
+        double v = 0.0;
+        if (rl < m.rows) {
+            const int64_t g = base + rl * S + j;
+            double tx = 0.0, tr = 0.0, tv = 0.0;
+#pragma unroll
+            for (int l = 0; l < S; ++l) {
+                const double p = sP[rl * S + l], q = sQ[rl * S + l];
+                tx += p * al[l];
+                tr += q * al[l];
+                tv += q * xi[l];
+            }
+            const double xn = a.Xt[g] + tx;
+            const double rn = a.R[g] - tr;
+            v = a.W[g] - tv;
+            a.Xt[g] = xn;
+            a.R[g] = rn;
+            a.W[g] = v;
+            const double dr = d[rl] * rn;
+            nu += dr * dr;
+        }
+        if (rl < BT) sV[rl * S + j] = v;
+    }
+    __syncthreads();
+    TileSums<E> gs;
+    gs.init();
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+        gi[k] = gj[k] = 0;
+        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+    }
+    gs.add_rows(m.rows, [&](int k, int r) { return sV[r * S + gi[k]] * sV[r * S + gj[k]]; });
+    const int64_t it = y.item_off + m.r0 / BT;
+    double* out = a.part + it * PSTRIDE;
+    gs.finish(red, out);
+    red[t] = nu;
+    __syncthreads();
+    if (t < S) {
+        double s = 0.0;
+        for (int q = 0; q < RPP; ++q) s += red[t + q * S];
+        out[E + t] = s;
+    }
+    __syncthreads();
+}
+
+// W = V M, P = W + P Z^T (FIRST: P = W, V read from R)
+template <int S, int FIRST>
+__device__ void ph_dir(const BArgs& a, const Item& m, double* sm) {
+    constexpr int RPP = MB_BLOCK / S;
+    const BSys& y = a.sys[m.sys];
+    const DevState* st = a.st + m.sys;
+    double* sV = sm;
+    double* sP = sm + BT * S;
+    const int t = threadIdx.x, j = t % S, rl0 = t / S;
+    double mm[S], z[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        mm[l] = st->M[l * MB_SM + j];
+        z[l] = st->Z[j * MB_SM + l];
+    }
+    const int64_t base = y.blk_off + m.r0 * S;
+    const double* V = FIRST ? a.R : a.W;
+    for (int e = t; e < BT * S; e += MB_BLOCK) {
+        const bool in = e < m.rows * S;
+        sV[e] = in ? V[base + e] : 0.0;
+        if (!FIRST) sP[e] = in ? a.P[base + e] : 0.0;
+    }
+    __syncthreads();
+    for (int rl = rl0; rl < m.rows; rl += RPP) {
+        double w = 0.0;
+#pragma unroll
+        for (int l = 0; l < S; ++l) w += sV[rl * S + l] * mm[l];
+        double p = w;
+        if (!FIRST) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < S; ++l) acc += sP[rl * S + l] * z[l];
+            p = w + acc;
+        }
+        a.W[base + rl * S + j] = w;
+        a.P[base + rl * S + j] = p;
+    }
+    __syncthreads();
+}
+
+// Gram of [b, D R] for the least-squares termination
+template <int S>
+__device__ void ph_ls_gram(const BArgs& a, const Item& m, double* sm) {
+    constexpr int NC = S + 1;
+    constexpr int E = tri_count(NC);
+    const BSys& y = a.sys[m.sys];
+    double* sM = sm;
+    double* red = sm + BT * NC;
+    const int t = threadIdx.x;
+    const int64_t base = y.blk_off + m.r0 * S;
+    const double* d = a.d + y.vec_off + m.r0;
+    const double* b = a.b + y.vec_off + m.r0;
+    for (int e = t; e < BT * S; e += MB_BLOCK) {
+        const int rl = e / S, j = e % S;
+        sM[rl * NC + 1 + j] = rl < m.rows ? d[rl] * a.R[base + e] : 0.0;
+    }
+    for (int rl = t; rl < BT; rl += MB_BLOCK) sM[rl * NC] = rl < m.rows ? b[rl] : 0.0;
+    __syncthreads();
+    TileSums<E> gs;
+    gs.init();
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+#pragma unroll
+    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+        gi[k] = gj[k] = 0;
+        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+    }
+    gs.add_rows(m.rows, [&](int k, int r) { return sM[r * NC + gi[k]] * sM[r * NC + gj[k]]; });
+    const int64_t it = y.item_off + m.r0 / BT;
+    gs.finish(red, a.part + it * PSTRIDE);
+    __syncthreads();
+}
+
+// x = D^-1 (X~ + X0) c, r = y0 b + (D R) c, partial ||r||^2 into part[0]
+template <int S>
+__device__ void ph_ls_apply(const BArgs& a, const Item& m, double* sm) {
+    const BSys& y = a.sys[m.sys];
+    const DevState* st = a.st + m.sys;
+    const int64_t base = y.blk_off + m.r0 * S;
+    const double* d = a.d + y.vec_off + m.r0;
+    const double* b = a.b + y.vec_off + m.r0;
+    double* x = a.x + y.vec_off + m.r0;
+    double c[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) c[j] = st->chat[j];
+    const double y0 = st->y0;
+    double s2 = 0.0;
+    for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK) {
+        double ax = 0.0, ar = 0.0;
+        const double dr = d[rl];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            ax += (a.Xt[base + rl * S + j] + a.X0[base + rl * S + j]) * c[j];
+            ar += (dr * a.R[base + rl * S + j]) * c[j];
+        }
+        x[rl] = ax / dr;
+        const double res = y0 * b[rl] + ar;
+        s2 += res * res;
+    }
+    const int64_t it = y.item_off + m.r0 / BT;
+    const double tot = block_sum(s2, sm);
+    if (threadIdx.x == 0) a.part[it * PSTRIDE + 0] = tot;
+}
+
+// best column when the combination was not accepted; x = 0 for b = 0
+template <int S>
+__device__ void ph_select(const BArgs& a, const Item& m) {
+    const BSys& y = a.sys[m.sys];
+    const DevState* st = a.st + m.sys;
+    double* x = a.x + y.vec_off + m.r0;
+    if (st->done == DONE_ZERO_RHS || !st->ready) {
+        for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK) x[rl] = 0.0;
+        return;
+    }
+    if (st->accepted) return;
+    const int h = st->h;
+    const int64_t base = y.blk_off + m.r0 * S;
+    const double* d = a.d + y.vec_off + m.r0;
+    for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK)
+        x[rl] = (a.Xt[base + rl * S + h] + a.X0[base + rl * S + h]) / d[rl];
+}
+
+// ||b - A x||^2 partial on the original values into part[1]
+__device__ void ph_resid(const BArgs& a, const Item& m, double* sm) {
+    const BSys& y = a.sys[m.sys];
+    const int32_t* rp = a.rowptr + y.rp_off;
+    const int32_t* ci = a.colind + y.nz_off;
+    const double* va = a.vals + y.nz_off;
+    const double* x = a.x + y.vec_off;
+    const double* b = a.b + y.vec_off;
+    double s2 = 0.0;
+    for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK) {
+        const int64_t r = m.r0 + rl;
+        double acc = 0.0;
+        for (int k = rp[r]; k < rp[r + 1]; ++k) acc += va[k] * x[ci[k]];
+        const double e = b[r] - acc;
+        s2 += e * e;
+    }
+    const int64_t it = y.item_off + m.r0 / BT;
+    const double tot = block_sum(s2, sm);
+    if (threadIdx.x == 0) a.part[it * PSTRIDE + 1] = tot;
+}
+
+// sum of part[slot] over a system's items (fixed order), result to thread 0
+__device__ double sys_sum(const BArgs& a, const BSys& y, int slot, double* sm) {
+    reduce_partials(a.part + (int64_t)y.item_off * PSTRIDE + slot, y.ntile, 1, PSTRIDE, sm,
+                    sm + 8);
+    return sm[0];
+}
+
+// ---------------------------------------------------------------------------
+// the persistent kernel
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
+    __shared__ double sm[BSM];
+    __shared__ int smi[48];
+    int* flag = smi + 40;
+    BCtl* ctl = a.ctl;
+#define SYNC_OR_QUIT \
+    if (!grid_sync(ctl, a.spin_limit, flag)) return;
+
+    // --- setup: scaling, b~, ||b||
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        ph_diag(a, m, sm);
+    }
+    SYNC_OR_QUIT
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        DISPATCH_S(a.sys[m.sys].S, ph_scale_u<SS>(a, m))
+    }
+    SYNC_OR_QUIT
+    // line X^0: Y = A~ U and ||Y||_F^2
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(a, m, a.U, a.Y, false, true, sm))
+    }
+    SYNC_OR_QUIT
+    FOR_SYS {
+        const BSys& y = a.sys[sy_];
+        DevState* st = a.st + sy_;
+        const double sb = sys_sum(a, y, 0, sm);
+        __syncthreads();
+        const double sbb = sys_sum(a, y, 1, sm);
+        __syncthreads();
+        const double sy = sys_sum(a, y, 2, sm);
+        if (threadIdx.x == 0) {
+            const double bn = sqrt(sb);
+            st->bnorm = bn;
+            st->bbar_norm = sqrt(sbb);
+            if (!finite_d(bn)) st->done = DONE_NONFINITE;
+            else if (bn == 0.0) st->done = DONE_ZERO_RHS;
+            else if (!st->done) {
+                const double g = sqrt((double)y.s * sbb) / sqrt(sy);
+                st->gamma = g;
+                if (!finite_d(g)) st->done = DONE_NONFINITE;
+            }
+        }
+        __syncthreads();
+    }
+    SYNC_OR_QUIT
+    // lines tilde_B .. R^0 and the partials of the first QR
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        if (a.st[m.sys].done) continue;
+        DISPATCH_S(a.sys[m.sys].S, ph_init<SS>(a, m, sm))
+    }
+    SYNC_OR_QUIT
+    FOR_SYS {
+        const BSys& y = a.sys[sy_];
+        DevState* st = a.st + sy_;
+        if (st->done) continue;
+        DISPATCH_S(y.S, tail_qr_body<SS>(a.part + (int64_t)y.item_off * PSTRIDE, y.ntile, PSTRIDE,
+                                         st, nullptr, 1, sm, smi))
+        __syncthreads();
+    }
+    SYNC_OR_QUIT
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        if (a.st[m.sys].done) continue;
+        DISPATCH_S(a.sys[m.sys].S, (ph_dir<SS, 1>(a, m, sm)))
+    }
+    FOR_SYS {
+        if (threadIdx.x == 0 && !a.st[sy_].done)
+            __hip_atomic_fetch_add(&ctl->active, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    SYNC_OR_QUIT
+
+    // --- the iteration loop (lines Xi .. Sigma) for every active system
+    for (int loop = 0; loop <= a.max_iter + 1; ++loop) {
+        FOR_ITEMS {
+            const Item m = item_of(a, it_);
+            if (a.st[m.sys].done) continue;
+            DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(a, m, a.P, a.Q, true, false, sm))
+        }
+        SYNC_OR_QUIT
+        FOR_SYS {
+            const BSys& y = a.sys[sy_];
+            DevState* st = a.st + sy_;
+            if (st->done) continue;
+            DISPATCH_S(y.S, tail_xi_body<SS>(a.part + (int64_t)y.item_off * PSTRIDE, y.ntile,
+                                             PSTRIDE, st, sm, smi))
+            __syncthreads();
+            if (threadIdx.x == 0 && st->done)
+                __hip_atomic_fetch_add(&ctl->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+        }
+        SYNC_OR_QUIT
+        FOR_ITEMS {
+            const Item m = item_of(a, it_);
+            if (a.st[m.sys].done) continue;
+            DISPATCH_S(a.sys[m.sys].S, ph_update<SS>(a, m, sm))
+        }
+        SYNC_OR_QUIT
+        FOR_SYS {
+            const BSys& y = a.sys[sy_];
+            DevState* st = a.st + sy_;
+            if (st->done) continue;
+            int fin = 0;
+            DISPATCH_S(y.S, fin = tail_qr_body<SS>(a.part + (int64_t)y.item_off * PSTRIDE, y.ntile,
+                                                   PSTRIDE, st, nullptr, 0, sm, smi))
+            __syncthreads();
+            if (threadIdx.x == 0 && fin)
+                __hip_atomic_fetch_add(&ctl->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+        }
+        SYNC_OR_QUIT
+        if (threadIdx.x == 0)
+            flag[1] = __hip_atomic_load(&ctl->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int still = flag[1];
+        __syncthreads();
+        if (still <= 0) break;
+        FOR_ITEMS {
+            const Item m = item_of(a, it_);
+            if (a.st[m.sys].done) continue;
+            DISPATCH_S(a.sys[m.sys].S, (ph_dir<SS, 0>(a, m, sm)))
+        }
+        SYNC_OR_QUIT
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->loops = loop + 1;
+    }
+
+    // --- termination (lines hat_B .. x)
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        if (a.st[m.sys].done != DONE_CONVERGED) continue;
+        DISPATCH_S(a.sys[m.sys].S, ph_ls_gram<SS>(a, m, sm))
+    }
+    SYNC_OR_QUIT
+    FOR_SYS {
+        const BSys& y = a.sys[sy_];
+        DevState* st = a.st + sy_;
+        if (st->done != DONE_CONVERGED) continue;
+        DISPATCH_S(y.S, tail_ls_body<SS>(a.part + (int64_t)y.item_off * PSTRIDE, y.ntile, PSTRIDE,
+                                         st, sm, smi))
+        __syncthreads();
+    }
+    SYNC_OR_QUIT
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        if (a.st[m.sys].done != DONE_CONVERGED) continue;
+        DISPATCH_S(a.sys[m.sys].S, ph_ls_apply<SS>(a, m, sm))
+    }
+    SYNC_OR_QUIT
+    FOR_SYS {
+        const BSys& y = a.sys[sy_];
+        DevState* st = a.st + sy_;
+        if (st->done != DONE_CONVERGED) {
+            if (threadIdx.x == 0) st->accepted = 0;
+            continue;
+        }
+        const double s2 = sys_sum(a, y, 0, sm);
+        if (threadIdx.x == 0) {
+            const double rel = sqrt(s2) / st->bnorm;
+            st->rel_ls = rel;
+            st->accepted = st->ls_ok && finite_d(rel) && rel < st->tol;
+        }
+        __syncthreads();
+    }
+    SYNC_OR_QUIT
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        DISPATCH_S(a.sys[m.sys].S, ph_select<SS>(a, m))
+    }
+    SYNC_OR_QUIT
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        ph_resid(a, m, sm);
+    }
+    SYNC_OR_QUIT
+    FOR_SYS {
+        const BSys& y = a.sys[sy_];
+        DevState* st = a.st + sy_;
+        const double s2 = sys_sum(a, y, 1, sm);
+        if (threadIdx.x == 0) st->rel_true = st->done == DONE_ZERO_RHS ? 0.0 : sqrt(s2) / st->bnorm;
+        __syncthreads();
+    }
+#undef SYNC_OR_QUIT
+}
+
+__global__ void k_batch_state_init(int nsys, DevState* st, const BSys* sys, int max_iter,
+                                   double tol, double tau) {
+    const int i = blockIdx.x;
+    if (i >= nsys) return;
+    DevState* s = st + i;
+    double* raw = reinterpret_cast<double*>(s);
+    const int nd = (int)(sizeof(DevState) / sizeof(double));
+    for (int e = threadIdx.x; e < nd; e += blockDim.x) raw[e] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s->s = sys[i].s;
+        s->max_iter = max_iter;
+        s->tol = tol;
+        s->tol0 = tol;
+        s->tau = tau;
+        s->width = sys[i].s;
+    }
+    if (threadIdx.x < MB_SM) s->active[threadIdx.x] = threadIdx.x < sys[i].s;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct BatchBufs {
+    std::vector<void*> ptrs;
+    ~BatchBufs() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    hipError_t alloc(T** p, size_t count) {
+        hipError_t e = hipMalloc((void**)p, sizeof(T) * std::max<size_t>(count, 1));
+        if (e == hipSuccess) ptrs.push_back((void*)*p);
+        return e;
+    }
+};
+
+int batch_default_G(int S) { return spmm_default_G(S); }
+
+mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_params& p,
+                         mbpcg_info* per_system, mbpcg_mem mem, hipStream_t user_stream,
+                         std::string& err) {
+#define BCK(expr)                                                              \
+    do {                                                                       \
+        hipError_t _e = (expr);                                                \
+        if (_e != hipSuccess) {                                                \
+            err = std::string(#expr) + ": " + hipGetErrorString(_e);          \
+            return _e == hipErrorOutOfMemory ? MBPCG_ERR_OOM : MBPCG_ERR_HIP;  \
+        }                                                                      \
+    } while (0)
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<BSys> hs(nsys);
+    std::vector<int32_t> item_sys;
+    int64_t rp = 0, nz = 0, vec = 0, blk = 0;
+    int items = 0;
+    for (int i = 0; i < nsys; ++i) {
+        const mbpcg_system& y = systems[i];
+        BSys& b = hs[i];
+        b.n = y.n;
+        b.rp_off = rp;
+        b.nz_off = nz;
+        b.vec_off = vec;
+        b.blk_off = blk;
+        b.s = y.s;
+        b.S = padded_width(y.s);
+        b.G = batch_default_G(b.S);
+        b.ntile = (int)((y.n + BT - 1) / BT);
+        b.item_off = items;
+        b.pad = 0;
+        for (int t = 0; t < b.ntile; ++t) item_sys.push_back(i);
+        items += b.ntile;
+        rp += y.n + 1;
+        nz += y.nnz;
+        vec += y.n;
+        blk += y.n * b.S;
+    }
+    if (items >= INT32_MAX / 2) {
+        err = "batch too large";
+        return MBPCG_ERR_UNSUPPORTED;
+    }
+    int dev = 0;
+    BCK(hipGetDevice(&dev));
+    hipStream_t stream = nullptr;
+    BCK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } sg{stream};
+    hipEvent_t ev = nullptr;
+    BCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    struct EventGuard {
+        hipEvent_t e;
+        ~EventGuard() { (void)hipEventDestroy(e); }
+    } eg{ev};
+    BCK(hipEventRecord(ev, user_stream));
+    BCK(hipStreamWaitEvent(stream, ev, 0));
+
+    BatchBufs B;
+    BArgs a;
+    memset(&a, 0, sizeof(a));
+    int32_t *d_rp, *d_ci, *d_items;
+    double *d_va, *d_vs, *d_b, *d_x, *d_d, *d_bb;
+    BSys* d_sys;
+    DevState* d_st;
+    BCtl* d_ctl;
+    BCK(B.alloc(&d_rp, rp));
+    BCK(B.alloc(&d_ci, nz));
+    BCK(B.alloc(&d_va, nz));
+    BCK(B.alloc(&d_vs, nz));
+    BCK(B.alloc(&d_b, vec));
+    BCK(B.alloc(&d_x, vec));
+    BCK(B.alloc(&d_d, vec));
+    BCK(B.alloc(&d_bb, vec));
+    BCK(B.alloc(&d_items, items));
+    BCK(B.alloc(&d_sys, nsys));
+    BCK(B.alloc(&d_st, nsys));
+    BCK(B.alloc(&d_ctl, 1));
+    double* blocks[8];
+    for (auto& q : blocks) BCK(B.alloc(&q, blk));
+    double* d_part;
+    BCK(B.alloc(&d_part, (size_t)items * PSTRIDE));
+
+    const hipMemcpyKind kind = mem == MBPCG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    for (int i = 0; i < nsys; ++i) {
+        const mbpcg_system& y = systems[i];
+        const BSys& b = hs[i];
+        BCK(hipMemcpyAsync(d_rp + b.rp_off, y.rowptr, sizeof(int32_t) * (y.n + 1), kind, stream));
+        if (y.nnz > 0) {
+            BCK(hipMemcpyAsync(d_ci + b.nz_off, y.colind, sizeof(int32_t) * y.nnz, kind, stream));
+            BCK(hipMemcpyAsync(d_va + b.nz_off, y.vals, sizeof(double) * y.nnz, kind, stream));
+        }
+        BCK(hipMemcpyAsync(d_b + b.vec_off, y.b, sizeof(double) * y.n, kind, stream));
+    }
+    BCK(hipMemcpyAsync(d_items, item_sys.data(), sizeof(int32_t) * items, hipMemcpyHostToDevice,
+                       stream));
+    BCK(hipMemcpyAsync(d_sys, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, stream));
+    BCK(hipMemsetAsync(d_ctl, 0, sizeof(BCtl), stream));
+    hipLaunchKernelGGL(k_batch_state_init, dim3(nsys), dim3(MB_BLOCK), 0, stream, nsys, d_st, d_sys,
+                       (int)p.max_iter, p.tol, p.tau > 0 ? p.tau : 1e-12);
+    BCK(hipGetLastError());
+
+    a.nsys = nsys;
+    a.total_items = items;
+    a.max_iter = (int)p.max_iter;
+    a.jacobi = p.precond == MBPCG_PRECOND_JACOBI;
+    a.tol = p.tol;
+    a.tau = p.tau > 0 ? p.tau : 1e-12;
+    a.seed = p.seed;
+    a.spin_limit = 1ll << 24;
+    a.sys = d_sys;
+    a.st = d_st;
+    a.ctl = d_ctl;
+    a.item_sys = d_items;
+    a.rowptr = d_rp;
+    a.colind = d_ci;
+    a.vals = d_va;
+    a.vals_s = d_vs;
+    a.b = d_b;
+    a.x = d_x;
+    a.d = d_d;
+    a.bbar = d_bb;
+    a.U = blocks[0];
+    a.Y = blocks[1];
+    a.X0 = blocks[2];
+    a.Xt = blocks[3];
+    a.R = blocks[4];
+    a.W = blocks[5];
+    a.P = blocks[6];
+    a.Q = blocks[7];
+    a.part = d_part;
+
+    // grid: every workgroup co-resident (the barrier needs it)
+    int per_cu = 0, cus = 0;
+    BCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, MB_BLOCK, 0));
+    BCK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (per_cu < 1) {
+        err = "batched kernel does not fit on a compute unit";
+        return MBPCG_ERR_HIP;
+    }
+    const int grid = std::max(1, std::min(items, per_cu * cus));
+
+    // one persistent kernel, captured in a graph and launched once
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BCK(hipStreamSynchronize(stream));
+    BCK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(MB_BLOCK), 0, stream, a);
+    hipError_t le = hipGetLastError();
+    hipError_t ce = hipStreamEndCapture(stream, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        err = std::string("capture of the batched kernel failed: ") +
+              hipGetErrorString(le != hipSuccess ? le : ce);
+        return MBPCG_ERR_HIP;
+    }
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        err = std::string("instantiate: ") + hipGetErrorString(ie);
+        return MBPCG_ERR_HIP;
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    hipError_t ge = hipGraphLaunch(exec, stream);
+    if (ge == hipSuccess) ge = hipStreamSynchronize(stream);
+    const auto t2 = std::chrono::steady_clock::now();
+    (void)hipGraphExecDestroy(exec);
+    BCK(ge);
+
+    BCtl hctl;
+    BCK(hipMemcpy(&hctl, d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost));
+    if (hctl.abort) {
+        err = "batched kernel: grid barrier wait exceeded its bound (grid not co-resident?)";
+        return MBPCG_ERR_HIP;
+    }
+    // results
+    const size_t head = offsetof(DevState, Xi);
+    std::vector<char> hst(head * (size_t)nsys);
+    BCK(hipMemcpy2D(hst.data(), head, d_st, sizeof(DevState), head, nsys, hipMemcpyDeviceToHost));
+    const hipMemcpyKind back = mem == MBPCG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    for (int i = 0; i < nsys; ++i)
+        BCK(hipMemcpyAsync(systems[i].x, d_x + hs[i].vec_off, sizeof(double) * systems[i].n, back,
+                           stream));
+    BCK(hipStreamSynchronize(stream));
+    const double ms_kernel = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    const double ms_all = std::chrono::duration<double, std::milli>(t2 - t0).count();
+    mbpcg_status worst = MBPCG_OK;
+    for (int i = 0; i < nsys; ++i) {
+        DevState s;
+        memcpy(&s, hst.data() + head * i, head);
+        mbpcg_status st;
+        switch (s.done) {
+            case DONE_CONVERGED: case DONE_ZERO_RHS: st = MBPCG_OK; break;
+            case DONE_MAXITER: st = MBPCG_NOT_CONVERGED; break;
+            case DONE_BREAKDOWN: st = MBPCG_ERR_BREAKDOWN; break;
+            case DONE_NOTSPD: st = MBPCG_ERR_NOT_SPD; break;
+            case DONE_NONFINITE: st = MBPCG_ERR_NONFINITE; break;
+            default: st = MBPCG_NOT_CONVERGED; break;
+        }
+        if (st != MBPCG_OK && (worst == MBPCG_OK || st < 0)) worst = st;
+        if (per_system) {
+            mbpcg_info& f = per_system[i];
+            memset(&f, 0, sizeof(f));
+            f.iterations = s.iter;
+            f.best_column = s.h;
+            f.final_width = s.width;
+            f.deflations = s.deflations;
+            f.used_fallback = (s.done == DONE_ZERO_RHS) ? 0 : (s.accepted ? 0 : 1);
+            f.rel_res_best_basis = s.nu_h;
+            f.rel_res_ls = s.done == DONE_CONVERGED ? s.rel_ls : NAN;
+            f.rel_res_true = s.rel_true;
+            f.ms_total = ms_all;
+            f.ms_per_iter = hctl.loops > 0 ? ms_kernel / hctl.loops : 0.0;
+            f.ms_phase[7] = ms_kernel;
+            f.status = st;
+        }
+    }
+    return worst;
+#undef BCK
 }
 
 }  // namespace mb

@@ -195,6 +195,7 @@ mbpcg_status mbpcg_solve(mbpcg_ctx ctx, const double* b, double* x, mbpcg_mem me
     mbpcg_info local;
     zero_info(&local);
     mbpcg_status st = mb::solve_entry(ctx->c, b, x, mem, *params, local, 0);
+    local.status = st;
     if (info) *info = local;
     return st;
 }
@@ -209,6 +210,7 @@ mbpcg_status mbpcg_cg_solve(mbpcg_ctx ctx, const double* b, double* x, mbpcg_mem
     mbpcg_info local;
     zero_info(&local);
     mbpcg_status st = mb::solve_entry(ctx->c, b, x, mem, *params, local, 1);
+    local.status = st;
     if (info) *info = local;
     return st;
 }

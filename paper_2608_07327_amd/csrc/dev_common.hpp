@@ -31,7 +31,7 @@ enum DoneCode : int32_t {
 struct DevState {
     int32_t done, iter, h, width;
     int32_t deflations, max_iter, s, accepted;
-    int32_t ls_ok, ls_width, n_hist, pad0;
+    int32_t ls_ok, ls_width, n_hist, ready;  // ready: setup finished (X0, X~ valid)
     double tol, tol0, bnorm, nu_h;
     double gamma, rel_ls, rel_true, y0;
     double tau, bbar_norm, res_norm, pad2;
@@ -95,7 +95,8 @@ __device__ __forceinline__ TileRange tile_range(int64_t ntiles) {
 // Deterministic per-workgroup accumulator of ETOT sums over rows of LDS tiles.
 // Entries are spread over the 256 threads; when ETOT < 256 each entry's rows
 // are split over TPE threads whose partial sums are added in a fixed order at
-// the end.  f(e, r) returns the term of entry e for tile row r.
+// the end.  f(k, r) returns the term of this thread's k-th entry (ent[k]) for
+// tile row r.
 // ---------------------------------------------------------------------------
 template <int ETOT>
 struct TileSums {
@@ -130,7 +131,7 @@ struct TileSums {
             const int e = ent[k];
             if (e < 0) continue;
             double a = acc[k];
-            for (int r = sub; r < rows; r += TPE) a += f(e, r);
+            for (int r = sub; r < rows; r += TPE) a += f(k, r);
             acc[k] = a;
         }
     }
@@ -157,15 +158,16 @@ struct TileSums {
     }
 };
 
-// Sum part[w * E + e] over w = 0..nwg-1 in a fixed order into out[e] (LDS),
-// using all threads of the block.  tmp must hold max(blockDim, E) doubles.
+// Sum part[w * stride + e] over w = 0..nwg-1 in a fixed order into out[e]
+// (LDS), using all threads of the block.  tmp must hold max(blockDim, E)
+// doubles.  Ends with a barrier.
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nwg, int E,
-                                                double* out, double* tmp) {
+                                                int stride, double* out, double* tmp) {
     const int B = blockDim.x, t = threadIdx.x;
     if (E >= B) {
         for (int e = t; e < E; e += B) {
             double s = 0.0;
-            for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * E + e];
+            for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * stride + e];
             out[e] = s;
         }
         __syncthreads();
@@ -177,7 +179,7 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
         const int chunk = (nwg + tpe - 1) / tpe;
         const int w0 = q * chunk, w1 = min(nwg, w0 + chunk);
         double s = 0.0;
-        for (int w = w0; w < w1; ++w) s += part[(int64_t)w * E + e];
+        for (int w = w0; w < w1; ++w) s += part[(int64_t)w * stride + e];
         tmp[q * E + e] = s;
     }
     __syncthreads();

@@ -1,0 +1,368 @@
+// s x s FP64 work of an MBPCG iteration, as device functions run by one
+// workgroup (all threads call them; they contain barriers).  Each takes the
+// partial sums of its reduction (nwg slots, `stride` doubles apart) and LDS
+// workspace from the caller, so the single-system tail kernels and the
+// batched persistent kernel share them.  The factorisations are sequential
+// stages separated by barriers; thread i owns row (or column) i.
+#pragma once
+#include "dev_common.hpp"
+
+namespace mb {
+
+// ---------------------------------------------------------------------------
+// lower Cholesky C = L L^T (S x S, reads the lower triangle).  Returns nonzero
+// when a pivot is not positive and finite.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ int chol_lower(const double* C, double* L, int* flag) {
+    const int t = threadIdx.x;
+    for (int e = t; e < S * S; e += blockDim.x) L[e] = 0.0;
+    if (t == 0) *flag = 0;
+    __syncthreads();
+    for (int j = 0; j < S; ++j) {
+        if (t == 0) {
+            double dd = C[j * S + j];
+            for (int k = 0; k < j; ++k) dd -= L[j * S + k] * L[j * S + k];
+            if (!(dd > 0.0) || !finite_d(dd)) {
+                *flag = 1;
+                dd = 1.0;
+            }
+            L[j * S + j] = sqrt(dd);
+        }
+        __syncthreads();
+        if (t > j && t < S) {
+            double v = C[t * S + j];
+            for (int k = 0; k < j; ++k) v -= L[t * S + k] * L[j * S + k];
+            L[t * S + j] = v / L[j * S + j];
+        }
+        __syncthreads();
+    }
+    const int f = *flag;
+    __syncthreads();
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky QR factor with column dropping (Sec. 3 uses single-pass Cholesky
+// QR; the paper only needs independent columns).  G = U^T U column by column;
+// column l is kept iff G_ll > 0, finite, and delta_l > tau G_ll with
+// delta_l = G_ll - sum_{kept q < l} U_ql^2.  Writes U (upper), keep[S],
+// Z = kept rows of U (upper trapezoidal, dropped rows zero) and M = inverse
+// of the kept block (dropped rows and columns zero).  Returns the number of
+// kept columns.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ int cholqr_factor(const double* G, double tau, double* U, int* keep, double* Z,
+                             double* M, int* cnt) {
+    const int t = threadIdx.x;
+    for (int e = t; e < S * S; e += blockDim.x) {
+        U[e] = 0.0;
+        M[e] = 0.0;
+    }
+    __syncthreads();
+    for (int l = 0; l < S; ++l) {
+        if (t == 0) {
+            const double g = G[l * S + l];
+            double dl = g;
+            for (int q = 0; q < l; ++q)
+                if (keep[q]) dl -= U[q * S + l] * U[q * S + l];
+            const int k = (g > 0.0) && finite_d(dl) && (dl > tau * g);
+            keep[l] = k;
+            if (k) U[l * S + l] = sqrt(dl);
+        }
+        __syncthreads();
+        if (keep[l] && t > l && t < S) {
+            double v = G[l * S + t];
+            for (int q = 0; q < l; ++q)
+                if (keep[q]) v -= U[q * S + l] * U[q * S + t];
+            U[l * S + t] = v / U[l * S + l];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e % S;
+        Z[e] = (keep[i] && j >= i) ? U[e] : 0.0;
+    }
+    if (t < S && keep[t]) {
+        const int c = t;
+        M[c * S + c] = 1.0 / U[c * S + c];
+        for (int a = c - 1; a >= 0; --a) {
+            if (!keep[a]) continue;
+            double v = 0.0;
+            for (int b = a + 1; b <= c; ++b)
+                if (keep[b]) v -= U[a * S + b] * M[b * S + c];
+            M[a * S + c] = v / U[a * S + a];
+        }
+    }
+    if (t == 0) {
+        int k = 0;
+        for (int l = 0; l < S; ++l) k += keep[l];
+        *cnt = k;
+    }
+    __syncthreads();
+    const int k = *cnt;
+    __syncthreads();
+    return k;
+}
+
+template <int E>
+struct RedWs {
+    static constexpr int N = E > MB_BLOCK ? E : MB_BLOCK;
+};
+
+// doubles / ints of LDS workspace each body needs
+template <int S>
+struct SxsWs {
+    static constexpr int XI = 2 * RedWs<tri_count(S)>::N + 4 * S * S;
+    static constexpr int QR = 2 * RedWs<tri_count(S) + S>::N + 5 * S * S;
+    static constexpr int LS = 2 * RedWs<tri_count(S + 1)>::N + 2 * (S + 1) * (S + 1) + 2 * (S + 1);
+    static constexpr int DOUBLES = XI > QR ? (XI > LS ? XI : LS) : (QR > LS ? QR : LS);
+    static constexpr int INTS = S + 8;
+};
+
+// ---------------------------------------------------------------------------
+// line Xi: C = P^T A P from partials; inactive columns get an identity
+// row/column; Xi = C^-1 through C = L L^T; alpha = Xi Sigma.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ void tail_xi_body(const double* __restrict__ part, int nwg, int stride,
+                             DevState* __restrict__ st, double* sm, int* smi) {
+    constexpr int E = tri_count(S);
+    constexpr int RN = RedWs<E>::N;
+    double* tri = sm;
+    double* tmp = sm + RN;
+    double* C = sm + 2 * RN;
+    double* L = C + S * S;
+    double* Li = L + S * S;
+    double* Xi = Li + S * S;
+    const int t = threadIdx.x;
+    reduce_partials(part, nwg, E, stride, tri, tmp);
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e % S;
+        const int a = i >= j ? i : j, b = i >= j ? j : i;
+        double v = tri[a * (a + 1) / 2 + b];
+        if (!st->active[i] || !st->active[j]) v = (i == j) ? 1.0 : 0.0;
+        C[e] = v;
+    }
+    __syncthreads();
+    if (chol_lower<S>(C, L, smi)) {
+        if (t == 0) st->done = DONE_NOTSPD;
+        return;
+    }
+    // L^-1 by forward substitution, one column per thread
+    for (int e = t; e < S * S; e += blockDim.x) Li[e] = 0.0;
+    __syncthreads();
+    if (t < S) {
+        const int c = t;
+        Li[c * S + c] = 1.0 / L[c * S + c];
+        for (int i = c + 1; i < S; ++i) {
+            double v = 0.0;
+            for (int k = c; k < i; ++k) v -= L[i * S + k] * Li[k * S + c];
+            Li[i * S + c] = v / L[i * S + i];
+        }
+    }
+    __syncthreads();
+    // Xi = L^-T L^-1
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e % S;
+        const int k0 = i > j ? i : j;
+        double v = 0.0;
+        for (int k = k0; k < S; ++k) v += Li[k * S + i] * Li[k * S + j];
+        Xi[e] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e % S;
+        double v = 0.0;
+        for (int l = 0; l < S; ++l) v += Xi[i * S + l] * st->Sigma[l * MB_SM + j];
+        st->alpha[i * MB_SM + j] = v;
+        st->Xi[i * MB_SM + j] = Xi[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// lines h, initial_tolerance, W_zeta (second half), Sigma; or, with setup,
+// line W^0_Sigma^0.  Partials hold the lower triangle of V^T V and then
+// nu_j = sum_r (d_r R_rj)^2.  Returns 1 when this call finished the system
+// (converged, stalled or failed), else 0.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride,
+                            DevState* __restrict__ st, double* __restrict__ hist, int setup,
+                            double* sm, int* smi) {
+    constexpr int E = tri_count(S);
+    constexpr int ET = E + S;
+    constexpr int RN = RedWs<ET>::N;
+    double* red = sm;
+    double* tmp = sm + RN;
+    double* G = sm + 2 * RN;
+    double* U = G + S * S;
+    double* Z = U + S * S;
+    double* M = Z + S * S;
+    double* Sg = M + S * S;
+    int* keep = smi;
+    int* cnt = smi + S;
+    int* stop = smi + S + 1;
+    const int t = threadIdx.x;
+    reduce_partials(part, nwg, ET, stride, red, tmp);
+    if (t == 0) {
+        // best column in the original residual norm (Sec. 1: R = D R~)
+        const int s = st->s;
+        int h = 0;
+        double best = red[E];
+        for (int j = 0; j < s; ++j) {
+            st->nu[j] = sqrt(red[E + j]) / st->bnorm;
+            if (j > 0 && red[E + j] < best) {
+                best = red[E + j];
+                h = j;
+            }
+        }
+        const double nu_h = sqrt(best) / st->bnorm;
+        st->h = h;
+        st->nu_h = nu_h;
+        int stp = 0;
+        if (!setup) {
+            const int it = st->iter + 1;
+            st->iter = it;
+            if (hist && it <= st->n_hist) hist[it - 1] = nu_h;
+            if (!finite_d(nu_h)) {
+                st->done = DONE_NONFINITE;
+                stp = 1;
+            } else if (nu_h < st->tol0) {
+                st->done = DONE_CONVERGED;
+                stp = 1;
+            }
+        }
+        *stop = stp;
+    }
+    __syncthreads();
+    if (*stop) return 1;
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e % S;
+        const int a = i >= j ? i : j, b = i >= j ? j : i;
+        G[e] = red[a * (a + 1) / 2 + b];
+    }
+    __syncthreads();
+    const int k = cholqr_factor<S>(G, st->tau, U, keep, Z, M, cnt);
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e % S;
+        double v;
+        if (setup) {
+            v = Z[e];
+        } else {
+            v = 0.0;
+            for (int l = 0; l < S; ++l) v += Z[i * S + l] * st->Sigma[l * MB_SM + j];
+        }
+        Sg[e] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e % S;
+        st->Sigma[i * MB_SM + j] = Sg[e];
+        st->Z[i * MB_SM + j] = Z[e];
+        st->M[i * MB_SM + j] = M[e];
+    }
+    if (t < S) st->active[t] = keep[t];
+    int fin = 0;
+    if (k == 0) fin = 1;
+    else if (!setup && st->iter >= st->max_iter) fin = 1;
+    if (t == 0) {
+        if (setup) st->ready = 1;
+        const int before = setup ? st->s : st->width;
+        st->deflations += before - k;
+        st->width = k;
+        if (k == 0) st->done = setup ? DONE_CONVERGED : DONE_BREAKDOWN;
+        else if (!setup && st->iter >= st->max_iter) st->done = DONE_MAXITER;
+    }
+    return fin;
+}
+
+// ---------------------------------------------------------------------------
+// Least squares of the termination (line hat_c).  Columns m_0 = b,
+// m_{j+1} = D R_j; K = M^T M (lower triangle from partials).  Minimise
+// ||M y|| subject to sum y = 1: with Delta = diag(||m_i||), K~ = Delta^-1 K
+// Delta^-1 and w = Delta^-1 1, y = Delta^-1 z / (w^T z) where K~ z = w,
+// solved by Cholesky over the independent columns (same dropping rule as
+// the Cholesky QR).  c_j = y_{j+1}.  Since b - B^ c = (1 - sum c) b + D R c,
+// this is the minimiser of ||b - B^ c||.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ void tail_ls_body(const double* __restrict__ part, int nwg, int stride,
+                             DevState* __restrict__ st, double* sm, int* smi) {
+    constexpr int NC = S + 1;
+    constexpr int E = tri_count(NC);
+    constexpr int RN = RedWs<E>::N;
+    double* red = sm;
+    double* tmp = sm + RN;
+    double* K = sm + 2 * RN;
+    double* Lk = K + NC * NC;
+    double* dn = Lk + NC * NC;
+    double* z = dn + NC;
+    int* keep = smi;
+    const int t = threadIdx.x;
+    reduce_partials(part, nwg, E, stride, red, tmp);
+    if (t < NC) dn[t] = sqrt(red[t * (t + 1) / 2 + t]);
+    __syncthreads();
+    for (int e = t; e < NC * NC; e += blockDim.x) {
+        const int i = e / NC, j = e % NC;
+        const int a = i >= j ? i : j, b = i >= j ? j : i;
+        const double den = dn[i] * dn[j];
+        K[e] = den > 0.0 ? red[a * (a + 1) / 2 + b] / den : 0.0;
+        Lk[e] = 0.0;
+    }
+    __syncthreads();
+    for (int l = 0; l < NC; ++l) {
+        if (t == 0) {
+            const double g = K[l * NC + l];
+            double dl = g;
+            for (int q = 0; q < l; ++q)
+                if (keep[q]) dl -= Lk[l * NC + q] * Lk[l * NC + q];
+            const int k = (dn[l] > 0.0) && (g > 0.0) && finite_d(dl) && (dl > st->tau * g);
+            keep[l] = k;
+            Lk[l * NC + l] = k ? sqrt(dl) : 1.0;
+        }
+        __syncthreads();
+        if (keep[l] && t > l && t < NC) {
+            double v = K[t * NC + l];
+            for (int q = 0; q < l; ++q)
+                if (keep[q]) v -= Lk[t * NC + q] * Lk[l * NC + q];
+            Lk[t * NC + l] = v / Lk[l * NC + l];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        // forward L y = w, backward L^T z = y (kept columns only); y in z's slot first
+        int kept = 0;
+        for (int i = 0; i < NC; ++i) {
+            z[i] = 0.0;
+            if (!keep[i]) continue;
+            ++kept;
+            double v = 1.0 / dn[i];
+            for (int q = 0; q < i; ++q)
+                if (keep[q]) v -= Lk[i * NC + q] * z[q];
+            z[i] = v / Lk[i * NC + i];
+        }
+        for (int i = NC - 1; i >= 0; --i) {
+            if (!keep[i]) continue;
+            double v = z[i];
+            for (int q = i + 1; q < NC; ++q)
+                if (keep[q]) v -= Lk[q * NC + i] * z[q];
+            z[i] = v / Lk[i * NC + i];
+        }
+        double wz = 0.0;
+        for (int i = 0; i < NC; ++i)
+            if (keep[i]) wz += z[i] / dn[i];
+        bool ok = wz > 0.0 && finite_d(wz);
+        for (int i = 0; i < NC; ++i) {
+            const double yi = keep[i] ? (z[i] / wz) / dn[i] : 0.0;
+            if (!finite_d(yi)) ok = false;
+            if (i == 0) st->y0 = yi;
+            else st->chat[i - 1] = yi;
+        }
+        st->ls_ok = ok ? 1 : 0;
+        st->ls_width = kept;
+    }
+    __syncthreads();
+}
+
+}  // namespace mb

@@ -398,9 +398,10 @@ __global__ void k_select(int64_t n, const double* __restrict__ Xt, const double*
                          const DevState* __restrict__ st) {
     if (st->accepted) return;
     const int h = st->h;
+    const bool ready = st->ready;  // a system that failed in setup returns x = 0
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * blockDim.x)
-        x[r] = (Xt[r * S + h] + X0[r * S + h]) / d[r];
+        x[r] = ready ? (Xt[r * S + h] + X0[r * S + h]) / d[r] : 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double*
             }
         }
     }
-    // D layout: lane l, element v -> row 4*(l/16) + v, column l % 16
+    // D layout of v_mfma_f64_16x16x4f64: lane l, element v -> row l/16 + 4v, column l % 16
     double* out = qpart + (int64_t)ks * n * S;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double*
         for (int c = 0; c < CT; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t r = rbase + 16 * t + 4 * lk + v;
+                const int64_t r = rbase + 16 * t + lk + 4 * v;
                 const int j = 16 * c + li;
                 if (r < n && j < S) out[r * S + j] = acc[t][c][v];
             }

