@@ -127,6 +127,10 @@ def main():
             raise RuntimeError(f"solve failed: {info}")
         return info
 
+    tuned = {}
+    for sw in sorted({1, s} | (set() if args.no_sweep else {1, 2, 4, 8, 16})):
+        tuned[sw] = solver.autotune(sw)
+
     for _ in range(args.warmup):
         run(solver.solve, s=s, seed=seed, profile=1)
         run(solver.cg_solve, profile=1)
@@ -218,7 +222,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"k_spmm<S={S}> (block product + Gram epilogue)",
+            "kernel": f"k_spmm<S={S},G={tuned[s][0]}> (block product + Gram epilogue), "
+                      f"{tuned[s][1]} workgroups (autotuned)",
             "avg_ms": round(spmm_ms, 5),
             "bytes_per_launch": bytes_alg,
         },

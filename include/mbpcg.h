@@ -131,6 +131,14 @@ mbpcg_status mbpcg_block_product(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond
 mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps,
                                       const double* P, double* Q, double* ms_avg);
 
+/* Autotune the block product of this context for block width s (1, 2, 4, 8,
+ * 16 or 32): time every (lanes per row G, workgroup count) candidate of the
+ * sparse kernel with HIP events on the context's stream and keep the fastest
+ * for later solves of this width (dense contexts keep their fixed tiling).
+ * Outputs may be NULL.  The block product is Alg. 1, line Xi. */
+mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, int32_t* lanes_per_row,
+                            int32_t* workgroups, double* ms_best);
+
 /* One independent system of a batch; pointers as given by `mem`. */
 typedef struct {
     int64_t n, nnz;

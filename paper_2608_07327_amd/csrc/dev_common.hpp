@@ -158,6 +158,20 @@ struct TileSums {
     }
 };
 
+// Sum of part[w * stride + e] for w in [w0, w1): eight interleaved
+// accumulators (eight loads in flight), combined in a fixed tree.
+__device__ __forceinline__ double sum_strided(const double* __restrict__ part, int w0, int w1,
+                                              int stride, int e) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int w = w0;
+    for (; w + 8 <= w1; w += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[(int64_t)(w + u) * stride + e];
+    }
+    for (int u = 0; w < w1; ++w, ++u) a[u] += part[(int64_t)w * stride + e];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 // Sum part[w * stride + e] over w = 0..nwg-1 in a fixed order into out[e]
 // (LDS), using all threads of the block.  tmp must hold max(blockDim, E)
 // doubles.  Ends with a barrier.
@@ -165,11 +179,7 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
                                                 int stride, double* out, double* tmp) {
     const int B = blockDim.x, t = threadIdx.x;
     if (E >= B) {
-        for (int e = t; e < E; e += B) {
-            double s = 0.0;
-            for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * stride + e];
-            out[e] = s;
-        }
+        for (int e = t; e < E; e += B) out[e] = sum_strided(part, 0, nwg, stride, e);
         __syncthreads();
         return;
     }
@@ -177,10 +187,8 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
     const int e = t % E, q = t / E;
     if (q < tpe) {
         const int chunk = (nwg + tpe - 1) / tpe;
-        const int w0 = q * chunk, w1 = min(nwg, w0 + chunk);
-        double s = 0.0;
-        for (int w = w0; w < w1; ++w) s += part[(int64_t)w * stride + e];
-        tmp[q * E + e] = s;
+        const int w0 = min(nwg, q * chunk), w1 = min(nwg, w0 + chunk);
+        tmp[q * E + e] = sum_strided(part, w0, w1, stride, e);
     }
     __syncthreads();
     if (t < E) {

@@ -15,8 +15,8 @@ namespace mb {
 
 template <int S>
 struct Tiles {
-    static constexpr int RPP = MB_BLOCK / S;
-    static constexpr int T = RPP >= 64 ? RPP : 64;
+    static constexpr int RPP = MB_BLOCK / S;   // rows per pass (one thread per column)
+    static constexpr int T = stream_tile(S);   // 4 passes per tile
 };
 
 // ---------------------------------------------------------------------------

@@ -22,10 +22,11 @@ __global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ r
                                                    const DevState* __restrict__ st) {
     static_assert(G % S == 0 && G <= 64 && (64 % G) == 0, "lanes per row");
     if (st && st->done) return;
-    constexpr int RPP = MB_BLOCK / G;            // rows per pass
-    constexpr int T = RPP >= 64 ? RPP : 64;      // tile rows
+    constexpr int RPP = MB_BLOCK / G;                 // rows per pass
+    constexpr int T = spmm_tile(S, G);                // tile rows
     constexpr int PASSES = T / RPP;
     constexpr int SLOTS = G / S;
+    constexpr int U = SLOTS >= 8 ? 1 : 8 / SLOTS;     // gathers in flight per lane
     constexpr int E = tri_count(S);
     __shared__ double sP[T * S];
     __shared__ double sQ[T * S];
@@ -51,15 +52,30 @@ __global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ r
     for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
         const int64_t r0 = tile * T;
         const int rows = (int)min((int64_t)T, n - r0);
-#pragma unroll
         for (int p = 0; p < PASSES; ++p) {
             const int rl = p * RPP + grp;
             double acc = 0.0;
             if (rl < rows) {
                 const int64_t r = r0 + rl;
-                const int kb = rowptr[r], ke = rowptr[r + 1];
-                for (int k = kb + slot; k < ke; k += SLOTS)
-                    acc += vals[k] * P[(int64_t)colind[k] * S + j];
+                const int ke = rowptr[r + 1];
+                // this lane's nonzeros kb+slot, kb+slot+SLOTS, ... in batches of
+                // U independent gathers, added in order
+                for (int k = rowptr[r] + slot; k < ke; k += U * SLOTS) {
+                    int c[U];
+                    double v[U], x[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int kk = k + u * SLOTS;
+                        const bool ok = kk < ke;
+                        c[u] = ok ? colind[kk] : 0;
+                        v[u] = ok ? vals[kk] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) x[u] = P[(int64_t)c[u] * S + j];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (k + u * SLOTS < ke) acc += v[u] * x[u];
+                }
             }
 #pragma unroll
             for (int off = S; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -85,7 +101,7 @@ bool spmm_valid_G(int S, int G) {
 }
 
 int spmm_default_G(int S) {
-    int G = 8 * S;
+    int G = 2 * S;
     return G > 64 ? 64 : G;
 }
 

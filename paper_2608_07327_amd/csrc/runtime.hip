@@ -164,10 +164,10 @@ static Plan make_plan(Ctx& c, int s, DenseKind kind) {
     const int cap = S >= 16 ? 512 : 1024;
     auto it = c.tune.find(S);
     pl.G = (it != c.tune.end() && it->second.G) ? it->second.G : spmm_default_G(S);
-    const int64_t spmm_tiles = (c.n + spmm_tile_rows(pl.G) - 1) / spmm_tile_rows(pl.G);
+    const int64_t spmm_tiles = (c.n + spmm_tile_rows(S, pl.G) - 1) / spmm_tile_rows(S, pl.G);
     pl.nwg_spmm = (it != c.tune.end() && it->second.nwg) ? std::min<int64_t>(it->second.nwg, NWG_MAX)
                                                          : round_grid(spmm_tiles, cap);
-    const int Tu = std::max(64, MB_BLOCK / S);
+    const int Tu = stream_tile(S);
     const int64_t upd_tiles = (c.n + Tu - 1) / Tu;
     pl.nwg_upd = round_grid(upd_tiles, cap);
     pl.nwg_dir = round_grid(upd_tiles, 1024);
@@ -735,6 +735,51 @@ mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, 
     float ms = 0.f;
     CK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
     *ms_avg = (double)ms / reps;
+    return MBPCG_OK;
+}
+
+mbpcg_status tune_entry(Ctx& c, int s, int* G_out, int* nwg_out, double* ms_out) {
+    CK(hipSetDevice(c.device));
+    Plan pl = make_plan(c, s, DENSE_F64);
+    const int S = pl.S;
+    CKS(ensure_blocks(c, S));
+    if (c.dense) {
+        if (G_out) *G_out = 0;
+        if (nwg_out) *nwg_out = pl.nwg_dred;
+        if (ms_out) *ms_out = 0.0;
+        return MBPCG_OK;
+    }
+    if (!c.vals_s) CKS(setup_scaling(c, pl, c.bdev, 1));
+    CK(hipMemsetAsync(c.P, 0, sizeof(double) * (size_t)c.n * S, c.stream));
+    CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
+    int bestG = pl.G, bestW = pl.nwg_spmm;
+    double best = 1e30;
+    for (int G = S; G <= 64; G *= 2) {
+        const int64_t tiles = (c.n + spmm_tile_rows(S, G) - 1) / spmm_tile_rows(S, G);
+        for (int w : {256, 512, 1024, 2048}) {
+            const int nwg = round_grid(std::min<int64_t>(tiles, w), NWG_MAX);
+            if (w > 256 && nwg < w) continue;  // grid already capped by the tile count
+            CK(launch_spmm(S, G, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
+            CK(hipEventRecord(c.ev_a, c.stream));
+            const int reps = 5;
+            for (int r = 0; r < reps; ++r)
+                CK(launch_spmm(S, G, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
+            CK(hipEventRecord(c.ev_b, c.stream));
+            CK(hipEventSynchronize(c.ev_b));
+            float ms = 0.f;
+            CK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
+            const double avg = ms / reps;
+            if (avg < best) {
+                best = avg;
+                bestG = G;
+                bestW = nwg;
+            }
+        }
+    }
+    c.tune[S] = Tuning{bestG, bestW};
+    if (G_out) *G_out = bestG;
+    if (nwg_out) *nwg_out = bestW;
+    if (ms_out) *ms_out = best;
     return MBPCG_OK;
 }
 

@@ -23,7 +23,7 @@ PRECOND_NONE, PRECOND_JACOBI = 0, 1
 FP64, FP32_IR, BF16_IR = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 
-EXPORTS = ("mbpcg_default_params", "mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve",
+EXPORTS = ("mbpcg_autotune", "mbpcg_default_params", "mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve",
            "mbpcg_cg_solve", "mbpcg_block_product", "mbpcg_time_block_product",
            "mbpcg_solve_batch", "mbpcg_stream_copy", "mbpcg_destroy", "mbpcg_status_str",
            "mbpcg_last_error")
@@ -89,6 +89,7 @@ def load():
     L.mbpcg_solve_batch.argtypes = [i32, C.POINTER(System), C.POINTER(Params), C.POINTER(Info),
                                     C.c_int, vp]
     L.mbpcg_stream_copy.argtypes = [vp, vp, i64, vp]
+    L.mbpcg_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]
     L.mbpcg_destroy.argtypes = [vp]
     L.mbpcg_destroy.restype = None
     L.mbpcg_status_str.argtypes = [C.c_int]
@@ -97,7 +98,7 @@ def load():
     L.mbpcg_last_error.restype = C.c_char_p
     for f in ("mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve", "mbpcg_cg_solve",
               "mbpcg_block_product", "mbpcg_time_block_product", "mbpcg_solve_batch",
-              "mbpcg_stream_copy"):
+              "mbpcg_stream_copy", "mbpcg_autotune"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -271,6 +272,14 @@ class Solver:
         st = load().mbpcg_block_product(self._h, int(s), int(precond), P.data_ptr(), Q.data_ptr(),
                                         Cmat.data_ptr())
         _check(st, self._h, allow=(OK,))
+
+    def autotune(self, s):
+        """Time the block-product candidates for width s; later solves use the best.
+        Returns (lanes_per_row, workgroups, ms)."""
+        G, w, ms = C.c_int32(), C.c_int32(), C.c_double()
+        st = load().mbpcg_autotune(self._h, int(s), C.byref(G), C.byref(w), C.byref(ms))
+        _check(st, self._h, allow=(OK,))
+        return G.value, w.value, ms.value
 
     def time_block_product(self, P, Q, s, reps=20):
         ms = C.c_double()

@@ -38,10 +38,18 @@ CFG_DENSE_MIXED = 4
 CFG_BATCH = 5
 
 
-def rng_for(tag) -> np.random.Generator:
+def _flat(tag):
     if isinstance(tag, (list, tuple)):
-        return np.random.default_rng([SEED_BASE, *[int(t) for t in tag]])
-    return np.random.default_rng([SEED_BASE, int(tag)])
+        out = []
+        for t in tag:
+            out.extend(_flat(t))
+        return out
+    return [int(tag)]
+
+
+def rng_for(tag) -> np.random.Generator:
+    """PCG64 stream for a (possibly nested) tuple of integer tags."""
+    return np.random.default_rng([SEED_BASE, *_flat(tag)])
 
 
 @dataclasses.dataclass

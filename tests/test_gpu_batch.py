@@ -65,6 +65,9 @@ def check_batch(systems, seed=100):
                    int(np.ceil(0.01 * io["iterations"])))
         assert abs(info["iterations"] - io["iterations"]) <= band, \
             (i, info["iterations"], io["iterations"], ip["iterations"])
+        if not np.any(xo):
+            assert not np.any(x), i
+            continue
         if info["iterations"] == io["iterations"] and ip["iterations"] == io["iterations"]:
             f = np.linalg.norm(xp - xo) / np.linalg.norm(xo)
             err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
