@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB mbpcg_stream_copy (reference for byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,6 +128,14 @@ def main():
         if info["status"] != 0:
             raise RuntimeError(f"solve failed: {info}")
         return info
+
+    if args.copy_calibration:
+        nb = 1 << 30
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        M.stream_copy(dst, src, nb)
+        torch.cuda.synchronize()
+        del src, dst
 
     tuned = {}
     for sw in sorted({1, s} | (set() if args.no_sweep else {1, 2, 4, 8, 16})):
@@ -222,8 +232,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"k_spmm<S={S},G={tuned[s][0]}> (block product + Gram epilogue), "
-                      f"{tuned[s][1]} workgroups (autotuned)",
+            "kernel": f"k_spmm<S={S},T={tuned[s][1]},lanes/row={tuned[s][0]}> (block product + "
+                      f"Gram epilogue), {tuned[s][2]} workgroups (autotuned)",
             "avg_ms": round(spmm_ms, 5),
             "bytes_per_launch": bytes_alg,
         },

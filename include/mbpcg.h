@@ -132,11 +132,12 @@ mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps,
                                       const double* P, double* Q, double* ms_avg);
 
 /* Autotune the block product of this context for block width s (1, 2, 4, 8,
- * 16 or 32): time every (lanes per row G, workgroup count) candidate of the
- * sparse kernel with HIP events on the context's stream and keep the fastest
- * for later solves of this width (dense contexts keep their fixed tiling).
- * Outputs may be NULL.  The block product is Alg. 1, line Xi. */
-mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, int32_t* lanes_per_row,
+ * 16 or 32): time every candidate shape of the sparse kernel -- rows per
+ * tile, lanes per row (s or 2s) and workgroup count -- with HIP events on the
+ * context's stream, and keep the fastest for later solves of this width.
+ * Dense contexts keep their fixed tiling.  Outputs may be NULL.  The block
+ * product is the A P of Alg. 1. */
+mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, int32_t* lanes_per_row, int32_t* tile_rows,
                             int32_t* workgroups, double* ms_best);
 
 /* One independent system of a batch; pointers as given by `mem`. */

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "dev_spmm.hpp"
 #include "dev_sxs.hpp"
 #include "runtime.hpp"
 
@@ -21,11 +22,11 @@ namespace mb {
 
 constexpr int BT = 128;        // rows per item
 constexpr int PSTRIDE = 48;    // doubles of partial sums per item
-constexpr int BSM = 3 * BT * 8 + MB_BLOCK;  // LDS doubles of the persistent kernel
+constexpr int BSM = 4096;    // LDS doubles of the persistent kernel (32 KB)
 
 struct BSys {
     int64_t n, rp_off, nz_off, vec_off, blk_off;
-    int32_t s, S, G, ntile, item_off, pad;
+    int32_t s, S, SL, ntile, item_off, pad;
 };
 
 struct BCtl {
@@ -197,48 +198,34 @@ __device__ void ph_scale_u(const BArgs& a, const Item& m) {
     }
 }
 
-// Q = A~ P for the tile (lanes per row G); optional lower-triangle Gram P^T Q
-// into part[0..E) and/or sum of Q^2 into part[2]
-template <int S, int G>
+// Q = A~ P for the tile (spmm_tile, CSR slice staged in LDS); optional
+// lower-triangle Gram P^T Q into part[0..E) and/or sum of Q^2 into part[2]
+template <int S, int SL>
 __device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double* Qb, bool gram,
                         bool qsq, double* sm) {
-    constexpr int RPP = MB_BLOCK / G;
-    constexpr int PASSES = (BT + RPP - 1) / RPP;
-    constexpr int SLOTS = G / S;
     constexpr int E = tri_count(S);
     const BSys& y = a.sys[m.sys];
-    const int32_t* rp = a.rowptr + y.rp_off;
-    const int32_t* ci = a.colind + y.nz_off;
-    const double* va = a.vals_s + y.nz_off;
     const double* P = Pb + y.blk_off;
     double* Q = Qb + y.blk_off;
-    double* sP = sm;
-    double* sQ = sm + BT * S;
-    double* red = sm + 2 * BT * S;
+    double* sQ = sm;                    // BT * 8
+    double* sP = sm + BT * 8;           // BT * 8
+    double* sV = sm + 2 * BT * 8;       // 8 * BT
+    int32_t* sC = reinterpret_cast<int32_t*>(sm + 2 * BT * 8 + 8 * BT);   // 8 * BT ints
+    int32_t* sRp = sC + 8 * BT;                                   // BT + 1 ints
+    double* red = sm + BSM - MB_BLOCK;
+    static_assert(2 * BT * 8 + 8 * BT + (8 * BT + BT + 2) / 2 + MB_BLOCK <= BSM, "batched LDS");
     const int tid = threadIdx.x;
-    const int grp = tid / G, lane = tid % G, slot = lane / S, j = lane % S;
-#pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-        const int rl = p * RPP + grp;
-        double acc = 0.0;
-        if (rl < m.rows) {
-            const int64_t r = m.r0 + rl;
-            const int kb = rp[r], ke = rp[r + 1];
-            for (int k = kb + slot; k < ke; k += SLOTS) acc += va[k] * P[(int64_t)ci[k] * S + j];
-        }
-#pragma unroll
-        for (int off = S; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
-        if (slot == 0 && rl < BT) sQ[rl * S + j] = acc;
-    }
+    spmm_tile<S, BT, SL>(a.rowptr + y.rp_off, a.colind + y.nz_off, a.vals_s + y.nz_off, P, m.r0,
+                         m.rows, sRp, sC, sV, sQ);
     if (gram)
         for (int e = tid; e < BT * S; e += MB_BLOCK) sP[e] = e < m.rows * S ? P[m.r0 * S + e] : 0.0;
-    __syncthreads();
     double q2 = 0.0;
     for (int e = tid; e < m.rows * S; e += MB_BLOCK) {
         const double q = sQ[e];
         Q[m.r0 * S + e] = q;
         q2 += q * q;
     }
+    __syncthreads();
     const int64_t it = y.item_off + m.r0 / BT;
     double* out = a.part + it * PSTRIDE;
     if (gram) {
@@ -263,14 +250,10 @@ __device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double*
 template <int S>
 __device__ void ph_spmm_dispatch(const BArgs& a, const Item& m, const double* P, double* Q,
                                  bool gram, bool qsq, double* sm) {
-    const int G = a.sys[m.sys].G;
-    switch (G) {
-#define BG(g) \
-    case g:   \
-        if constexpr (g >= S) ph_spmm<S, g>(a, m, P, Q, gram, qsq, sm); \
-        break;
-        BG(1) BG(2) BG(4) BG(8) BG(16) BG(32) BG(64)
-#undef BG
+    if (a.sys[m.sys].SL == 2) {
+        if constexpr (S * 2 <= 64) ph_spmm<S, 2>(a, m, P, Q, gram, qsq, sm);
+    } else {
+        ph_spmm<S, 1>(a, m, P, Q, gram, qsq, sm);
     }
 }
 
@@ -771,7 +754,8 @@ struct BatchBufs {
     }
 };
 
-int batch_default_G(int S) { return spmm_default_G(S); }
+// slots per row: a second lane group per row pays off for long rows
+static int batch_slots(const mbpcg_system& y) { return (y.nnz >= 16 * y.n) ? 2 : 1; }
 
 mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_params& p,
                          mbpcg_info* per_system, mbpcg_mem mem, hipStream_t user_stream,
@@ -799,7 +783,7 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
         b.blk_off = blk;
         b.s = y.s;
         b.S = padded_width(y.s);
-        b.G = batch_default_G(b.S);
+        b.SL = batch_slots(y);
         b.ntile = (int)((y.n + BT - 1) / BT);
         b.item_off = items;
         b.pad = 0;

@@ -14,7 +14,7 @@ mbpcg_status solve_entry(Ctx& c, const double* b, double* x, mbpcg_mem mem, cons
 mbpcg_status block_product_entry(Ctx& c, int s, int jacobi, const double* P, double* Q, double* C);
 mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, double* Q,
                                       double* ms_avg);
-mbpcg_status tune_entry(Ctx& c, int s, int* G_out, int* nwg_out, double* ms_out);
+mbpcg_status tune_entry(Ctx& c, int s, int* LPR_out, int* T_out, int* nwg_out, double* ms_out);
 mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_params& common,
                          mbpcg_info* per_system, mbpcg_mem mem, hipStream_t stream,
                          std::string& err);
@@ -233,15 +233,16 @@ mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps, co
     return mb::time_block_product_entry(ctx->c, s, reps, P, Q, ms_avg);
 }
 
-mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, int32_t* lanes_per_row, int32_t* workgroups,
-                            double* ms_best) {
+mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, int32_t* lanes_per_row, int32_t* tile_rows,
+                            int32_t* workgroups, double* ms_best) {
     if (!ctx) return MBPCG_ERR_INVALID_ARG;
     if (!pow2_width(s)) return MBPCG_ERR_UNSUPPORTED;
-    int G = 0, w = 0;
+    int L = 0, T = 0, w = 0;
     double ms = 0.0;
-    mbpcg_status st = mb::tune_entry(ctx->c, s, &G, &w, &ms);
+    mbpcg_status st = mb::tune_entry(ctx->c, s, &L, &T, &w, &ms);
     if (st != MBPCG_OK) return st;
-    if (lanes_per_row) *lanes_per_row = G;
+    if (lanes_per_row) *lanes_per_row = L;
+    if (tile_rows) *tile_rows = T;
     if (workgroups) *workgroups = w;
     if (ms_best) *ms_best = ms;
     return MBPCG_OK;

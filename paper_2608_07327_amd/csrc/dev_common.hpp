@@ -158,6 +158,83 @@ struct TileSums {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Lower triangle of X^T Y over the rows of tiles, on the matrix cores
+// (v_mfma_f64_16x16x4f64), for S >= 8.  Wavefront w takes rows 4w..4w+3 of
+// every 16-row group of a tile; lane l feeds A = X^T[i = l%16][k = l/16] and
+// B = Y[k = l/16][j = l%16], and holds C[i = l/16 + 4v][j = l%16] in element
+// v of its accumulator.  The four wavefronts' sums are added in a fixed order
+// once, at the end.
+// ---------------------------------------------------------------------------
+typedef double mb_d4 __attribute__((ext_vector_type(4)));
+
+template <int S>
+struct GramMfma {
+    static constexpr int NB = S >= 16 ? S / 16 : 1;  // 16 x 16 blocks per dimension
+    mb_d4 acc[NB][NB];
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = mb_d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+    // xv(r, c) / yv(r, c): element (row r, column c) of X / Y in this tile
+    template <class FX, class FY>
+    __device__ __forceinline__ void add_tile(int rows, FX xv, FY yv) {
+        const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const int li = l & 15, lk = l >> 4;
+        for (int k0 = wave * 4; k0 < rows; k0 += 16) {
+            const int r = k0 + lk;
+            const bool ok = r < rows;
+            double a[NB], b[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int c = q * 16 + li;
+                a[q] = (ok && c < S) ? xv(r, c) : 0.0;
+                b[q] = (ok && c < S) ? yv(r, c) : 0.0;
+            }
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                for (int jb = 0; jb <= ib; ++jb)
+                    acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc[ib][jb], 0, 0, 0);
+        }
+    }
+
+    // Writes the workgroup's lower triangle (e = i(i+1)/2 + j) to out.  lds
+    // must hold S*S doubles; ends with a barrier.
+    __device__ __forceinline__ void finish(double* lds, double* out) {
+        const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const int li = l & 15, lk = l >> 4;
+        __syncthreads();
+        for (int w = 0; w < MB_BLOCK / 64; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb <= ib; ++jb)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = ib * 16 + lk + 4 * v, j = jb * 16 + li;
+                            if (i < S && j < S) {
+                                const double x = acc[ib][jb][v];
+                                lds[i * S + j] = (w == 0) ? x : lds[i * S + j] + x;
+                            }
+                        }
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < tri_count(S); e += MB_BLOCK) {
+            int i, j;
+            tri_ij(e, i, j);
+            out[e] = lds[i * S + j];
+        }
+        __syncthreads();
+    }
+};
+
 // Sum of part[w * stride + e] for w in [w0, w1): eight interleaved
 // accumulators (eight loads in flight), combined in a fixed tree.
 __device__ __forceinline__ double sum_strided(const double* __restrict__ part, int w0, int w1,

@@ -1,0 +1,95 @@
+// One tile of the CSR block product Q = A P (row-major P, Q with S columns),
+// shared by the single-system kernel and the batched persistent kernel.
+//
+// The tile's row pointers and then its slice of column indices and values
+// (one contiguous range of the CSR arrays) are copied into LDS with
+// coalesced loads, in chunks of NZC nonzeros so rows of any length work.
+// A row is then handled by S*SL lanes: lane (slot, j) walks every SL-th
+// nonzero of the row from LDS and gathers P[col][j] -- a contiguous 8S-byte
+// row of P per nonzero for the S lanes of a slot -- up to 8 gathers in
+// flight, adding them in order; the SL slot sums are combined by a fixed
+// butterfly.  The tile's Q rows land in LDS (sQ) for a coalesced store and
+// for the Gram epilogue.
+#pragma once
+#include "dev_common.hpp"
+
+namespace mb {
+
+template <int S, int T, int SL>
+struct SpmmTile {
+    static constexpr int LPR = S * SL;                 // lanes per row
+    static constexpr int RPP = MB_BLOCK / LPR;         // rows per pass
+    static constexpr int NR = (T + RPP - 1) / RPP;     // passes per tile
+    static constexpr int NZC = 8 * T;                  // nonzeros per LDS chunk
+    static constexpr int U = 8 / SL;                   // gathers in flight per lane
+    // LDS: row pointers, chunk of column indices and values, Q tile
+    static constexpr int LDS_BYTES = 4 * (T + 1) + 4 * NZC + 8 * NZC + 8 * T * S;
+};
+
+// Computes the tile's rows [r0, r0 + rows) of Q into sQ (T x S, rows >= `rows`
+// zero).  All threads of the block call it; it ends with a barrier.
+template <int S, int T, int SL>
+__device__ __forceinline__ void spmm_tile(const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ colind,
+                                          const double* __restrict__ vals,
+                                          const double* __restrict__ P, int64_t r0, int rows,
+                                          int32_t* sRp, int32_t* sC, double* sV, double* sQ) {
+    using TL = SpmmTile<S, T, SL>;
+    constexpr int RPP = TL::RPP, NR = TL::NR, NZC = TL::NZC, U = TL::U;
+    const int tid = threadIdx.x;
+    const int grp = tid / TL::LPR, lane = tid % TL::LPR;
+    const int slot = lane / S, j = lane % S;
+    for (int e = tid; e <= rows; e += MB_BLOCK) sRp[e] = rowptr[r0 + e];
+    __syncthreads();
+    const int nz0 = sRp[0];
+    const int nzt = sRp[rows] - nz0;
+    double acc[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) acc[i] = 0.0;
+    for (int cb = 0; cb < nzt; cb += NZC) {
+        const int cn = min(NZC, nzt - cb);
+        for (int e = tid; e < cn; e += MB_BLOCK) {
+            sC[e] = colind[nz0 + cb + e];
+            sV[e] = vals[nz0 + cb + e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int rl = i * RPP + grp;
+            if (rl >= rows) continue;
+            const int kb = sRp[rl] - nz0, ke = sRp[rl + 1] - nz0;
+            // this slot's nonzeros kb + slot + m*SL that fall in [cb, cb + cn)
+            int k = kb + slot;
+            if (k < cb) k += ((cb - k + SL - 1) / SL) * SL;
+            const int kend = min(ke, cb + cn);
+            double a = acc[i];
+            for (; k < kend; k += U * SL) {
+                double v[U], x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int kk = k + u * SL;
+                    const bool ok = kk < kend;
+                    const int c = ok ? sC[kk - cb] : 0;
+                    v[u] = ok ? sV[kk - cb] : 0.0;
+                    x[u] = P[(int64_t)c * S + j];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (k + u * SL < kend) a += v[u] * x[u];
+            }
+            acc[i] = a;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        double a = acc[i];
+#pragma unroll
+        for (int off = S; off < TL::LPR; off <<= 1) a += __shfl_xor(a, off, 64);
+        const int rl = i * RPP + grp;
+        if (slot == 0 && rl < T) sQ[rl * S + j] = rl < rows ? a : 0.0;
+    }
+    __syncthreads();
+}
+
+}  // namespace mb

@@ -47,13 +47,19 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
         al[l] = st->alpha[l * MB_SM + j];
         xi[l] = st->Xi[l * MB_SM + j];
     }
+    constexpr bool MF = S >= 8;   // V^T V on the matrix cores
     TileSums<E> gs;
-    gs.init();
+    GramMfma<S> gm;
     int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+    if constexpr (MF) {
+        gm.init();
+    } else {
+        gs.init();
 #pragma unroll
-    for (int k = 0; k < TileSums<E>::EPT; ++k) {
-        gi[k] = gj[k] = 0;
-        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+        for (int k = 0; k < TileSums<E>::EPT; ++k) {
+            gi[k] = gj[k] = 0;
+            if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+        }
     }
     double nu = 0.0;
     const int64_t ntiles = (n + T - 1) / T;
@@ -93,11 +99,16 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
             sV[rl * S + j] = v;
         }
         __syncthreads();
-        gs.add_rows(rows, [&](int k, int r) { return sV[r * S + gi[k]] * sV[r * S + gj[k]]; });
+        if constexpr (MF)
+            gm.add_tile(rows, [&](int r, int c) { return sV[r * S + c]; },
+                        [&](int r, int c) { return sV[r * S + c]; });
+        else
+            gs.add_rows(rows, [&](int k, int r) { return sV[r * S + gi[k]] * sV[r * S + gj[k]]; });
         __syncthreads();
     }
     double* out = part + (int64_t)blockIdx.x * (E + S);
-    gs.finish(red, out);
+    if constexpr (MF) gm.finish(sV, out);
+    else gs.finish(red, out);
     __syncthreads();
     red[t] = nu;
     __syncthreads();
@@ -275,13 +286,19 @@ __global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* _
     __shared__ double sX[T * S];
     __shared__ double red[MB_BLOCK];
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
+    constexpr bool MF = S >= 8;
     TileSums<E> gs;
-    gs.init();
+    GramMfma<S> gm;
     int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+    if constexpr (MF) {
+        gm.init();
+    } else {
+        gs.init();
 #pragma unroll
-    for (int k = 0; k < TileSums<E>::EPT; ++k) {
-        gi[k] = gj[k] = 0;
-        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+        for (int k = 0; k < TileSums<E>::EPT; ++k) {
+            gi[k] = gj[k] = 0;
+            if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+        }
     }
     double nu = 0.0;
     const int64_t ntiles = (n + T - 1) / T;
@@ -295,11 +312,16 @@ __global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* _
             const double v = d[r0 + rl] * sX[rl * S + j];
             nu += v * v;
         }
-        gs.add_rows(rows, [&](int k, int r) { return sX[r * S + gi[k]] * sX[r * S + gj[k]]; });
+        if constexpr (MF)
+            gm.add_tile(rows, [&](int r, int c) { return sX[r * S + c]; },
+                        [&](int r, int c) { return sX[r * S + c]; });
+        else
+            gs.add_rows(rows, [&](int k, int r) { return sX[r * S + gi[k]] * sX[r * S + gj[k]]; });
         __syncthreads();
     }
     double* out = part + (int64_t)blockIdx.x * (E + S);
-    gs.finish(red, out);
+    if constexpr (MF) gm.finish(sX, out);
+    else gs.finish(red, out);
     __syncthreads();
     red[t] = nu;
     __syncthreads();

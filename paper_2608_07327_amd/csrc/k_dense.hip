@@ -270,17 +270,23 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit
                                                            double* __restrict__ part,
                                                            const DevState* __restrict__ st) {
     if (st && st->done) return;
-    constexpr int T = 64;
+    constexpr int T = 64 > S ? 64 : S;
     constexpr int E = tri_count(S);
+    constexpr bool MF = S >= 8;
     __shared__ double sP[T * S], sQ[T * S], red[MB_BLOCK];
     const int t = threadIdx.x;
     TileSums<E> gs;
-    gs.init();
+    GramMfma<S> gm;
     int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+    if constexpr (MF) {
+        gm.init();
+    } else {
+        gs.init();
 #pragma unroll
-    for (int k = 0; k < TileSums<E>::EPT; ++k) {
-        gi[k] = gj[k] = 0;
-        if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+        for (int k = 0; k < TileSums<E>::EPT; ++k) {
+            gi[k] = gj[k] = 0;
+            if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+        }
     }
     const int64_t ntiles = (n + T - 1) / T;
     const TileRange tr = tile_range(ntiles);
@@ -300,11 +306,19 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit
             sP[e] = p;
         }
         __syncthreads();
-        if (part)
-            gs.add_rows(rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
+        if (part) {
+            if constexpr (MF)
+                gm.add_tile(rows, [&](int r, int c) { return sP[r * S + c]; },
+                            [&](int r, int c) { return sQ[r * S + c]; });
+            else
+                gs.add_rows(rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
+        }
         __syncthreads();
     }
-    if (part) gs.finish(red, part + (int64_t)blockIdx.x * E);
+    if (part) {
+        if constexpr (MF) gm.finish(sQ, part + (int64_t)blockIdx.x * E);
+        else gs.finish(red, part + (int64_t)blockIdx.x * E);
+    }
 }
 
 // r = b - sum of partials of A x (S = 1), partial ||r||^2 per workgroup

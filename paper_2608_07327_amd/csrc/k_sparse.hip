@@ -1,18 +1,18 @@
 // Block product of the sparse path: Q = A~ P for CSR A~ and row-major P with
-// S columns, fused with the per-workgroup lower triangle of P^T Q
-// (Alg. 1, line Xi).  A is read once for all S columns: the nonzeros of a row
-// are spread over a group of G lanes as (slot, column) pairs, each slot walks
-// every (G/S)-th nonzero and gathers one contiguous S-wide row of P per
-// nonzero, and the slots are combined by a butterfly.  Q goes through LDS so
-// that its store is a linear, coalesced copy and the Gram epilogue reads the
-// tile from LDS.
+// S columns, fused with the per-workgroup lower triangle of P^T Q (the Gram
+// of Alg. 1's step coefficient).  Each tile of T rows is computed by
+// spmm_tile (CSR slice staged through LDS, A read once for all S columns);
+// the Gram is an epilogue on the LDS tiles.  (T, SL, grid) are the tuned
+// shape: T rows per tile, SL lanes-groups (slots) per row.
 #include "kernels.hpp"
 
 #include <algorithm>
 
+#include "dev_spmm.hpp"
+
 namespace mb {
 
-template <int S, int G>
+template <int S, int T, int SL>
 __global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ colind,
                                                    const double* __restrict__ vals, int64_t n,
@@ -20,123 +20,114 @@ __global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ r
                                                    double* __restrict__ Q,
                                                    double* __restrict__ part,
                                                    const DevState* __restrict__ st) {
-    static_assert(G % S == 0 && G <= 64 && (64 % G) == 0, "lanes per row");
+    using TL = SpmmTile<S, T, SL>;
     if (st && st->done) return;
-    constexpr int RPP = MB_BLOCK / G;                 // rows per pass
-    constexpr int T = spmm_tile(S, G);                // tile rows
-    constexpr int PASSES = T / RPP;
-    constexpr int SLOTS = G / S;
-    constexpr int U = SLOTS >= 8 ? 1 : 8 / SLOTS;     // gathers in flight per lane
     constexpr int E = tri_count(S);
-    __shared__ double sP[T * S];
+    constexpr bool MF = S >= 8;                 // Gram on the matrix cores
+    __shared__ int32_t sRp[T + 1];
+    __shared__ int32_t sC[TL::NZC];
+    __shared__ double sV[TL::NZC];
     __shared__ double sQ[T * S];
+    __shared__ double sP[MF ? 1 : T * S];
     __shared__ double red[MB_BLOCK];
-
     const int tid = threadIdx.x;
-    const int grp = tid / G, lane = tid % G;
-    const int slot = lane / S, j = lane % S;
     const int64_t ntiles = (n + T - 1) / T;
     const TileRange tr = tile_range(ntiles);
 
     TileSums<E> gs;
+    GramMfma<S> gm;
     int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
     if (part) {
-        gs.init();
+        if constexpr (MF) {
+            gm.init();
+        } else {
+            gs.init();
 #pragma unroll
-        for (int k = 0; k < TileSums<E>::EPT; ++k) {
-            gi[k] = gj[k] = 0;
-            if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+            for (int k = 0; k < TileSums<E>::EPT; ++k) {
+                gi[k] = gj[k] = 0;
+                if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
+            }
         }
     }
-
     for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
         const int64_t r0 = tile * T;
         const int rows = (int)min((int64_t)T, n - r0);
-        for (int p = 0; p < PASSES; ++p) {
-            const int rl = p * RPP + grp;
-            double acc = 0.0;
-            if (rl < rows) {
-                const int64_t r = r0 + rl;
-                const int ke = rowptr[r + 1];
-                // this lane's nonzeros kb+slot, kb+slot+SLOTS, ... in batches of
-                // U independent gathers, added in order
-                for (int k = rowptr[r] + slot; k < ke; k += U * SLOTS) {
-                    int c[U];
-                    double v[U], x[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int kk = k + u * SLOTS;
-                        const bool ok = kk < ke;
-                        c[u] = ok ? colind[kk] : 0;
-                        v[u] = ok ? vals[kk] : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) x[u] = P[(int64_t)c[u] * S + j];
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (k + u * SLOTS < ke) acc += v[u] * x[u];
-                }
-            }
-#pragma unroll
-            for (int off = S; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
-            if (slot == 0) sQ[rl * S + j] = acc;
-        }
-        if (part) {
-            const double* Pt = P + r0 * S;
+        spmm_tile<S, T, SL>(rowptr, colind, vals, P, r0, rows, sRp, sC, sV, sQ);
+        const double* Pt = P + r0 * S;
+        if (part && !MF)
             for (int e = tid; e < T * S; e += MB_BLOCK) sP[e] = (e < rows * S) ? Pt[e] : 0.0;
-        }
-        __syncthreads();
         double* Qt = Q + r0 * S;
         for (int e = tid; e < rows * S; e += MB_BLOCK) Qt[e] = sQ[e];
         if (part) {
-            gs.add_rows(rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
+            if constexpr (MF) {
+                gm.add_tile(rows, [&](int r, int c) { return Pt[r * S + c]; },
+                            [&](int r, int c) { return sQ[r * S + c]; });
+            } else {
+                __syncthreads();
+                gs.add_rows(rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
+            }
         }
         __syncthreads();
     }
-    if (part) gs.finish(red, part + (int64_t)blockIdx.x * E);
+    if (part) {
+        if constexpr (MF) gm.finish(sQ, part + (int64_t)blockIdx.x * E);
+        else gs.finish(red, part + (int64_t)blockIdx.x * E);
+    }
 }
 
-bool spmm_valid_G(int S, int G) {
-    return G >= S && G <= 64 && (G & (G - 1)) == 0;
+// ---- shapes compiled per width: tile rows x slots
+bool spmm_valid_shape(int S, int T, int SL) {
+    if (!(SL == 1 || SL == 2) || S * SL > 64) return false;
+    if (!(T == 32 || T == 64 || T == 128 || T == 256)) return false;
+    return T * S <= 1024;
 }
 
-int spmm_default_G(int S) {
-    int G = 2 * S;
-    return G > 64 ? 64 : G;
+void spmm_default_shape(int S, int* T, int* SL) {
+    *SL = 1;
+    *T = S <= 4 ? 128 : (S == 8 ? 64 : 32);
 }
 
-template <int S, int G>
+template <int S, int T, int SL>
 static hipError_t spmm_one(int nwg, const CsrDev& A, const double* P, double* Q, double* part,
                            const DevState* st, hipStream_t stream) {
-    hipLaunchKernelGGL((k_spmm<S, G>), dim3(nwg), dim3(MB_BLOCK), 0, stream, A.rowptr, A.colind,
-                       A.vals, A.n, P, Q, part, st);
+    hipLaunchKernelGGL((k_spmm<S, T, SL>), dim3(nwg), dim3(MB_BLOCK), 0, stream, A.rowptr,
+                       A.colind, A.vals, A.n, P, Q, part, st);
     return hipGetLastError();
 }
 
-template <int S>
-static hipError_t spmm_s(int G, int nwg, const CsrDev& A, const double* P, double* Q,
+template <int S, int T>
+static hipError_t spmm_t(int SL, int nwg, const CsrDev& A, const double* P, double* Q,
                          double* part, const DevState* st, hipStream_t stream) {
-    switch (G) {
-#define MB_G(g)                                                                   \
-    case g:                                                                       \
-        if constexpr (g >= S) return spmm_one<S, g>(nwg, A, P, Q, part, st, stream); \
-        break;
-        MB_G(1) MB_G(2) MB_G(4) MB_G(8) MB_G(16) MB_G(32) MB_G(64)
-#undef MB_G
+    if constexpr (T * S <= 1024) {
+        if (SL == 1) return spmm_one<S, T, 1>(nwg, A, P, Q, part, st, stream);
+        if constexpr (S * 2 <= 64)
+            if (SL == 2) return spmm_one<S, T, 2>(nwg, A, P, Q, part, st, stream);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmm(int S, int G, int nwg, const CsrDev& A, const double* P, double* Q,
+template <int S>
+static hipError_t spmm_s(int T, int SL, int nwg, const CsrDev& A, const double* P, double* Q,
+                         double* part, const DevState* st, hipStream_t stream) {
+    switch (T) {
+        case 32: return spmm_t<S, 32>(SL, nwg, A, P, Q, part, st, stream);
+        case 64: return spmm_t<S, 64>(SL, nwg, A, P, Q, part, st, stream);
+        case 128: return spmm_t<S, 128>(SL, nwg, A, P, Q, part, st, stream);
+        case 256: return spmm_t<S, 256>(SL, nwg, A, P, Q, part, st, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_spmm(int S, int T, int SL, int nwg, const CsrDev& A, const double* P, double* Q,
                        double* part, const DevState* st, hipStream_t stream) {
-    if (!spmm_valid_G(S, G)) return hipErrorInvalidValue;
+    if (!spmm_valid_shape(S, T, SL)) return hipErrorInvalidValue;
     switch (S) {
-        case 1: return spmm_s<1>(G, nwg, A, P, Q, part, st, stream);
-        case 2: return spmm_s<2>(G, nwg, A, P, Q, part, st, stream);
-        case 4: return spmm_s<4>(G, nwg, A, P, Q, part, st, stream);
-        case 8: return spmm_s<8>(G, nwg, A, P, Q, part, st, stream);
-        case 16: return spmm_s<16>(G, nwg, A, P, Q, part, st, stream);
-        case 32: return spmm_s<32>(G, nwg, A, P, Q, part, st, stream);
+        case 1: return spmm_s<1>(T, SL, nwg, A, P, Q, part, st, stream);
+        case 2: return spmm_s<2>(T, SL, nwg, A, P, Q, part, st, stream);
+        case 4: return spmm_s<4>(T, SL, nwg, A, P, Q, part, st, stream);
+        case 8: return spmm_s<8>(T, SL, nwg, A, P, Q, part, st, stream);
+        case 16: return spmm_s<16>(T, SL, nwg, A, P, Q, part, st, stream);
+        case 32: return spmm_s<32>(T, SL, nwg, A, P, Q, part, st, stream);
     }
     return hipErrorInvalidValue;
 }

@@ -26,21 +26,15 @@ inline int part_entries_gram(int S) { return tri_count(S); }
 inline int part_entries_update(int S) { return tri_count(S) + S; }
 inline int part_entries_ls(int S) { return tri_count(S + 1); }
 
-// tile rows of the block product for (S, G): 1024/S rows (an 8 KB tile of P),
-// at least one pass of MB_BLOCK/G rows
-__host__ __device__ constexpr int spmm_tile(int S, int G) {
-    return (MB_BLOCK / G) > (1024 / S) ? (MB_BLOCK / G) : (1024 / S);
-}
-inline int spmm_tile_rows(int S, int G) { return spmm_tile(S, G); }
 // tile rows of the streaming n x S kernels: 4 rows per thread
 __host__ __device__ constexpr int stream_tile(int S) { return 1024 / S; }
 
-// ---- block product Q = A P (+ lower triangle of P^T Q per workgroup)
-hipError_t launch_spmm(int S, int G, int nwg, const CsrDev& A, const double* P, double* Q,
+// ---- block product Q = A P (+ lower triangle of P^T Q per workgroup).
+// Shape: T rows per tile (32..256, T*S <= 1024), SL slots (lane groups) per row.
+hipError_t launch_spmm(int S, int T, int SL, int nwg, const CsrDev& A, const double* P, double* Q,
                        double* part, const DevState* st, hipStream_t stream);
-// valid lanes-per-row choices for width S
-bool spmm_valid_G(int S, int G);
-int spmm_default_G(int S);
+bool spmm_valid_shape(int S, int T, int SL);
+void spmm_default_shape(int S, int* T, int* SL);
 
 // ---- dense product: Q partials over KSPLIT column ranges, then reduce + Gram
 enum DenseKind { DENSE_F64 = 0, DENSE_F32 = 1, DENSE_BF16 = 2 };

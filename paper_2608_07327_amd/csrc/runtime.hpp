@@ -20,7 +20,8 @@ struct DevBuf {
 };
 
 struct Tuning {
-    int G = 0;     // lanes per row of the sparse block product
+    int T = 0;     // rows per tile of the sparse block product
+    int SL = 0;    // slots (lane groups of S) per row
     int nwg = 0;   // workgroups of the block product
 };
 
@@ -75,7 +76,7 @@ struct Ctx {
     std::vector<hipEvent_t> pev;  // profile mode: 6 events per iteration
     double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
-    // graphs keyed by (kind, S, m, G, nwg, precision)
+    // graphs keyed by (kind, S, m, tile shape, nwg, precision)
     std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::map<int, Tuning> tune;  // per S
 

@@ -89,7 +89,8 @@ def load():
     L.mbpcg_solve_batch.argtypes = [i32, C.POINTER(System), C.POINTER(Params), C.POINTER(Info),
                                     C.c_int, vp]
     L.mbpcg_stream_copy.argtypes = [vp, vp, i64, vp]
-    L.mbpcg_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]
+    L.mbpcg_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                 C.POINTER(C.c_double)]
     L.mbpcg_destroy.argtypes = [vp]
     L.mbpcg_destroy.restype = None
     L.mbpcg_status_str.argtypes = [C.c_int]
@@ -274,12 +275,12 @@ class Solver:
         _check(st, self._h, allow=(OK,))
 
     def autotune(self, s):
-        """Time the block-product candidates for width s; later solves use the best.
-        Returns (lanes_per_row, workgroups, ms)."""
-        G, w, ms = C.c_int32(), C.c_int32(), C.c_double()
-        st = load().mbpcg_autotune(self._h, int(s), C.byref(G), C.byref(w), C.byref(ms))
+        """Time the block-product shapes for width s; later solves use the best.
+        Returns (lanes_per_row, tile_rows, workgroups, ms)."""
+        L, T, w, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        st = load().mbpcg_autotune(self._h, int(s), C.byref(L), C.byref(T), C.byref(w), C.byref(ms))
         _check(st, self._h, allow=(OK,))
-        return G.value, w.value, ms.value
+        return L.value, T.value, w.value, ms.value
 
     def time_block_product(self, P, Q, s, reps=20):
         ms = C.c_double()
