@@ -232,8 +232,10 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"k_spmm<S={S},T={tuned[s][1]},lanes/row={tuned[s][0]}> (block product + "
-                      f"Gram epilogue), {tuned[s][2]} workgroups (autotuned)",
+            "kernel": (f"k_spmm S={S}: {tuned[s]['tile_rows']} rows/tile, "
+                       f"{tuned[s]['lanes_per_row']} lanes/row, {tuned[s]['cols_per_lane']} cols/lane, "
+                       f"{tuned[s]['loads_in_flight']} loads in flight, {tuned[s]['workgroups']} "
+                       f"workgroups (autotuned); block product + Gram epilogue"),
             "avg_ms": round(spmm_ms, 5),
             "bytes_per_launch": bytes_alg,
         },

@@ -131,14 +131,35 @@ mbpcg_status mbpcg_block_product(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond
 mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps,
                                       const double* P, double* Q, double* ms_avg);
 
-/* Autotune the block product of this context for block width s (1, 2, 4, 8,
- * 16 or 32): time every candidate shape of the sparse kernel -- rows per
- * tile, lanes per row (s or 2s) and workgroup count -- with HIP events on the
- * context's stream, and keep the fastest for later solves of this width.
- * Dense contexts keep their fixed tiling.  Outputs may be NULL.  The block
- * product is the A P of Alg. 1. */
-mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, int32_t* lanes_per_row, int32_t* tile_rows,
-                            int32_t* workgroups, double* ms_best);
+/* Tile shape of the sparse block product, as chosen by mbpcg_autotune. */
+typedef struct {
+    int32_t tile_rows;       /* rows of A per tile; the tile's CSR slice is staged in LDS */
+    int32_t lanes_per_row;   /* lanes sharing one row of A */
+    int32_t cols_per_lane;   /* adjacent columns of P one lane gathers per nonzero (1, 2, 4) */
+    int32_t loads_in_flight; /* gathers a lane issues before it consumes the first */
+    int32_t workgroups;      /* grid of the block-product kernel */
+    int32_t reserved;
+    double ms;               /* mean duration of one block product with this shape */
+} mbpcg_tile_shape;
+
+/* Autotune the block product Q = A~ P, C = P^T Q of this context (the A P of
+ * Alg. 1) for block width s (1, 2, 4, 8, 16 or 32): every compiled tile shape
+ * and grid size is timed with HIP events on the context's stream and the
+ * fastest is kept for later solves of this width.  Dense contexts keep their
+ * fixed tiling (tile_rows = 256, other fields 0).  best may be NULL. */
+mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, mbpcg_tile_shape* best);
+
+/* The compiled tile shapes of the sparse block product for width s: writes
+ * up to cap of them (workgroups = 0, ms = 0) and their total number to
+ * *count.  Needs no GPU. */
+mbpcg_status mbpcg_tile_shapes(int32_t s, mbpcg_tile_shape* out, int32_t cap, int32_t* count);
+
+/* Fix the block-product tile shape of this context for width s, as if
+ * mbpcg_autotune had chosen it: tile_rows, lanes_per_row, cols_per_lane and
+ * loads_in_flight must name a compiled shape (MBPCG_ERR_UNSUPPORTED
+ * otherwise); workgroups <= 0 selects the default grid.  Ignored by dense
+ * contexts. */
+mbpcg_status mbpcg_set_tile_shape(mbpcg_ctx ctx, int32_t s, const mbpcg_tile_shape* shape);
 
 /* One independent system of a batch; pointers as given by `mem`. */
 typedef struct {

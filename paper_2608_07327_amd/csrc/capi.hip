@@ -14,7 +14,8 @@ mbpcg_status solve_entry(Ctx& c, const double* b, double* x, mbpcg_mem mem, cons
 mbpcg_status block_product_entry(Ctx& c, int s, int jacobi, const double* P, double* Q, double* C);
 mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, double* Q,
                                       double* ms_avg);
-mbpcg_status tune_entry(Ctx& c, int s, int* LPR_out, int* T_out, int* nwg_out, double* ms_out);
+mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out);
+mbpcg_status set_shape_entry(Ctx& c, int s, const mbpcg_tile_shape& t);
 mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_params& common,
                          mbpcg_info* per_system, mbpcg_mem mem, hipStream_t stream,
                          std::string& err);
@@ -233,19 +234,36 @@ mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps, co
     return mb::time_block_product_entry(ctx->c, s, reps, P, Q, ms_avg);
 }
 
-mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, int32_t* lanes_per_row, int32_t* tile_rows,
-                            int32_t* workgroups, double* ms_best) {
+mbpcg_status mbpcg_autotune(mbpcg_ctx ctx, int32_t s, mbpcg_tile_shape* best) {
     if (!ctx) return MBPCG_ERR_INVALID_ARG;
     if (!pow2_width(s)) return MBPCG_ERR_UNSUPPORTED;
-    int L = 0, T = 0, w = 0;
-    double ms = 0.0;
-    mbpcg_status st = mb::tune_entry(ctx->c, s, &L, &T, &w, &ms);
+    mbpcg_tile_shape t{};
+    mbpcg_status st = mb::tune_entry(ctx->c, s, &t);
     if (st != MBPCG_OK) return st;
-    if (lanes_per_row) *lanes_per_row = L;
-    if (tile_rows) *tile_rows = T;
-    if (workgroups) *workgroups = w;
-    if (ms_best) *ms_best = ms;
+    if (best) *best = t;
     return MBPCG_OK;
+}
+
+mbpcg_status mbpcg_tile_shapes(int32_t s, mbpcg_tile_shape* out, int32_t cap, int32_t* count) {
+    if (!pow2_width(s) || cap < 0 || (cap > 0 && !out)) return s < 1 ? MBPCG_ERR_INVALID_ARG
+                                                                    : MBPCG_ERR_UNSUPPORTED;
+    mb::SpmmShape sh[64];
+    const int k = mb::spmm_shape_list(s, sh, 64);
+    for (int i = 0; i < k && i < cap; ++i) {
+        out[i] = mbpcg_tile_shape{};
+        out[i].tile_rows = sh[i].T;
+        out[i].lanes_per_row = mb::spmm_lanes_per_row(s, sh[i]);
+        out[i].cols_per_lane = sh[i].V;
+        out[i].loads_in_flight = sh[i].U;
+    }
+    if (count) *count = k;
+    return MBPCG_OK;
+}
+
+mbpcg_status mbpcg_set_tile_shape(mbpcg_ctx ctx, int32_t s, const mbpcg_tile_shape* shape) {
+    if (!ctx || !shape) return MBPCG_ERR_INVALID_ARG;
+    if (!pow2_width(s)) return MBPCG_ERR_UNSUPPORTED;
+    return mb::set_shape_entry(ctx->c, s, *shape);
 }
 
 mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,

@@ -1,18 +1,71 @@
 // Block product of the sparse path: Q = A~ P for CSR A~ and row-major P with
 // S columns, fused with the per-workgroup lower triangle of P^T Q (the Gram
-// of Alg. 1's step coefficient).  Each tile of T rows is computed by
-// spmm_tile (CSR slice staged through LDS, A read once for all S columns);
-// the Gram is an epilogue on the LDS tiles.  (T, SL, grid) are the tuned
-// shape: T rows per tile, SL lanes-groups (slots) per row.
+// whose inverse is Alg. 1's step matrix Xi).
+//
+// A tile of T rows has its row pointers and then its CSR slice (column
+// indices and values, one contiguous range) staged in LDS with coalesced
+// loads, so A is read from HBM once per product for all S columns.  A row is
+// handled by LPR = (S / V) * SL lanes: lane (slot, jv) accumulates the V
+// adjacent columns jv .. jv+V-1 of P (16-byte loads for V = 2, 4) over every
+// SL-th nonzero of the row, with U gathers in flight.  Q leaves the lanes'
+// registers with coalesced vector stores.
+//
+// Gram epilogue, chosen by width so that it costs few registers (the kernel
+// lives on occupancy: its gathers' latency is hidden by other wavefronts):
+//  - S <= 2: each lane keeps the S x V block of P^T Q that its rows feed,
+//    from its own P row; reduced over lanes and waves once per workgroup.
+//  - S = 4: the tile's P rows (staged in LDS next to the row pointers) and Q
+//    rows (from the lanes) feed a per-thread fixed-order sum of one entry.
+//  - S >= 8: the same LDS tiles feed the 16 x 16 x 4 FP64 MFMA.
+// The tuned shape is (T, SL, V, U) plus the grid size.
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <tuple>
 
 #include "dev_spmm.hpp"
 
 namespace mb {
 
-template <int S, int T, int SL>
+template <int S_, int T_, int SL_, int V_, int U_>
+struct BpShape {
+    static constexpr int S = S_, T = T_, SL = SL_, V = V_, U = U_;
+    static constexpr int CPR = S / V;                  // lanes per row and slot
+    static constexpr int LPR = CPR * SL;               // lanes per row
+    static constexpr int RPP = MB_BLOCK / LPR;         // rows per pass of the block
+    static constexpr int NR = (T + RPP - 1) / RPP;     // passes per tile
+    static constexpr int NZC = 8 * T;                  // nonzeros per LDS chunk
+    static constexpr bool REG = S <= 2;                // Gram in lane registers
+    static constexpr bool MF = S >= 8;                 // Gram on the matrix cores
+    static_assert(S % V == 0 && LPR <= 64 && (V == 1 || V == 2 || V == 4), "shape");
+};
+
+template <int V>
+__device__ __forceinline__ void load_cols(const double* p, double* x) {
+    if constexpr (V == 1) {
+        x[0] = p[0];
+    } else {
+#pragma unroll
+        for (int h = 0; h < V / 2; ++h) {
+            const double2 t = reinterpret_cast<const double2*>(p)[h];
+            x[2 * h] = t.x;
+            x[2 * h + 1] = t.y;
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_cols(double* p, const double* x) {
+    if constexpr (V == 1) {
+        p[0] = x[0];
+    } else {
+#pragma unroll
+        for (int h = 0; h < V / 2; ++h)
+            reinterpret_cast<double2*>(p)[h] = make_double2(x[2 * h], x[2 * h + 1]);
+    }
+}
+
+template <class B>
 __global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ colind,
                                                    const double* __restrict__ vals, int64_t n,
@@ -20,116 +73,250 @@ __global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ r
                                                    double* __restrict__ Q,
                                                    double* __restrict__ part,
                                                    const DevState* __restrict__ st) {
-    using TL = SpmmTile<S, T, SL>;
-    if (st && st->done) return;
+    constexpr int S = B::S, T = B::T, SL = B::SL, V = B::V, U = B::U;
+    constexpr int RPP = B::RPP, NR = B::NR, NZC = B::NZC;
+    constexpr bool REG = B::REG, MF = B::MF;
     constexpr int E = tri_count(S);
-    constexpr bool MF = S >= 8;                 // Gram on the matrix cores
+    if (st && st->done) return;
     __shared__ int32_t sRp[T + 1];
-    __shared__ int32_t sC[TL::NZC];
-    __shared__ double sV[TL::NZC];
-    __shared__ double sQ[T * S];
-    __shared__ double sP[MF ? 1 : T * S];
-    __shared__ double red[MB_BLOCK];
+    __shared__ int32_t sC[NZC];
+    __shared__ double sV[NZC];
+    __shared__ double sQ[REG ? 1 : T * S];
+    __shared__ double sP[REG ? 1 : T * S];
+    __shared__ double red[REG ? (MB_BLOCK / 64) * S * S : (S * S > MB_BLOCK ? S * S : MB_BLOCK)];
     const int tid = threadIdx.x;
-    const int64_t ntiles = (n + T - 1) / T;
-    const TileRange tr = tile_range(ntiles);
+    const int grp = tid / B::LPR, lane = tid % B::LPR;
+    const int slot = lane / B::CPR, jv = (lane % B::CPR) * V;
+    const bool gram = part != nullptr;
 
-    TileSums<E> gs;
-    GramMfma<S> gm;
-    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
-    if (part) {
-        if constexpr (MF) {
-            gm.init();
-        } else {
-            gs.init();
+    double g[REG ? S : 1][V];          // register Gram: G[i][jv + q]
 #pragma unroll
-            for (int k = 0; k < TileSums<E>::EPT; ++k) {
-                gi[k] = gj[k] = 0;
-                if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
-            }
+    for (int i = 0; i < (REG ? S : 1); ++i)
+#pragma unroll
+        for (int q = 0; q < V; ++q) g[i][q] = 0.0;
+    TileSums<E> gs;
+    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+    GramMfma<S> gm;
+    if constexpr (MF) {
+        gm.init();
+    } else if constexpr (!REG) {
+        gs.init();
+#pragma unroll
+        for (int k = 0; k < TileSums<E>::EPT; ++k) {
+            gi[k] = gj[k] = 0;
+            if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
         }
     }
+
+    const int64_t ntiles = (n + T - 1) / T;
+    const TileRange tr = tile_range(ntiles);
     for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
         const int64_t r0 = tile * T;
         const int rows = (int)min((int64_t)T, n - r0);
-        spmm_tile<S, T, SL>(rowptr, colind, vals, P, r0, rows, sRp, sC, sV, sQ);
         const double* Pt = P + r0 * S;
-        if (part && !MF)
-            for (int e = tid; e < T * S; e += MB_BLOCK) sP[e] = (e < rows * S) ? Pt[e] : 0.0;
-        double* Qt = Q + r0 * S;
-        for (int e = tid; e < rows * S; e += MB_BLOCK) Qt[e] = sQ[e];
-        if (part) {
-            if constexpr (MF) {
-                gm.add_tile(rows, [&](int r, int c) { return Pt[r * S + c]; },
-                            [&](int r, int c) { return sQ[r * S + c]; });
+
+        double pr[REG ? NR : 1][S];    // register Gram: this lane's P rows
+        if (gram) {
+            if constexpr (REG) {
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    const int rl = i * RPP + grp;
+                    if (rl < rows && slot == 0) {
+                        load_cols<S>(Pt + (int64_t)rl * S, pr[i]);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < S; ++c) pr[i][c] = 0.0;
+                    }
+                }
             } else {
+                for (int e = tid; e < T * S; e += MB_BLOCK) sP[e] = e < rows * S ? Pt[e] : 0.0;
+            }
+        }
+        for (int e = tid; e <= rows; e += MB_BLOCK) sRp[e] = rowptr[r0 + e];
+        __syncthreads();
+        const int nz0 = sRp[0];
+        const int nzt = sRp[rows] - nz0;
+        double acc[NR][V];
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc[i][q] = 0.0;
+        for (int cb = 0; cb < nzt; cb += NZC) {
+            const int cn = min(NZC, nzt - cb);
+            for (int e = tid; e < cn; e += MB_BLOCK) {
+                sC[e] = colind[nz0 + cb + e];
+                sV[e] = vals[nz0 + cb + e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int rl = i * RPP + grp;
+                if (rl >= rows) continue;
+                const int kb = sRp[rl] - nz0, ke = sRp[rl + 1] - nz0;
+                // this slot's nonzeros kb + slot + m*SL inside [cb, cb + cn)
+                int k = kb + slot;
+                if (k < cb) k += ((cb - k + SL - 1) / SL) * SL;
+                const int kend = min(ke, cb + cn);
+                for (; k < kend; k += U * SL) {
+                    double v[U], x[U][V];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int kk = k + u * SL;
+                        const bool ok = kk < kend;
+                        const int c = ok ? sC[kk - cb] : 0;
+                        v[u] = ok ? sV[kk - cb] : 0.0;
+                        load_cols<V>(P + (int64_t)c * S + jv, x[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (k + u * SL < kend) {
+#pragma unroll
+                            for (int q = 0; q < V; ++q) acc[i][q] += v[u] * x[u][q];
+                        }
+                }
+            }
+            __syncthreads();
+        }
+
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int rl = i * RPP + grp;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                double a = acc[i][q];
+#pragma unroll
+                for (int off = B::CPR; off < B::LPR; off <<= 1) a += __shfl_xor(a, off, 64);
+                acc[i][q] = a;
+            }
+            if (slot == 0 && rl < T) {
+                if (rl < rows) store_cols<V>(Q + (r0 + rl) * S + jv, acc[i]);
+                if constexpr (REG) {
+#pragma unroll
+                    for (int c = 0; c < S; ++c)
+#pragma unroll
+                        for (int q = 0; q < V; ++q) g[c][q] += pr[i][c] * acc[i][q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < V; ++q) sQ[rl * S + jv + q] = rl < rows ? acc[i][q] : 0.0;
+                }
+            }
+        }
+        if constexpr (!REG) {
+            if (gram) {
                 __syncthreads();
-                gs.add_rows(rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
+                if constexpr (MF)
+                    gm.add_tile(rows, [&](int r, int c) { return sP[r * S + c]; },
+                                [&](int r, int c) { return sQ[r * S + c]; });
+                else
+                    gs.add_rows(rows, [&](int k, int r) { return sP[r * S + gi[k]] * sQ[r * S + gj[k]]; });
             }
         }
         __syncthreads();
     }
-    if (part) {
-        if constexpr (MF) gm.finish(sQ, part + (int64_t)blockIdx.x * E);
-        else gs.finish(red, part + (int64_t)blockIdx.x * E);
+    if (!gram) return;
+
+    if constexpr (REG) {
+        // sum over the row groups of the wave (lanes with equal slot and jv)
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                double x = g[c][q];
+#pragma unroll
+                for (int off = B::LPR; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
+                g[c][q] = x;
+            }
+        const int wave = tid >> 6;
+        if ((tid & 63) < B::LPR && slot == 0) {
+#pragma unroll
+            for (int c = 0; c < S; ++c)
+#pragma unroll
+                for (int q = 0; q < V; ++q) red[wave * S * S + c * S + jv + q] = g[c][q];
+        }
+        __syncthreads();
+        for (int e = tid; e < E; e += MB_BLOCK) {
+            int i, j;
+            tri_ij(e, i, j);
+            double s = red[i * S + j];
+#pragma unroll
+            for (int w = 1; w < MB_BLOCK / 64; ++w) s += red[w * S * S + i * S + j];
+            part[(int64_t)blockIdx.x * E + e] = s;
+        }
+    } else if constexpr (MF) {
+        gm.finish(red, part + (int64_t)blockIdx.x * E);
+    } else {
+        gs.finish(red, part + (int64_t)blockIdx.x * E);
     }
 }
 
-// ---- shapes compiled per width: tile rows x slots
-bool spmm_valid_shape(int S, int T, int SL) {
-    if (!(SL == 1 || SL == 2) || S * SL > 64) return false;
-    if (!(T == 32 || T == 64 || T == 128 || T == 256)) return false;
-    return T * S <= 1024;
+// ---- compiled shapes (S, T, SL, V, U)
+using BpShapes = std::tuple<
+    BpShape<1, 64, 1, 1, 8>, BpShape<1, 128, 1, 1, 8>, BpShape<1, 256, 1, 1, 8>,
+    BpShape<1, 64, 2, 1, 4>, BpShape<1, 128, 2, 1, 4>, BpShape<1, 256, 2, 1, 4>,
+    BpShape<2, 64, 1, 2, 8>, BpShape<2, 128, 1, 2, 8>, BpShape<2, 256, 1, 2, 8>,
+    BpShape<2, 128, 1, 2, 4>, BpShape<2, 256, 1, 2, 4>, BpShape<2, 128, 2, 2, 4>,
+    BpShape<4, 64, 1, 2, 4>, BpShape<4, 128, 1, 2, 4>, BpShape<4, 64, 1, 2, 8>,
+    BpShape<4, 128, 1, 2, 8>, BpShape<4, 128, 1, 4, 4>, BpShape<4, 256, 1, 4, 4>,
+    BpShape<4, 128, 2, 2, 4>,
+    BpShape<8, 32, 1, 2, 8>, BpShape<8, 64, 1, 2, 8>, BpShape<8, 64, 1, 2, 4>,
+    BpShape<8, 128, 1, 2, 4>, BpShape<8, 64, 1, 4, 4>, BpShape<8, 128, 1, 4, 4>,
+    BpShape<16, 32, 1, 2, 8>, BpShape<16, 32, 1, 2, 4>, BpShape<16, 64, 1, 2, 8>,
+    BpShape<16, 32, 1, 4, 4>, BpShape<16, 64, 1, 4, 4>,
+    BpShape<32, 32, 1, 2, 8>, BpShape<32, 32, 1, 2, 4>, BpShape<32, 32, 1, 4, 4>>;
+
+template <class F, class... Bs>
+static bool any_shape(F&& f, std::tuple<Bs...>*) {
+    return (f(Bs{}) || ...);
 }
 
-void spmm_default_shape(int S, int* T, int* SL) {
-    *SL = 1;
-    *T = S <= 4 ? 128 : (S == 8 ? 64 : 32);
+template <class B>
+static bool shape_is(const B&, int S, const SpmmShape& sh) {
+    return B::S == S && B::T == sh.T && B::SL == sh.SL && B::V == sh.V && B::U == sh.U;
 }
 
-template <int S, int T, int SL>
-static hipError_t spmm_one(int nwg, const CsrDev& A, const double* P, double* Q, double* part,
-                           const DevState* st, hipStream_t stream) {
-    hipLaunchKernelGGL((k_spmm<S, T, SL>), dim3(nwg), dim3(MB_BLOCK), 0, stream, A.rowptr,
-                       A.colind, A.vals, A.n, P, Q, part, st);
-    return hipGetLastError();
+bool spmm_valid_shape(int S, const SpmmShape& sh) {
+    return any_shape([&](auto b) { return shape_is(b, S, sh); }, (BpShapes*)nullptr);
 }
 
-template <int S, int T>
-static hipError_t spmm_t(int SL, int nwg, const CsrDev& A, const double* P, double* Q,
-                         double* part, const DevState* st, hipStream_t stream) {
-    if constexpr (T * S <= 1024) {
-        if (SL == 1) return spmm_one<S, T, 1>(nwg, A, P, Q, part, st, stream);
-        if constexpr (S * 2 <= 64)
-            if (SL == 2) return spmm_one<S, T, 2>(nwg, A, P, Q, part, st, stream);
-    }
-    return hipErrorInvalidValue;
+int spmm_shape_list(int S, SpmmShape* out, int cap) {
+    int k = 0;
+    any_shape(
+        [&](auto b) {
+            using B = decltype(b);
+            if (B::S == S && k < cap) out[k++] = SpmmShape{B::T, B::SL, B::V, B::U};
+            return false;
+        },
+        (BpShapes*)nullptr);
+    return k;
 }
 
-template <int S>
-static hipError_t spmm_s(int T, int SL, int nwg, const CsrDev& A, const double* P, double* Q,
-                         double* part, const DevState* st, hipStream_t stream) {
-    switch (T) {
-        case 32: return spmm_t<S, 32>(SL, nwg, A, P, Q, part, st, stream);
-        case 64: return spmm_t<S, 64>(SL, nwg, A, P, Q, part, st, stream);
-        case 128: return spmm_t<S, 128>(SL, nwg, A, P, Q, part, st, stream);
-        case 256: return spmm_t<S, 256>(SL, nwg, A, P, Q, part, st, stream);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_spmm(int S, int T, int SL, int nwg, const CsrDev& A, const double* P, double* Q,
-                       double* part, const DevState* st, hipStream_t stream) {
-    if (!spmm_valid_shape(S, T, SL)) return hipErrorInvalidValue;
+SpmmShape spmm_default_shape(int S) {
     switch (S) {
-        case 1: return spmm_s<1>(T, SL, nwg, A, P, Q, part, st, stream);
-        case 2: return spmm_s<2>(T, SL, nwg, A, P, Q, part, st, stream);
-        case 4: return spmm_s<4>(T, SL, nwg, A, P, Q, part, st, stream);
-        case 8: return spmm_s<8>(T, SL, nwg, A, P, Q, part, st, stream);
-        case 16: return spmm_s<16>(T, SL, nwg, A, P, Q, part, st, stream);
-        case 32: return spmm_s<32>(T, SL, nwg, A, P, Q, part, st, stream);
+        case 1: return SpmmShape{128, 1, 1, 8};
+        case 2: return SpmmShape{128, 1, 2, 4};
+        case 4: return SpmmShape{128, 1, 2, 4};
+        case 8: return SpmmShape{64, 1, 2, 4};
+        case 16: return SpmmShape{32, 1, 2, 8};
+        default: return SpmmShape{32, 1, 2, 8};
     }
-    return hipErrorInvalidValue;
+}
+
+int spmm_lanes_per_row(int S, const SpmmShape& sh) { return S / sh.V * sh.SL; }
+
+hipError_t launch_spmm(int S, const SpmmShape& sh, int nwg, const CsrDev& A, const double* P,
+                       double* Q, double* part, const DevState* st, hipStream_t stream) {
+    hipError_t err = hipErrorInvalidValue;
+    any_shape(
+        [&](auto b) {
+            using B = decltype(b);
+            if (!shape_is(b, S, sh)) return false;
+            hipLaunchKernelGGL((k_spmm<B>), dim3(nwg), dim3(MB_BLOCK), 0, stream, A.rowptr,
+                               A.colind, A.vals, A.n, P, Q, part, st);
+            err = hipGetLastError();
+            return true;
+        },
+        (BpShapes*)nullptr);
+    return err;
 }
 
 // residual of the original system, one row per 8-lane group: b - A x, sum of squares

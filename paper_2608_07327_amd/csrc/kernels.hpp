@@ -30,11 +30,17 @@ inline int part_entries_ls(int S) { return tri_count(S + 1); }
 __host__ __device__ constexpr int stream_tile(int S) { return 1024 / S; }
 
 // ---- block product Q = A P (+ lower triangle of P^T Q per workgroup).
-// Shape: T rows per tile (32..256, T*S <= 1024), SL slots (lane groups) per row.
-hipError_t launch_spmm(int S, int T, int SL, int nwg, const CsrDev& A, const double* P, double* Q,
-                       double* part, const DevState* st, hipStream_t stream);
-bool spmm_valid_shape(int S, int T, int SL);
-void spmm_default_shape(int S, int* T, int* SL);
+// Shape: T rows per tile, SL slots per row, V adjacent columns per lane, U
+// gathers in flight per lane; only the compiled combinations are valid.
+struct SpmmShape {
+    int T = 0, SL = 0, V = 0, U = 0;
+};
+hipError_t launch_spmm(int S, const SpmmShape& sh, int nwg, const CsrDev& A, const double* P,
+                       double* Q, double* part, const DevState* st, hipStream_t stream);
+bool spmm_valid_shape(int S, const SpmmShape& sh);
+int spmm_shape_list(int S, SpmmShape* out, int cap);
+SpmmShape spmm_default_shape(int S);
+int spmm_lanes_per_row(int S, const SpmmShape& sh);
 
 // ---- dense product: Q partials over KSPLIT column ranges, then reduce + Gram
 enum DenseKind { DENSE_F64 = 0, DENSE_F32 = 1, DENSE_BF16 = 2 };

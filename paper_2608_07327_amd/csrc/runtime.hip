@@ -138,7 +138,7 @@ static mbpcg_status ensure_hist(Ctx& c, int64_t cap) {
 struct Plan {
     int s = 1, S = 1;
     DenseKind kind = DENSE_F64;
-    int T = 128, SL = 1;   // sparse block-product tile shape
+    SpmmShape sp;          // sparse block-product tile shape
     int nwg_prod = 1;    // partials of the block product's Gram
     int nwg_spmm = 1;    // grid of the sparse product
     int nwg_upd = 1;     // update / gram_nu grid
@@ -163,12 +163,9 @@ static Plan make_plan(Ctx& c, int s, DenseKind kind) {
     const int S = pl.S;
     const int cap = S >= 16 ? 512 : 1024;
     auto it = c.tune.find(S);
-    spmm_default_shape(S, &pl.T, &pl.SL);
-    if (it != c.tune.end() && it->second.T) {
-        pl.T = it->second.T;
-        pl.SL = it->second.SL;
-    }
-    const int64_t spmm_tiles = (c.n + pl.T - 1) / pl.T;
+    pl.sp = spmm_default_shape(S);
+    if (it != c.tune.end() && it->second.sh.T) pl.sp = it->second.sh;
+    const int64_t spmm_tiles = (c.n + pl.sp.T - 1) / pl.sp.T;
     pl.nwg_spmm = (it != c.tune.end() && it->second.nwg) ? std::min<int64_t>(it->second.nwg, NWG_MAX)
                                                          : round_grid(spmm_tiles, 2048);
     const int Tu = stream_tile(S);
@@ -203,9 +200,8 @@ static hipError_t launch_product(Ctx& c, const Plan& pl, const double* P, double
                                  const DevState* st, int S_override = 0) {
     const int S = S_override ? S_override : pl.S;
     if (!c.dense) {
-        int T = pl.T, SL = pl.SL;
-        if (S_override) spmm_default_shape(S, &T, &SL);
-        return launch_spmm(S, T, SL, pl.nwg_spmm, csr_of(c, true), P, Q, part, st, c.stream);
+        const SpmmShape sh = S_override ? spmm_default_shape(S) : pl.sp;
+        return launch_spmm(S, sh, pl.nwg_spmm, csr_of(c, true), P, Q, part, st, c.stream);
     }
     const void* A = pl.kind == DENSE_F64 ? (const void*)c.As : (const void*)c.Alo;
     hipError_t e = launch_dense_ap(S, pl.kind, c.n, A, c.n, c.Plo, P, c.qpart, pl.ksplit, st,
@@ -237,7 +233,7 @@ static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist) {
 }
 
 static mbpcg_status get_graph(Ctx& c, const Plan& pl, int m, int cg, hipGraphExec_t* out) {
-    auto key = std::make_tuple(cg * 2 + c.dense, pl.S, m, pl.T * 4 + pl.SL, pl.nwg_spmm, (int)pl.kind);
+    auto key = std::make_tuple(cg * 2 + c.dense, pl.S, m, pl.sp.T * 1000 + pl.sp.SL * 100 + pl.sp.V * 10 + pl.sp.U, pl.nwg_spmm, (int)pl.kind);
     auto it = c.graphs.find(key);
     if (it != c.graphs.end()) {
         *out = it->second;
@@ -731,7 +727,7 @@ mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, 
     CK(hipEventRecord(c.ev_a, c.stream));
     for (int i = 0; i < reps; ++i) {
         if (!c.dense) {
-            CK(launch_spmm(pl.S, pl.T, pl.SL, pl.nwg_spmm, csr_of(c, true), P, Q, c.part_a, c.st,
+            CK(launch_spmm(pl.S, pl.sp, pl.nwg_spmm, csr_of(c, true), P, Q, c.part_a, c.st,
                            c.stream));
         } else {
             CK(launch_dense_ap(pl.S, DENSE_F64, c.n, c.As, c.n, nullptr, P, c.qpart, pl.ksplit, c.st,
@@ -746,52 +742,74 @@ mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, 
     return MBPCG_OK;
 }
 
-mbpcg_status tune_entry(Ctx& c, int s, int* LPR_out, int* T_out, int* nwg_out, double* ms_out) {
+mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out) {
     CK(hipSetDevice(c.device));
     Plan pl = make_plan(c, s, DENSE_F64);
     const int S = pl.S;
     CKS(ensure_blocks(c, S));
     if (c.dense) {
-        if (LPR_out) *LPR_out = 0;
-        if (T_out) *T_out = 256;
-        if (nwg_out) *nwg_out = pl.nwg_dred;
-        if (ms_out) *ms_out = 0.0;
+        if (out) {
+            *out = mbpcg_tile_shape{};
+            out->tile_rows = 256;
+            out->workgroups = pl.nwg_dred;
+        }
         return MBPCG_OK;
     }
     if (!c.vals_s) CKS(setup_scaling(c, pl, c.bdev, 1));
     CK(hipMemsetAsync(c.P, 0, sizeof(double) * (size_t)c.n * S, c.stream));
     CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
-    Tuning best_t{pl.T, pl.SL, pl.nwg_spmm};
+    Tuning best_t{pl.sp, pl.nwg_spmm};
     double best = 1e30;
-    for (int T : {32, 64, 128, 256})
-        for (int SL : {1, 2}) {
-            if (!spmm_valid_shape(S, T, SL)) continue;
-            const int64_t tiles = (c.n + T - 1) / T;
-            for (int w : {1024, 2048, 4096}) {
-                const int nwg = round_grid(std::min<int64_t>(tiles, w), NWG_MAX);
-                if (w > 1024 && nwg < w) continue;  // already capped by the tile count
-                CK(launch_spmm(S, T, SL, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
-                CK(hipEventRecord(c.ev_a, c.stream));
-                const int reps = 5;
-                for (int r = 0; r < reps; ++r)
-                    CK(launch_spmm(S, T, SL, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st,
-                                   c.stream));
-                CK(hipEventRecord(c.ev_b, c.stream));
-                CK(hipEventSynchronize(c.ev_b));
-                float ms = 0.f;
-                CK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
-                const double avg = ms / reps;
-                if (avg < best) {
-                    best = avg;
-                    best_t = Tuning{T, SL, nwg};
-                }
+    SpmmShape shapes[32];
+    const int nsh = spmm_shape_list(S, shapes, 32);
+    for (int k = 0; k < nsh; ++k) {
+        const SpmmShape sh = shapes[k];
+        const int64_t tiles = (c.n + sh.T - 1) / sh.T;
+        for (int w : {1024, 2048, 4096}) {
+            const int nwg = round_grid(std::min<int64_t>(tiles, w), NWG_MAX);
+            if (w > 1024 && nwg < w) continue;  // already capped by the tile count
+            CK(launch_spmm(S, sh, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
+            CK(hipEventRecord(c.ev_a, c.stream));
+            const int reps = 5;
+            for (int r = 0; r < reps; ++r)
+                CK(launch_spmm(S, sh, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
+            CK(hipEventRecord(c.ev_b, c.stream));
+            CK(hipEventSynchronize(c.ev_b));
+            float ms = 0.f;
+            CK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
+            const double avg = ms / reps;
+            if (avg < best) {
+                best = avg;
+                best_t = Tuning{sh, nwg};
             }
         }
+    }
     c.tune[S] = best_t;
-    if (LPR_out) *LPR_out = S * best_t.SL;
-    if (T_out) *T_out = best_t.T;
-    if (nwg_out) *nwg_out = best_t.nwg;
-    if (ms_out) *ms_out = best;
+    if (out) {
+        *out = mbpcg_tile_shape{};
+        out->tile_rows = best_t.sh.T;
+        out->lanes_per_row = spmm_lanes_per_row(S, best_t.sh);
+        out->cols_per_lane = best_t.sh.V;
+        out->loads_in_flight = best_t.sh.U;
+        out->workgroups = best_t.nwg;
+        out->ms = best;
+    }
+    return MBPCG_OK;
+}
+
+mbpcg_status set_shape_entry(Ctx& c, int s, const mbpcg_tile_shape& t) {
+    const int S = padded_width(s);
+    if (t.cols_per_lane <= 0 || t.lanes_per_row <= 0) return MBPCG_ERR_UNSUPPORTED;
+    SpmmShape sh;
+    sh.T = t.tile_rows;
+    sh.V = t.cols_per_lane;
+    sh.U = t.loads_in_flight;
+    sh.SL = t.lanes_per_row * t.cols_per_lane / S;
+    if (sh.SL * S != t.lanes_per_row * t.cols_per_lane || !spmm_valid_shape(S, sh))
+        return MBPCG_ERR_UNSUPPORTED;
+    int nwg = 0;
+    if (t.workgroups > 0) nwg = std::min(t.workgroups, NWG_MAX);
+    c.tune[S] = Tuning{sh, nwg};
     return MBPCG_OK;
 }
 

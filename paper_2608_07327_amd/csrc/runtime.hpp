@@ -20,8 +20,7 @@ struct DevBuf {
 };
 
 struct Tuning {
-    int T = 0;     // rows per tile of the sparse block product
-    int SL = 0;    // slots (lane groups of S) per row
+    SpmmShape sh;  // tile shape of the sparse block product (T = 0: not tuned)
     int nwg = 0;   // workgroups of the block product
 };
 

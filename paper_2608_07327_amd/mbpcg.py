@@ -26,7 +26,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 EXPORTS = ("mbpcg_autotune", "mbpcg_default_params", "mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve",
            "mbpcg_cg_solve", "mbpcg_block_product", "mbpcg_time_block_product",
            "mbpcg_solve_batch", "mbpcg_stream_copy", "mbpcg_destroy", "mbpcg_status_str",
-           "mbpcg_last_error")
+           "mbpcg_last_error", "mbpcg_tile_shapes", "mbpcg_set_tile_shape")
 
 
 class Params(C.Structure):
@@ -59,6 +59,15 @@ class System(C.Structure):
                 ("x", C.c_void_p), ("s", C.c_int32)]
 
 
+class TileShape(C.Structure):
+    _fields_ = [("tile_rows", C.c_int32), ("lanes_per_row", C.c_int32),
+                ("cols_per_lane", C.c_int32), ("loads_in_flight", C.c_int32),
+                ("workgroups", C.c_int32), ("reserved", C.c_int32), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class MbpcgError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"mbpcg status {status}: {msg}")
@@ -89,8 +98,9 @@ def load():
     L.mbpcg_solve_batch.argtypes = [i32, C.POINTER(System), C.POINTER(Params), C.POINTER(Info),
                                     C.c_int, vp]
     L.mbpcg_stream_copy.argtypes = [vp, vp, i64, vp]
-    L.mbpcg_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
-                                 C.POINTER(C.c_double)]
+    L.mbpcg_autotune.argtypes = [vp, i32, C.POINTER(TileShape)]
+    L.mbpcg_tile_shapes.argtypes = [i32, C.POINTER(TileShape), i32, C.POINTER(i32)]
+    L.mbpcg_set_tile_shape.argtypes = [vp, i32, C.POINTER(TileShape)]
     L.mbpcg_destroy.argtypes = [vp]
     L.mbpcg_destroy.restype = None
     L.mbpcg_status_str.argtypes = [C.c_int]
@@ -99,7 +109,7 @@ def load():
     L.mbpcg_last_error.restype = C.c_char_p
     for f in ("mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve", "mbpcg_cg_solve",
               "mbpcg_block_product", "mbpcg_time_block_product", "mbpcg_solve_batch",
-              "mbpcg_stream_copy", "mbpcg_autotune"):
+              "mbpcg_stream_copy", "mbpcg_autotune", "mbpcg_tile_shapes", "mbpcg_set_tile_shape"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -276,11 +286,19 @@ class Solver:
 
     def autotune(self, s):
         """Time the block-product shapes for width s; later solves use the best.
-        Returns (lanes_per_row, tile_rows, workgroups, ms)."""
-        L, T, w, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
-        st = load().mbpcg_autotune(self._h, int(s), C.byref(L), C.byref(T), C.byref(w), C.byref(ms))
+        Returns the chosen shape as a dict (tile_rows, lanes_per_row,
+        cols_per_lane, loads_in_flight, workgroups, ms)."""
+        t = TileShape()
+        st = load().mbpcg_autotune(self._h, int(s), C.byref(t))
         _check(st, self._h, allow=(OK,))
-        return L.value, T.value, w.value, ms.value
+        return t.as_dict()
+
+    def set_tile_shape(self, s, shape):
+        """Fix the block-product shape for width s (a dict as returned by
+        tile_shapes() or autotune(); workgroups <= 0 means the default grid)."""
+        t = TileShape(**{k: int(v) for k, v in shape.items() if k != "ms"})
+        st = load().mbpcg_set_tile_shape(self._h, int(s), C.byref(t))
+        _check(st, self._h, allow=(OK,))
 
     def time_block_product(self, P, Q, s, reps=20):
         ms = C.c_double()
@@ -312,6 +330,15 @@ def solve_batch(systems, **kw):
     st = L.mbpcg_solve_batch(len(systems), arr, C.byref(p), infos, mem, _stream_ptr(None))
     _check(st, None, allow=(OK, NOT_CONVERGED, ERR_NOT_SPD, ERR_BREAKDOWN, ERR_NONFINITE))
     return st, [infos[i].as_dict() for i in range(len(systems))]
+
+
+def tile_shapes(s):
+    """Compiled block-product tile shapes for width s (list of dicts)."""
+    cnt = C.c_int32()
+    buf = (TileShape * 64)()
+    st = load().mbpcg_tile_shapes(int(s), buf, 64, C.byref(cnt))
+    _check(st, allow=(OK,))
+    return [buf[i].as_dict() for i in range(min(cnt.value, 64))]
 
 
 def stream_copy(dst, src, nbytes, stream=None):

@@ -106,3 +106,21 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(M, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         M.load()
+
+
+def test_tile_shapes_listing():
+    for s in (1, 2, 4, 8, 16, 32):
+        shapes = M.tile_shapes(s)
+        assert len(shapes) >= 3
+        for sh in shapes:
+            V, L = sh["cols_per_lane"], sh["lanes_per_row"]
+            assert V in (1, 2, 4) and s % V == 0
+            slots = L * V // s
+            assert slots in (1, 2) and slots * s == L * V
+            assert sh["tile_rows"] in (32, 64, 128, 256)
+            assert sh["loads_in_flight"] in (4, 8)
+    L = M.load()
+    cnt = C.c_int32()
+    assert L.mbpcg_tile_shapes(3, None, 0, C.byref(cnt)) == M.ERR_UNSUPPORTED
+    assert L.mbpcg_tile_shapes(0, None, 0, C.byref(cnt)) == M.ERR_INVALID_ARG
+    assert L.mbpcg_set_tile_shape(None, 4, None) == M.ERR_INVALID_ARG

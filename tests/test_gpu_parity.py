@@ -114,6 +114,70 @@ def test_block_product_and_gram_small(s):
     solver.close()
 
 
+def _hub_laplacian():
+    """Random graph Laplacian (avg degree 8, n = 3001) with node 0 joined to
+    2500 others: its row and the tiles holding it need many LDS chunks."""
+    import scipy.sparse as sp
+    rng = W.rng_for((73,))
+    L = W.graph_laplacian(3001, 8, 1e-2, rng).to_scipy().tolil()
+    nb = rng.choice(np.arange(1, 3001), 2500, replace=False)
+    for j in nb:
+        if L[0, j] == 0:
+            L[0, j] = L[j, 0] = -0.25
+            L[0, 0] += 0.25
+            L[j, j] += 0.25
+    L = sp.csr_matrix(L)
+    L.sort_indices()
+    return W.CSR(L.shape[0], L.indptr.astype(np.int32), L.indices.astype(np.int32),
+                 L.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("s", [1, 2, 4, 8, 16, 32])
+def test_block_product_every_tile_shape(s):
+    # every compiled (tile rows, lanes per row, columns per lane, loads in
+    # flight), on the default grid and on an 8-workgroup grid, against the
+    # oracle: two k-term sums in any order differ by at most 2 (k + 1) eps
+    # (|A| |P|) per entry, and the Gram likewise over n terms
+    A = _hub_laplacian()
+    P = W.rng_for((74, s)).standard_normal((A.n, s))
+    Qo = O.matmul_block(A, P)
+    Co = O.gram(P, Qo)
+    As = A.to_scipy()
+    k = np.diff(A.rowptr)[:, None]
+    eps = np.finfo(np.float64).eps
+    bq = 2 * (k + 1) * eps * (abs(As) @ np.abs(P))
+    bc = 2 * (A.n + 1) * eps * (np.abs(P).T @ np.abs(Qo)) + np.abs(P).T @ bq
+    solver = M.Solver.from_matrix(A)
+    Q = torch.empty((A.n, s), dtype=torch.float64, device=DEV)
+    Cm = torch.zeros((s, s), dtype=torch.float64, device=DEV)
+    Pd = dev(P)
+    shapes = M.tile_shapes(s)
+    assert shapes
+    for sh in shapes:
+        for wg in (0, 8):
+            say("tile shape", s, sh, wg)
+            solver.set_tile_shape(s, dict(sh, workgroups=wg))
+            Q.fill_(np.nan)
+            Cm.zero_()
+            solver.block_product(Pd, Q, Cm, s, precond=M.PRECOND_NONE)
+            Qg = Q.cpu().numpy()
+            assert np.all(np.abs(Qg - Qo) <= bq), (sh, wg)
+            Cg = np.tril(Cm.cpu().numpy())
+            assert np.all(np.abs(Cg - np.tril(Co)) <= np.tril(bc)), (sh, wg)
+    solver.close()
+
+
+def test_set_tile_shape_rejects_unknown_shapes():
+    A = W.poisson2d(16)
+    solver = M.Solver.from_matrix(A)
+    for bad in ({"tile_rows": 48, "lanes_per_row": 4, "cols_per_lane": 1, "loads_in_flight": 8},
+                {"tile_rows": 64, "lanes_per_row": 3, "cols_per_lane": 1, "loads_in_flight": 8},
+                {"tile_rows": 64, "lanes_per_row": 1, "cols_per_lane": 0, "loads_in_flight": 8}):
+        with pytest.raises(M.MbpcgError):
+            solver.set_tile_shape(4, bad)
+    solver.close()
+
+
 @pytest.mark.parametrize("s", [1, 4, 16, 32])
 def test_dense_block_product(s):
     n = 300
