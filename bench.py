@@ -16,6 +16,16 @@ the library's stream inside the timed solves (profile mode), and its
 algorithmic bytes per launch are 12 nnz + 4 (n + 1) + 16 n S (values and
 column indices, row pointers, one read of P and one write of Q, S = padded
 block width).
+
+Other workloads (--workload), each printing its own JSON line:
+  dense        FP64 SPD A = G G^T / n + 1e-3 I, n = 8192, s in {1,4,8,16,32},
+               against FP64 CG on the same GPU
+  dense-mixed  the same construction at n = 16384: FP32 and BF16 products
+               inside the FP64 iterative-refinement loop to 1e-10, s in
+               {8,16,32}, against FP64 CG to 1e-10
+  batch        512 random-graph Laplacians (avg degree 8, + 1e-2 I, n
+               log-uniform in [1e3, 2e5], s in {1,4,8}) in one persistent
+               launch, against the same systems solved one after another
 """
 from __future__ import annotations
 
@@ -85,13 +95,37 @@ def cpu_baseline(A, b, s, seed, iters_gpu, budget_s):
     }
 
 
+def copy_bandwidth(M, torch, dev):
+    """GB/s (read + write) of the library's streaming copy over 1 GiB: the
+    achievable HBM rate that the roofline fractions can be read against."""
+    nb = 1 << 30
+    src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    M.stream_copy(dst, src, nb)
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        M.stream_copy(dst, src, nb)   # default stream: the events above see it
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return round(2 * nb / (ms * 1e-3) / 1e9, 1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="diffusion3d",
+                    choices=("diffusion3d", "dense", "dense-mixed", "batch"))
     ap.add_argument("--s", type=int, default=DEFAULT_S)
     ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--n", type=int, default=0, help="dense order (default 8192 / 16384)")
+    ap.add_argument("--count", type=int, default=512, help="systems of the batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sweep", action="store_true")
@@ -104,7 +138,15 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "diffusion3d":
+        bench_sparse(args)
+    elif args.workload == "batch":
+        bench_batch(args)
+    else:
+        bench_dense(args, mixed=args.workload == "dense-mixed")
 
+
+def bench_sparse(args):
     import numpy as np
     import torch
 
@@ -195,6 +237,8 @@ def main():
                 "rel_res_true": inf["rel_res_true"],
             }
 
+    copy_gbs = copy_bandwidth(M, torch, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A, b, s, seed, it, args.cpu_seconds)
@@ -238,11 +282,197 @@ def main():
                        f"workgroups (autotuned); block product + Gram epilogue"),
             "avg_ms": round(spmm_ms, 5),
             "bytes_per_launch": bytes_alg,
+            "copy_GBps": copy_gbs,
         },
         "cpu_baseline": cpu,
         "sweep": sweep,
     }
     solver.close()
+    print(json.dumps(out))
+
+
+def dense_on_device(n, tag, torch, dev, shift=1e-3):
+    """workloads.dense_spd's recipe with the n^3 product done on the GPU: G iid
+    N(0,1) from the same seeded stream, A = G G^T / n with the lower triangle
+    mirrored (bitwise symmetric), + shift I.  Input generation only."""
+    from paper_2608_07327_amd import workloads as W
+    g = torch.as_tensor(W.rng_for(tag).standard_normal((n, n)), device=dev)
+    a = torch.mm(g, g.t().contiguous())
+    del g
+    a /= n
+    a = torch.tril(a)
+    a = a + torch.tril(a, -1).t()
+    a.diagonal().add_(shift)
+    torch.cuda.synchronize()
+    return a
+
+
+def bench_dense(args, mixed):
+    import numpy as np
+    import torch
+
+    from paper_2608_07327_amd import mbpcg as M
+    from paper_2608_07327_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    n = args.n or (16384 if mixed else 8192)
+    cfg = W.CFG_DENSE_MIXED if mixed else W.CFG_DENSE
+    A = dense_on_device(n, cfg, torch, dev)
+    bd = torch.as_tensor(W.rhs(n, cfg), device=dev)
+    x = torch.empty_like(bd)
+    solver = M.Solver.from_dense(A)
+    tol = 1e-10 if mixed else 1e-8
+    nrm_b = float(torch.linalg.vector_norm(bd))
+
+    def timed(fn, **kw):
+        for _ in range(args.warmup):
+            fn(bd, x=x, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(args.steps):
+            _, info = fn(bd, x=x, **kw)
+            infos.append(info)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        info = infos[-1]
+        # FP64 residual of the returned x, recomputed here with torch (reported, not used)
+        r = float(torch.linalg.vector_norm(bd - A @ x)) / nrm_b
+        return sec, info, r
+
+    cg_sec, cg_info, cg_r = timed(solver.cg_solve, tol=tol, precond=M.PRECOND_NONE, profile=1)
+    runs = {}
+    if mixed:
+        for prec, name in ((M.FP32_IR, "fp32"), (M.BF16_IR, "bf16")):
+            for sw in (8, 16, 32):
+                sec, info, r = timed(solver.solve, s=sw, precision=prec, ir_tol=tol,
+                                     precond=M.PRECOND_NONE, seed=W.uniform_block_seed(cfg, sw),
+                                     profile=1)
+                runs[f"{name}_s{sw}"] = (sec, info, r, sw, name)
+        sec, info, r = timed(solver.solve, s=16, tol=tol, precond=M.PRECOND_NONE,
+                             seed=W.uniform_block_seed(cfg, 16), profile=1)
+        runs["fp64_s16"] = (sec, info, r, 16, "fp64")
+    else:
+        for sw in (1, 4, 8, 16, 32):
+            sec, info, r = timed(solver.solve, s=sw, tol=tol, precond=M.PRECOND_NONE,
+                                 seed=W.uniform_block_seed(cfg, sw), profile=1)
+            runs[f"fp64_s{sw}"] = (sec, info, r, sw, "fp64")
+    ok = {k: v for k, v in runs.items() if v[1]["status"] == 0 and v[2] < 2 * tol}
+    pick = min(ok or runs, key=lambda k: (ok or runs)[k][0])
+    sec, info, r, sw, prec = runs[pick]
+    S = 1
+    while S < sw:
+        S *= 2
+    esz = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+    prod_ms = max(info["ms_spmm"] / max(1, info["spmm_launches"]), 1e-9)
+    bytes_prod = esz * n * n
+    flops_prod = 2.0 * n * n * S
+    peak_tf = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}[prec]
+    sweep = {}
+    for k, (sec_k, inf_k, r_k, sw_k, prec_k) in runs.items():
+        pm = max(inf_k["ms_spmm"] / max(1, inf_k["spmm_launches"]), 1e-9)
+        Sk = 1
+        while Sk < sw_k:
+            Sk *= 2
+        e = {"fp64": 8, "fp32": 4, "bf16": 2}[prec_k]
+        sweep[k] = {"seconds": round(sec_k, 5), "iterations": inf_k["iterations"],
+                    "outer_iterations": inf_k["outer_iterations"], "status": inf_k["status"],
+                    "rel_res_true": r_k, "product_ms": round(pm, 5),
+                    "product_GBps": round(e * n * n / (pm * 1e-3) / 1e9, 1),
+                    "product_TFLOPs": round(2.0 * n * n * Sk / (pm * 1e-3) / 1e12, 2)}
+    out = {
+        "metric": ("time-to-solution at rel.res 1e-10, mixed-precision iterative refinement "
+                   "(plain FP64 CG on the same GPU beside it)" if mixed else
+                   "time-to-solution at rel.res 1e-8, dense FP64 (plain FP64 CG on the same GPU "
+                   "beside it)"),
+        "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec if prec != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dense SPD A = G G^T/n + 1e-3 I, n={n}, b~N(0,1), no precond, "
+                               f"tol {tol:g}, best of {sorted(runs)}: {pick}", "n": n, "s": sw},
+        "iterations": info["iterations"], "rel_res_true": r,
+        "cg_seconds": round(cg_sec, 6), "cg_iterations": cg_info["iterations"],
+        "cg_rel_res_true": cg_r, "speedup_vs_cg": round(cg_sec / sec, 4),
+        "roofline": {
+            "bound": "hbm", "achieved": round(bytes_prod / (prod_ms * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(bytes_prod / (prod_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": None, "kernel": f"dense product A P ({prec}, S={S}) + reduce/Gram",
+            "avg_ms": round(prod_ms, 5), "bytes_per_launch": bytes_prod,
+            "mfma_TFLOPs": round(flops_prod / (prod_ms * 1e-3) / 1e12, 2),
+            "mfma_peak_TFLOPs": peak_tf,
+            "mfma_frac": round(flops_prod / (prod_ms * 1e-3) / 1e12 / peak_tf, 4),
+        },
+        "cpu_baseline": None,
+        "sweep": sweep,
+    }
+    solver.close()
+    print(json.dumps(out))
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_2608_07327_amd import mbpcg as M
+    from paper_2608_07327_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    systems = W.graph_laplacian_batch(count=args.count)
+    print(f"[bench] batch of {len(systems)} generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    items = []
+    for y in systems:
+        items.append({"n": y.A.n, "rowptr": torch.as_tensor(y.A.rowptr, device=dev),
+                      "colind": torch.as_tensor(y.A.colind, device=dev),
+                      "vals": torch.as_tensor(y.A.vals, device=dev),
+                      "b": torch.as_tensor(y.b, device=dev),
+                      "x": torch.empty(y.A.n, dtype=torch.float64, device=dev), "s": y.s})
+    seed = 500
+    for _ in range(args.warmup):
+        M.solve_batch(items, seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, infos = M.solve_batch(items, seed=seed)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] batched solve {sec:.4f} s", file=sys.stderr, flush=True)
+    # the same systems one after another through the single-system path
+    t0 = time.perf_counter()
+    seq_its = []
+    for i, (y, it) in enumerate(zip(systems, items)):
+        solver = M.Solver.from_csr(y.A.n, it["rowptr"], it["colind"], it["vals"])
+        _, inf = solver.solve(it["b"], s=y.s, seed=seed + i)
+        seq_its.append(inf["iterations"])
+        solver.close()
+        if (i + 1) % 64 == 0:
+            print(f"[bench] sequential {i + 1}/{len(systems)} {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    nnz = sum(y.A.nnz for y in systems)
+    n_tot = sum(y.A.n for y in systems)
+    worst = max(i["rel_res_true"] for i in infos)
+    out = {
+        "metric": "time-to-solution of the whole batch at rel.res 1e-8 (one persistent launch; "
+                  "the same systems solved one after another beside it)",
+        "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{len(systems)} random-graph Laplacians (avg degree 8) + 1e-2 I, "
+                               "n log-uniform in [1e3, 2e5], s in {1,4,8}, Jacobi, tol 1e-8",
+                   "systems": len(systems), "n_total": n_tot, "nnz_total": nnz},
+        "status": st, "converged": sum(1 for i in infos if i["status"] == 0),
+        "iterations_max": max(i["iterations"] for i in infos),
+        "iterations_sum": sum(i["iterations"] for i in infos),
+        "worst_rel_res_true": worst,
+        "sequential_seconds": round(seq, 4), "sequential_iterations_sum": sum(seq_its),
+        "speedup_vs_sequential": round(seq / sec, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
     print(json.dumps(out))
 
 

@@ -68,7 +68,9 @@ typedef struct {
     double tau;             /* deflation threshold of Cholesky QR; <= 0 means 1e-12      */
     mbpcg_precision precision;
     double ir_tol;          /* IR: outer tolerance (FP64 residual)                       */
-    double inner_tol;       /* IR: tolerance of each inner solve                         */
+    double inner_tol;       /* IR: tightest relative tolerance of an inner solve; each   */
+                            /* inner solve asks only for 0.5 ir_tol / (current outer     */
+                            /* residual), clamped to [inner_tol, 0.1]                    */
     int32_t max_outer;      /* IR: outer iteration cap                                   */
     double* history;        /* optional host array [max_iter]: ||R_h|| / ||b|| per step  */
     int32_t poll_every;     /* iterations per graph launch between host checks; 0 = auto */
@@ -95,7 +97,7 @@ typedef struct {
 } mbpcg_info;
 
 /* Fill *p with defaults: s=4, tol=1e-8, tol_initial=0, max_iter=100000,
- * JACOBI, seed=0, tau=1e-12, FP64, ir_tol=1e-10, inner_tol=1e-5, max_outer=50. */
+ * JACOBI, seed=0, tau=1e-12, FP64, ir_tol=1e-10, inner_tol=5e-6, max_outer=50. */
 void mbpcg_default_params(mbpcg_params* p);
 
 /* Create a context for sparse A (CSR, FP64 values, int32 rowptr[n+1] and

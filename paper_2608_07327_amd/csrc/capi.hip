@@ -43,7 +43,7 @@ void mbpcg_default_params(mbpcg_params* p) {
     p->tau = 1e-12;
     p->precision = MBPCG_FP64;
     p->ir_tol = 1e-10;
-    p->inner_tol = 1e-5;
+    p->inner_tol = 5e-6;
     p->max_outer = 50;
     p->history = nullptr;
     p->poll_every = 0;

@@ -166,8 +166,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
             const int64_t g = (r0 + rl) * S + j;
             W[g] = w;
             P[g] = p;
-            if (LO == DENSE_F32) static_cast<float*>(Plo)[g] = (float)p;
-            if (LO == DENSE_BF16) static_cast<__hip_bfloat16*>(Plo)[g] = __double2bfloat16(p);
+            if (LO == DENSE_F32) static_cast<float*>(Plo)[lo_pindex(LO, r0 + rl, j, S)] = (float)p;
+            if (LO == DENSE_BF16)
+                static_cast<__hip_bfloat16*>(Plo)[lo_pindex(LO, r0 + rl, j, S)] = __double2bfloat16(p);
         }
         __syncthreads();
     }
@@ -497,21 +498,29 @@ __global__ void k_copy_bytes(const unsigned char* __restrict__ src, unsigned cha
         dst[i] = src[i];
 }
 
-// copy of an n x S block rounded to FP32 or BF16 (initial block of a low-precision product)
+// n x S block rounded to FP32 or BF16 in the low-precision P layout, rows n ..
+// lo_rows_padded(n) zero (initial block of a low-precision product)
 template <int LO>
-__global__ void k_block_to_lo(int64_t count, const double* __restrict__ src, void* __restrict__ dst) {
+__global__ void k_block_to_lo(int64_t n, int S, const double* __restrict__ src,
+                              void* __restrict__ dst) {
+    const int64_t count = lo_rows_padded(n) * S;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        if (LO == DENSE_F32) static_cast<float*>(dst)[i] = (float)src[i];
-        else static_cast<__hip_bfloat16*>(dst)[i] = __double2bfloat16(src[i]);
+        const int64_t k = i / S;
+        const int j = (int)(i % S);
+        const double v = k < n ? src[i] : 0.0;
+        const int64_t o = lo_pindex(LO, k, j, S);
+        if (LO == DENSE_F32) static_cast<float*>(dst)[o] = (float)v;
+        else static_cast<__hip_bfloat16*>(dst)[o] = __double2bfloat16(v);
     }
 }
 
-// x += d (iterative refinement update, FP64)
-__global__ void k_axpy_ir(int64_t n, double* __restrict__ x, const double* __restrict__ d) {
+// x += alpha d (iterative refinement update, FP64; alpha = -1 takes it back)
+__global__ void k_axpy_ir(int64_t n, double* __restrict__ x, const double* __restrict__ d,
+                          double alpha) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        x[i] = x[i] + d[i];
+        x[i] = x[i] + alpha * d[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -671,21 +680,22 @@ hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* 
     return hipGetLastError();
 }
 
-hipError_t launch_block_to_lo(DenseKind kind, int64_t count, const double* src, void* dst,
+hipError_t launch_block_to_lo(DenseKind kind, int64_t n, int S, const double* src, void* dst,
                              hipStream_t s) {
+    const int64_t count = lo_rows_padded(n) * S;
     if (kind == DENSE_F32)
         hipLaunchKernelGGL(k_block_to_lo<DENSE_F32>, dim3(grid_for(count, 8192)), dim3(MB_BLOCK), 0,
-                           s, count, src, dst);
+                           s, n, S, src, dst);
     else if (kind == DENSE_BF16)
         hipLaunchKernelGGL(k_block_to_lo<DENSE_BF16>, dim3(grid_for(count, 8192)), dim3(MB_BLOCK),
-                           0, s, count, src, dst);
+                           0, s, n, S, src, dst);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_axpy_ir(int64_t n, double* x, const double* d, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy_ir, dim3(grid_for(n, 4096)), dim3(MB_BLOCK), 0, s, n, x, d);
+hipError_t launch_axpy_ir(int64_t n, double* x, const double* d, double alpha, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_ir, dim3(grid_for(n, 4096)), dim3(MB_BLOCK), 0, s, n, x, d, alpha);
     return hipGetLastError();
 }
 

@@ -9,8 +9,8 @@
 // order by k_dense_reduce, which also forms the Gram P^T Q of the tail.
 //
 //   FP64:  v_mfma_f64_16x16x4f64 on the caller's column-major A.
-//   FP32:  v_mfma_f32_16x16x4f32 on a row-major FP32 copy of A.
-//   BF16:  v_mfma_f32_16x16x32_bf16 on a row-major BF16 copy of A.
+//   FP32:  v_mfma_f32_16x16x4f32 on a tiled FP32 copy of A.
+//   BF16:  v_mfma_f32_16x16x32_bf16 on a tiled BF16 copy of A.
 // Low-precision kinds accumulate in FP32 inside a workgroup; partials are
 // stored and added in FP64.
 #include "kernels.hpp"
@@ -101,8 +101,14 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double*
             }
 }
 
-// FP32 copy of A, row-major.  Each lane loads four consecutive k of its row;
-// the four MFMAs of a step use the same permutation of k for A and P.
+// Low-precision products on the tiled copies (layouts in kernels.hpp).  A
+// wavefront streams its four 16-row tiles of A with one contiguous 1 KiB load
+// each per k-step and reads its P operand (one 16-byte vector per lane, the
+// P block is L2-resident) directly: no LDS and no barriers, so the loads of
+// the next steps overlap the matrix-core work of this one.
+//   FP32: v_mfma_f32_16x16x4f32, k-step 16 = four MFMAs on k = 16kc + 4lk + u.
+//   BF16: v_mfma_f32_16x16x32_bf16, k-step 32: lane (lk, li) holds
+//         A[row li][8 lk .. 8 lk + 7] and P[8 lk .. 8 lk + 7][column li].
 template <int S>
 __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* __restrict__ A,
                                                         const float* __restrict__ P,
@@ -110,61 +116,53 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* 
                                                         const DevState* __restrict__ st) {
     if (st && st->done) return;
     constexpr int CT = S >= 16 ? S / 16 : 1;
-    constexpr int KB = 64;
-    __shared__ float sB[KB * 16 * CT];
     const int rb = blockIdx.x / ksplit, ks = blockIdx.x % ksplit;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int64_t kchunk = (n + ksplit - 1) / ksplit;
-    const int64_t kbeg = ks * kchunk, kend = min(n, kbeg + kchunk);
-    const int64_t rbase = (int64_t)rb * DENSE_ROWS + wave * 64;
     const int li = l & 15, lk = l >> 4;
+    const int64_t NK = (n + 15) / 16, RT = (n + 15) / 16;
+    const int64_t sps = (NK + ksplit - 1) / ksplit;
+    const int64_t kc0 = ks * sps, kc1 = min(NK, kc0 + sps);
+    const f4* A4 = reinterpret_cast<const f4*>(A);
+    const f4* P4 = reinterpret_cast<const f4*>(P);
+    int64_t rt[4];
+    bool rok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        rt[t] = (int64_t)rb * 16 + wave * 4 + t;
+        rok[t] = rt[t] < RT;
+    }
     f4 acc[4][CT];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
-    const bool vec_ok = ((kend - kbeg) % 4 == 0) && (kbeg % 4 == 0) && (n % 4 == 0);
-
-    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
-        f4 a[KB / 16][4];
+    auto load = [&](int64_t kc, f4* a, f4* bv) {
 #pragma unroll
-        for (int q = 0; q < KB / 16; ++q) {
-            const int64_t k = k0 + 16 * q + 4 * lk;
+        for (int t = 0; t < 4; ++t)
+            a[t] = (rok[t] && kc < kc1) ? A4[(rt[t] * NK + kc) * 64 + l] : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t r = rbase + 16 * t + li;
-                f4 v = f4{0.f, 0.f, 0.f, 0.f};
-                if (r < n) {
-                    if (vec_ok && k + 3 < kend) {
-                        v = *reinterpret_cast<const f4*>(A + r * n + k);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (k + u < kend) v[u] = A[r * n + k + u];
-                    }
-                }
-                a[q][t] = v;
-            }
+        for (int c = 0; c < CT; ++c) {
+            const int j = 16 * c + li;
+            bv[c] = (j < S && kc < kc1) ? P4[(4 * kc + lk) * S + j] : f4{0.f, 0.f, 0.f, 0.f};
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < KB * 16 * CT; e += MB_BLOCK) {
-            const int kk = e / (16 * CT), j = e % (16 * CT);
-            const int64_t k = k0 + kk;
-            sB[e] = (k < kend && j < S) ? P[k * S + j] : 0.f;
-        }
-        __syncthreads();
+    };
+    auto mma = [&](const f4* a, const f4* bv) {
 #pragma unroll
-        for (int q = 0; q < KB / 16; ++q)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int c = 0; c < CT; ++c)
 #pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    const float bv = sB[(16 * q + 4 * lk + u) * (16 * CT) + 16 * c + li];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][t][u], bv, acc[t][c],
-                                                                         0, 0, 0);
-                }
+                for (int t = 0; t < 4; ++t)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bv[c][u], acc[t][c],
+                                                                     0, 0, 0);
+    };
+    // two k-steps per trip: both steps' loads are issued before either's MFMAs
+    for (int64_t kc = kc0; kc < kc1; kc += 2) {
+        f4 a0[4], b0[CT], a1[4], b1[CT];
+        load(kc, a0, b0);
+        load(kc + 1, a1, b1);
+        mma(a0, b0);
+        mma(a1, b1);
     }
     double* out = qpart + (int64_t)ks * n * S;
 #pragma unroll
@@ -173,15 +171,12 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* 
         for (int c = 0; c < CT; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t r = rbase + 16 * t + 4 * lk + v;
+                const int64_t r = rt[t] * 16 + 4 * lk + v;
                 const int j = 16 * c + li;
                 if (r < n && j < S) out[r * S + j] = (double)acc[t][c][v];
             }
 }
 
-// BF16 copy of A, row-major.  v_mfma_f32_16x16x32_bf16: lane l holds
-// A[row l%16][8*(l/16) .. +7] and P[8*(l/16) .. +7][col l%16]; P is kept
-// transposed in LDS so that each lane's eight values are contiguous.
 template <int S>
 __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16* __restrict__ A,
                                                          const __bf16* __restrict__ P,
@@ -189,63 +184,53 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16
                                                          const DevState* __restrict__ st) {
     if (st && st->done) return;
     constexpr int CT = S >= 16 ? S / 16 : 1;
-    constexpr int KB = 128;
-    constexpr int KBP = KB + 8;  // padded LDS row (keeps 16-byte alignment)
-    __shared__ __attribute__((aligned(16))) __bf16 sBt[16 * CT * KBP];
     const int rb = blockIdx.x / ksplit, ks = blockIdx.x % ksplit;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int64_t kchunk = (n + ksplit - 1) / ksplit;
-    const int64_t kbeg = ks * kchunk, kend = min(n, kbeg + kchunk);
-    const int64_t rbase = (int64_t)rb * DENSE_ROWS + wave * 64;
     const int li = l & 15, lk = l >> 4;
+    const int64_t NK = (n + 31) / 32, RT = (n + 15) / 16;
+    const int64_t sps = (NK + ksplit - 1) / ksplit;
+    const int64_t kc0 = ks * sps, kc1 = min(NK, kc0 + sps);
+    const bf8* A8 = reinterpret_cast<const bf8*>(A);
+    const bf8* P8 = reinterpret_cast<const bf8*>(P);
+    bf8 zero8;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) zero8[u] = (__bf16)0.0f;
+    int64_t rt[4];
+    bool rok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        rt[t] = (int64_t)rb * 16 + wave * 4 + t;
+        rok[t] = rt[t] < RT;
+    }
     f4 acc[4][CT];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
-    const bool vec_ok = ((kend - kbeg) % 8 == 0) && (kbeg % 8 == 0) && (n % 8 == 0);
-    const __bf16 zero = (__bf16)0.0f;
-
-    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
-        bf8 a[KB / 32][4];
+    auto load = [&](int64_t kc, bf8* a, bf8* bv) {
 #pragma unroll
-        for (int q = 0; q < KB / 32; ++q) {
-            const int64_t k = k0 + 32 * q + 8 * lk;
+        for (int t = 0; t < 4; ++t)
+            a[t] = (rok[t] && kc < kc1) ? A8[(rt[t] * NK + kc) * 64 + l] : zero8;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t r = rbase + 16 * t + li;
-                bf8 v;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = zero;
-                if (r < n) {
-                    if (vec_ok && k + 7 < kend) {
-                        v = *reinterpret_cast<const bf8*>(A + r * n + k);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < 8; ++u)
-                            if (k + u < kend) v[u] = A[r * n + k + u];
-                    }
-                }
-                a[q][t] = v;
-            }
+        for (int c = 0; c < CT; ++c) {
+            const int j = 16 * c + li;
+            bv[c] = (j < S && kc < kc1) ? P8[(4 * kc + lk) * S + j] : zero8;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < KB * 16 * CT; e += MB_BLOCK) {
-            const int kk = e / (16 * CT), j = e % (16 * CT);
-            const int64_t k = k0 + kk;
-            sBt[j * KBP + kk] = (k < kend && j < S) ? P[k * S + j] : zero;
-        }
-        __syncthreads();
+    };
+    auto mma = [&](const bf8* a, const bf8* bv) {
 #pragma unroll
-        for (int q = 0; q < KB / 32; ++q)
+        for (int c = 0; c < CT; ++c)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const bf8 bv =
-                    *reinterpret_cast<const bf8*>(&sBt[(16 * c + li) * KBP + 32 * q + 8 * lk]);
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q][t], bv, acc[t][c], 0, 0, 0);
-            }
+            for (int t = 0; t < 4; ++t)
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bv[c], acc[t][c], 0, 0, 0);
+    };
+    // two k-steps per trip: both steps' loads are issued before either's MFMAs
+    for (int64_t kc = kc0; kc < kc1; kc += 2) {
+        bf8 a0[4], b0[CT], a1[4], b1[CT];
+        load(kc, a0, b0);
+        load(kc + 1, a1, b1);
+        mma(a0, b0);
+        mma(a1, b1);
     }
     double* out = qpart + (int64_t)ks * n * S;
 #pragma unroll
@@ -254,7 +239,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16
         for (int c = 0; c < CT; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t r = rbase + 16 * t + 4 * lk + v;
+                const int64_t r = rt[t] * 16 + 4 * lk + v;
                 const int j = 16 * c + li;
                 if (r < n && j < S) out[r * S + j] = (double)acc[t][c][v];
             }
@@ -346,30 +331,35 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_resid_reduce(int64_t n, int 
     }
 }
 
-// low-precision, row-major copy of column-major A (round to nearest even)
+// FP64 column-major A -> tiled low-precision layout (round to nearest even).
+// One thread writes one lane vector of one tile; the 16 lanes li of a k-group
+// read 16 consecutive rows of a column (128 contiguous bytes).
 template <int KIND>
 __global__ void k_cast_dense(int64_t n, const double* __restrict__ A, int64_t lda,
                              void* __restrict__ out) {
-    __shared__ double tile[64][65];
-    const int64_t nt = (n + 63) / 64;
-    for (int64_t tb = blockIdx.x; tb < nt * nt; tb += gridDim.x) {
-        const int64_t tr = tb / nt, tc = tb % nt;  // tile of rows tr*64.., cols tc*64..
-        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-        for (int cc = ty; cc < 64; cc += 4) {
-            const int64_t c = tc * 64 + cc, r = tr * 64 + tx;
-            tile[cc][tx] = (c < n && r < n) ? A[c * lda + r] : 0.0;
+    constexpr int VL = lo_vec(KIND), KS = lo_kstep(KIND);
+    const int64_t NK = (n + KS - 1) / KS, RT = (n + 15) / 16;
+    const int64_t total = RT * NK * 64;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < total;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(v & 63);
+        const int64_t tile = v >> 6;
+        const int64_t rt = tile / NK, kc = tile % NK;
+        const int64_t r = rt * 16 + (lane & 15);
+        const int64_t k = kc * KS + (int64_t)(lane >> 4) * VL;
+#pragma unroll
+        for (int u = 0; u < VL; ++u) {
+            const double x = (r < n && k + u < n) ? A[(k + u) * lda + r] : 0.0;
+            if (KIND == DENSE_F32) static_cast<float*>(out)[v * VL + u] = (float)x;
+            else static_cast<__hip_bfloat16*>(out)[v * VL + u] = __double2bfloat16(x);
         }
-        __syncthreads();
-        for (int rr = ty; rr < 64; rr += 4) {
-            const int64_t r = tr * 64 + rr, c = tc * 64 + tx;
-            if (r < n && c < n) {
-                const double v = tile[tx][rr];
-                if (KIND == DENSE_F32) static_cast<float*>(out)[r * n + c] = (float)v;
-                else static_cast<__hip_bfloat16*>(out)[r * n + c] = __double2bfloat16(v);
-            }
-        }
-        __syncthreads();
     }
+}
+
+size_t dense_lo_bytes(DenseKind kind, int64_t n) {
+    const int KS = lo_kstep(kind);
+    const size_t rows = (size_t)((n + 15) / 16) * 16, cols = (size_t)((n + KS - 1) / KS) * KS;
+    return rows * cols * (kind == DENSE_F32 ? 4 : 2);
 }
 
 __global__ void k_diag_dense(int64_t n, const double* __restrict__ A, int64_t lda, int jacobi,
@@ -438,8 +428,7 @@ hipError_t launch_dense_reduce(int S, int64_t n, int ksplit, const double* qpart
 
 hipError_t launch_cast_dense(DenseKind kind, int64_t n, const double* A, int64_t lda, void* out,
                              hipStream_t stream) {
-    const int64_t nt = (n + 63) / 64;
-    const int g = (int)std::min<int64_t>(nt * nt, 8192);
+    const int g = 8192;
     if (kind == DENSE_F32)
         hipLaunchKernelGGL(k_cast_dense<DENSE_F32>, dim3(g), dim3(MB_BLOCK), 0, stream, n, A, lda, out);
     else if (kind == DENSE_BF16)

@@ -52,7 +52,24 @@ int dense_nwg_rows(int64_t n);
 hipError_t launch_dense_reduce(int S, int64_t n, int ksplit, const double* qpart, const double* P,
                                double* Q, double* part, int nwg, const DevState* st,
                                hipStream_t stream);
-// FP64 column-major A -> low precision, row-major (transposed), round to nearest even
+// Low-precision operands of the dense product, stored in the matrix cores'
+// operand order so that every wavefront load is one contiguous 1 KiB run:
+//  A: 16-row x KS-column tiles (KS = 16 for FP32, 32 for BF16), tile (rt, kc)
+//     at ((rt * ceil(n/KS) + kc) * 64 + lane) * VL elements, lane = 16 lk + li
+//     holding A[16 rt + li][KS kc + VL lk + u], u < VL (VL = 4 FP32, 8 BF16);
+//     rows and columns beyond n are zero.
+//  P: groups of VL consecutive rows, element (k, j) at
+//     (k / VL) * S * VL + j * VL + k % VL; rows are padded to a multiple of 32
+//     with zeros.
+__host__ __device__ constexpr int lo_vec(int kind) { return kind == DENSE_F32 ? 4 : 8; }
+__host__ __device__ constexpr int lo_kstep(int kind) { return kind == DENSE_F32 ? 16 : 32; }
+__host__ __device__ inline int64_t lo_pindex(int kind, int64_t k, int j, int S) {
+    const int vl = lo_vec(kind);
+    return (k / vl) * S * vl + (int64_t)j * vl + k % vl;
+}
+__host__ __device__ inline int64_t lo_rows_padded(int64_t n) { return (n + 31) / 32 * 32; }
+size_t dense_lo_bytes(DenseKind kind, int64_t n);
+// FP64 column-major A -> the tiled low-precision layout, round to nearest even
 hipError_t launch_cast_dense(DenseKind kind, int64_t n, const double* A, int64_t lda, void* out,
                              hipStream_t stream);
 // r = b - (sum of the ksplit partials of A x) and partial sums of r^2 (S = 1)
@@ -119,9 +136,10 @@ hipError_t launch_tail_cg(int nwg_u, const double* part_u, int nwg_s, const doub
 hipError_t launch_state_init(DevState* st, int s, int max_iter, double tol, double tol0,
                              double tau, int n_hist, hipStream_t stream);
 
-hipError_t launch_block_to_lo(DenseKind kind, int64_t count, const double* src, void* dst,
+// n x S block -> the low-precision P layout (padding rows zero)
+hipError_t launch_block_to_lo(DenseKind kind, int64_t n, int S, const double* src, void* dst,
                              hipStream_t s);
-hipError_t launch_axpy_ir(int64_t n, double* x, const double* d, hipStream_t s);
+hipError_t launch_axpy_ir(int64_t n, double* x, const double* d, double alpha, hipStream_t s);
 // sqrt of a reduced sum of squares into st->res_norm
 hipError_t launch_tail_norm(int nwg, const double* part, DevState* st, hipStream_t s);
 // reduce Gram partials (lower triangle) into C (S x S row-major, i >= j)

@@ -107,7 +107,7 @@ static mbpcg_status ensure_blocks(Ctx& c, int S) {
     const size_t bb = sizeof(double) * (size_t)c.n * S;
     DALLOC(c.U, bb); DALLOC(c.Y, bb); DALLOC(c.X0, bb); DALLOC(c.Xt, bb);
     DALLOC(c.R, bb); DALLOC(c.W, bb); DALLOC(c.P, bb); DALLOC(c.Q, bb);
-    DALLOC(c.Plo, sizeof(float) * (size_t)c.n * S);
+    DALLOC(c.Plo, sizeof(float) * (size_t)lo_rows_padded(c.n) * S);
     int e = std::max(part_entries_update(S), part_entries_ls(S));
     e = std::max(e, 4);
     c.part_elems = (int64_t)NWG_MAX * e;
@@ -453,7 +453,7 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     if (Udev) CK(launch_pad_block(S, c.n, s, Udev, c.U, c.stream));
     else CK(launch_uniform(S, c.n, s, p.seed, c.U, c.stream));
     // line X^0: Y = A~ U, ||Y||_F
-    if (kind != DENSE_F64) CK(launch_block_to_lo(kind, c.n * S, c.U, c.Plo, c.stream));
+    if (kind != DENSE_F64) CK(launch_block_to_lo(kind, c.n, S, c.U, c.Plo, c.stream));
     CK(launch_product(c, pl, c.U, c.Y, nullptr, c.st));
     CK(launch_ynorm(S, pl.nwg_e, c.n, c.Y, c.part_a, c.stream));
     CK(launch_tail_gamma(pl.nwg_e, c.part_c, pl.nwg_e, c.part_a, c.st, c.stream));
@@ -591,10 +591,9 @@ static mbpcg_status run_ir(Ctx& c, const double* b, double* x, const double* Ude
     const int jac = p.precond == MBPCG_PRECOND_JACOBI;
     CK(launch_state_init(c.st, p.s, 1, p.tol, p.tol, 1e-12, 0, c.stream));
     CKS(setup_scaling(c, pl, b, jac));
-    const size_t esz = kind == DENSE_F32 ? sizeof(float) : 2;
     if (!c.Alo || c.alo_kind != kind) {
         dfree(c.Alo);
-        DALLOC(c.Alo, esz * (size_t)c.n * c.n);
+        DALLOC(c.Alo, dense_lo_bytes(kind, c.n));
         c.alo_kind = kind;
         drop_graphs(c);
     }
@@ -615,14 +614,30 @@ static mbpcg_status run_ir(Ctx& c, const double* b, double* x, const double* Ude
         return MBPCG_OK;
     }
     mbpcg_params inner = p;
-    inner.tol = p.inner_tol;
     inner.tol_initial = 0.0;
     inner.history = nullptr;
     mbpcg_status last = MBPCG_OK;
     double rel = 1.0;
+    bool stalled = false;
     int outer = 0;
     const int max_outer = p.max_outer > 0 ? p.max_outer : 50;
+    const double floor_tol = p.inner_tol > 0 ? p.inner_tol : 5e-6;
+    // the FP64 residual of the new x, into rvec and rel
+    auto fp64_residual = [&]() -> mbpcg_status {
+        CK(launch_dense_ap(1, DENSE_F64, c.n, c.A, c.n, nullptr, c.xacc, c.qpart, pl.ksplit, nullptr,
+                           c.stream));
+        CK(launch_dense_resid_reduce(c.n, pl.ksplit, c.qpart, b, c.rvec, c.part_a, pl.nwg_e,
+                                     c.stream));
+        CK(launch_tail_norm(pl.nwg_e, c.part_a, c.st, c.stream));
+        CKS(read_state(c));
+        rel = c.st_host->res_norm / bnorm;
+        return MBPCG_OK;
+    };
     for (outer = 1; outer <= max_outer; ++outer) {
+        // an inner solve needs to reduce r only as far as this outer step can
+        // finish the job: ir_tol / rel with a factor 2 of margin, never looser
+        // than 0.1 and never tighter than inner_tol
+        inner.tol = std::min(0.1, std::max(floor_tol, 0.5 * p.ir_tol / rel));
         inner.seed = p.seed + (uint64_t)(outer - 1) * 7919u;
         mbpcg_info ii;
         memset(&ii, 0, sizeof(ii));
@@ -630,6 +645,9 @@ static mbpcg_status run_ir(Ctx& c, const double* b, double* x, const double* Ude
         last = run_mbpcg(c, c.rvec, c.xdev, outer == 1 ? Udev : nullptr, inner, kind, false, ii);
         info.iterations += ii.iterations;
         info.deflations += ii.deflations;
+        info.ms_spmm += ii.ms_spmm;
+        info.spmm_launches += ii.spmm_launches;
+        for (int k = 0; k < 8; ++k) info.ms_phase[k] += ii.ms_phase[k];
         info.best_column = ii.best_column;
         info.final_width = ii.final_width;
         info.used_fallback = ii.used_fallback;
@@ -638,17 +656,21 @@ static mbpcg_status run_ir(Ctx& c, const double* b, double* x, const double* Ude
         if (last == MBPCG_ERR_HIP || last == MBPCG_ERR_OOM) return last;
         if (last == MBPCG_ERR_NOT_SPD || last == MBPCG_ERR_NONFINITE) break;
         // x += d;  r = b - A x with the FP64 A
-        CK(launch_axpy_ir(c.n, c.xacc, c.xdev, c.stream));
-        CK(launch_dense_ap(1, DENSE_F64, c.n, c.A, c.n, nullptr, c.xacc, c.qpart, pl.ksplit, nullptr,
-                           c.stream));
-        CK(launch_dense_resid_reduce(c.n, pl.ksplit, c.qpart, b, c.rvec, c.part_a, pl.nwg_e,
-                                     c.stream));
-        CK(launch_tail_norm(pl.nwg_e, c.part_a, c.st, c.stream));
-        CKS(read_state(c));
-        rel = c.st_host->res_norm / bnorm;
-        info.rel_res_true = rel;
+        const double rel_before = rel;
+        CK(launch_axpy_ir(c.n, c.xacc, c.xdev, 1.0, c.stream));
+        CKS(fp64_residual());
+        if (!(rel < rel_before)) {
+            // no progress (the low-precision operator is too far from A for
+            // this system): take the step back and stop with the best x
+            CK(launch_axpy_ir(c.n, c.xacc, c.xdev, -1.0, c.stream));
+            CKS(fp64_residual());
+            stalled = true;
+            break;
+        }
         if (!(rel > p.ir_tol)) break;
     }
+    info.rel_res_true = rel;
+    if (stalled && last == MBPCG_OK) last = MBPCG_NOT_CONVERGED;
     if (x) CK(hipMemcpyAsync(x, c.xacc, sizeof(double) * c.n, hipMemcpyDeviceToDevice, c.stream));
     CK(hipStreamSynchronize(c.stream));
     info.outer_iterations = std::min(outer, max_outer);

@@ -40,7 +40,7 @@ struct Ctx {
     double* vals_s = nullptr;   // scaled values
     double* A = nullptr;        // dense original, column-major, lda = n
     double* As = nullptr;       // dense scaled (== A when no scaling)
-    void* Alo = nullptr;        // dense low-precision row-major copy
+    void* Alo = nullptr;        // dense low-precision copy in the tiled operand layout
     DenseKind alo_kind = DENSE_F64;
     int scaled_jacobi = -1;     // which scaling vals_s / As hold
 

@@ -385,8 +385,30 @@ def test_bf16_iterative_refinement_reports_honestly():
                            ir_tol=1e-10, inner_tol=1e-2, max_outer=30, seed=4)
     x = x.cpu().numpy()
     truth = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
-    # whatever the outcome, the reported FP64 residual is the true one
+    # whatever the outcome, the reported FP64 residual is the true one, and an
+    # outer step that does not lower it is taken back (never worse than x = 0)
     assert abs(truth - info["rel_res_true"]) <= 1e-6 * max(truth, 1e-12) + 1e-14
+    assert truth <= 1.0
     if info["status"] == 0:
         assert truth <= 2e-10
+    solver.close()
+
+
+@pytest.mark.parametrize("prec,n,s", [("fp32", 300, 4), ("fp32", 613, 32), ("bf16", 300, 16),
+                                      ("bf16", 613, 8)])
+def test_low_precision_products_on_ragged_orders(prec, n, s):
+    # orders that are not multiples of the 16/32-wide tiles of the
+    # low-precision copies, one and two 16-column MFMA tiles; a system
+    # conditioned so that even BF16 products make the refinement contract
+    A = W.tiny_spd(n, 20.0, tag=(4, 54, n))
+    b = W.rng_for((4, 55, n)).standard_normal(n)
+    say("low-precision IR", prec, n, s)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(dev(b), s=s, precision=M.FP32_IR if prec == "fp32" else M.BF16_IR,
+                           precond=M.PRECOND_NONE, ir_tol=1e-10, seed=5)
+    x = x.cpu().numpy()
+    truth = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert info["status"] == 0, info
+    assert truth <= 2e-10
+    assert abs(truth - info["rel_res_true"]) <= 1e-6 * truth + 1e-14
     solver.close()
