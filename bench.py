@@ -45,7 +45,7 @@ DEFAULT_S = 4
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("k_sparse.hip", "dev_common.hpp"):
+    for f in ("k_sparse.hip", "dev_common.hpp", "dev_spmm.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2608_07327_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -135,7 +135,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "diffusion3d":
@@ -474,6 +474,8 @@ def bench_batch(args):
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out))
+    if out["converged"] != len(systems):
+        sys.exit(1)
 
 
 if __name__ == "__main__":

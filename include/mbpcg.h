@@ -43,7 +43,7 @@ typedef enum {
     MBPCG_ERR_NONFINITE = -4,    /* NaN/Inf in the input or the iteration       */
     MBPCG_ERR_HIP = -5,          /* a HIP runtime call failed (see last_error)  */
     MBPCG_ERR_OOM = -6,
-    MBPCG_ERR_UNSUPPORTED = -7   /* e.g. s > 32, or a mode this build lacks     */
+    MBPCG_ERR_UNSUPPORTED = -7   /* e.g. s > 32, or a mode the library lacks    */
 } mbpcg_status;
 
 typedef enum { MBPCG_PRECOND_NONE = 0, MBPCG_PRECOND_JACOBI = 1 } mbpcg_precond;
@@ -124,7 +124,7 @@ mbpcg_status mbpcg_cg_solve(mbpcg_ctx ctx, const double* b, double* x, mbpcg_mem
  * measurement: Q = A~ P and C = P^T Q for the scaled matrix A~ = D^-1 A D^-1
  * (D = I with precond NONE), P and Q row-major n x s on the device, C row-major
  * s x s on the device (lower triangle i >= j written; upper left untouched).
- * Alg. 1, line Xi. */
+ * This is the A P and P^T A P of Alg. 1. */
 mbpcg_status mbpcg_block_product(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond,
                                  const double* P, double* Q, double* C);
 

@@ -114,7 +114,7 @@ static double dot_strided(int64_t n, const double* x, int64_t incx, const double
 }
 
 /* ---------------------------------------------------------------------------
- * Random initial block (Alg. 1, line U; Sec. 2 states only that the entries
+ * Random initial block (Alg. 1, the random block U; Sec. 2 states only that the entries
  * are iid Uniform(-1, 1)).  Reading taken: SplitMix64 (Steele, Lea & Flood,
  * "Fast splittable pseudorandom number generators", OOPSLA 2014) used as a
  * counter-based generator: output k of the stream seeded with `seed`.
@@ -138,7 +138,7 @@ void or_uniform_block(uint64_t seed, int64_t n, int s, double* U)
 }
 
 /* ---------------------------------------------------------------------------
- * Block product Y = A X (Alg. 1, lines X^0 and Xi: A U and A P).  CSR rows
+ * Block product Y = A X (Alg. 1: A U for the initial block and A P in every iteration).  CSR rows
  * are summed in stored order; a dense product sums over columns in order.
  * ------------------------------------------------------------------------- */
 void or_matmul_block(const or_matrix* A, int k, const double* X, double* Y)
@@ -166,7 +166,7 @@ void or_matmul_block(const or_matrix* A, int k, const double* X, double* Y)
     }
 }
 
-/* C = X^T Y (Alg. 1, line Xi: P^T A P; the Cholesky QR Grams) */
+/* C = X^T Y (Alg. 1: P^T A P of the step matrix Xi; the Cholesky QR Grams) */
 void or_gram(int64_t n, int k1, const double* X, int k2, const double* Y, double* C)
 {
     reducer R;
@@ -283,7 +283,7 @@ int or_cholqr_deflate(int64_t n, int m, const double* V, double tau,
 }
 
 /* ---------------------------------------------------------------------------
- * Least squares min_c ||b - B c|| (Alg. 1, line hat_c).  The paper writes
+ * Least squares min_c ||b - B c|| (Alg. 1, the combination c^ of the termination).  The paper writes
  * the normal equations and reports that forming B^T B overflows or loses
  * accuracy; the oracle computes the same minimiser by Householder QR.
  * ------------------------------------------------------------------------- */
@@ -481,7 +481,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
 
     for (int64_t r = 0; r < n; ++r) bbar[r] = b[r] / d[r];
 
-    /* lines U, X^0: X0 = (||B||_F / ||A U||_F) U with B = [b ... b] */
+    /* random block and initial guess: X0 = (||B||_F / ||A U||_F) U with B = [b ... b] */
     if (p->U) memcpy(U, p->U, sizeof(double) * blk);
     else or_uniform_block(p->seed, n, s, U);
     or_matmul_block(As, s, U, Y);
@@ -499,14 +499,14 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
         red_finish(&Rf, &ny2);
     }
     double gamma = sqrt((double)s * nb2) / sqrt(ny2);
-    /* lines tilde_B, tilde_X^0, R^0: A X0 is taken as gamma * (A U) */
+    /* scaled right-hand sides, X~0 = 0 and R0: A X0 is taken as gamma * (A U) */
     for (size_t e = 0; e < blk; ++e) {
         X0[e] = gamma * U[e];
         R[e] = bbar[e / (size_t)s] - gamma * Y[e];
     }
     if (!isfinite(gamma)) { rc = OR_ERR_NONFINITE; goto fallback_none; }
 
-    /* line W^0_Sigma^0, P^0 */
+    /* first Cholesky QR (W0, Sigma0) and P0 = W0 */
     int m = or_cholqr_deflate(n, s, R, tau, W, Z, keep);
     inf.deflations = s - m;
     memcpy(Sig, Z, sizeof(double) * (size_t)(m * s));
@@ -530,7 +530,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
         converged = 1;
     }
     for (it = 1; !converged && it <= p->max_iter; ++it) {
-        /* line Xi */
+        /* step matrix Xi = (P^T A P)^-1 */
         or_matmul_block(As, m, P, Q);
         or_gram(n, m, P, m, Q, C);
         if (or_cholesky(m, C, L) != 0) { rc = OR_ERR_NOT_SPD; it -= 1; break; }
@@ -541,7 +541,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
                 for (int c = 0; c < m; ++c) acc += Xi[a * m + c] * Sig[c * s + j];
                 al[a * s + j] = acc;
             }
-        /* lines tilde_X, R */
+        /* X~ += P alpha, R -= (A P) alpha */
         for (int64_t r = 0; r < n; ++r)
             for (int j = 0; j < s; ++j) {
                 double tx = 0.0, tr = 0.0;
@@ -552,7 +552,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
                 Xt[r * s + j] = Xt[r * s + j] + tx;
                 R[r * s + j] = R[r * s + j] - tr;
             }
-        /* line h: best column in the original residual norm */
+        /* best column h in the original residual norm */
         residual_norms(n, s, R, d, p->ls_scaled, nu);
         double bref = p->ls_scaled ? sqrt(nb2) : bnorm;
         h = 0;
@@ -573,9 +573,9 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
             p->prop1_gap[it - 1] = sqrt(g2) / sqrt((double)s * nb2);
         }
         if (!isfinite(nu_h)) { rc = OR_ERR_NONFINITE; break; }
-        /* lines initial_tolerance .. convergence_tolerance */
+        /* stop test and least-squares termination */
         if (nu_h < tol0) {
-            /* line hat_B, hat_c, r: B^ = B - R in the original space */
+            /* B^ = B - R in the original space, c^ and its residual */
             double* Bh = V;
             for (int64_t r = 0; r < n; ++r)
                 for (int j = 0; j < s; ++j) {
@@ -604,7 +604,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
             if (finite && rel_ls < tol) { converged = 1; accepted = 1; break; }
             if (nu_h < tol) { converged = 1; accepted = 0; break; }
         }
-        /* line W_zeta: V = W - (A P) Xi, then Cholesky QR */
+        /* V = W - (A P) Xi, then Cholesky QR with column dropping */
         for (int64_t r = 0; r < n; ++r)
             for (int c = 0; c < m; ++c) {
                 double acc = 0.0;
@@ -613,7 +613,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
             }
         int mn = or_cholqr_deflate(n, m, V, tau, W, Z, keep);
         inf.deflations += m - mn;
-        /* lines P, Sigma */
+        /* P = W + P Z^T, Sigma = Z Sigma */
         for (int64_t r = 0; r < n; ++r)
             for (int c = 0; c < mn; ++c) {
                 double acc = 0.0;
@@ -638,7 +638,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
     inf.rel_res_best = nu_h;
     inf.rel_res_ls = rel_ls;
 
-    /* line X, x: X = X~ + X0, x = X c^ (or the best column) in the original space */
+    /* X = X~ + X0, x = X c^ (or the best column) in the original space */
     if (converged && accepted) {
         for (int64_t r = 0; r < n; ++r) {
             double acc = 0.0;

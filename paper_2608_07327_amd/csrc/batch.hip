@@ -170,7 +170,7 @@ __device__ __forceinline__ uint64_t splitmix64_at_b(uint64_t seed, uint64_t k) {
     return z ^ (z >> 31);
 }
 
-// scaled values a_rc / (d_r d_c) and the Uniform(-1,1) block U (Alg. 1, line U)
+// scaled values a_rc / (d_r d_c) and the Uniform(-1,1) block U (Alg. 1, the random block U)
 template <int S>
 __device__ void ph_scale_u(const BArgs& a, const Item& m) {
     const BSys& y = a.sys[m.sys];
@@ -306,7 +306,7 @@ __device__ void ph_init(const BArgs& a, const Item& m, double* sm) {
     __syncthreads();
 }
 
-// lines tilde_X, R and V = W - Q Xi, with Gram of V and nu partials
+// X~ += P alpha, R -= Q alpha and V = W - Q Xi, with Gram of V and nu partials
 template <int S>
 __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
     constexpr int RPP = MB_BLOCK / S;
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         DISPATCH_S(a.sys[m.sys].S, ph_scale_u<SS>(a, m))
     }
     SYNC_OR_QUIT
-    // line X^0: Y = A~ U and ||Y||_F^2
+    // initial guess: Y = A~ U and ||Y||_F^2
     FOR_ITEMS {
         const Item m = item_of(a, it_);
         DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(a, m, a.U, a.Y, false, true, sm))
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         __syncthreads();
     }
     SYNC_OR_QUIT
-    // lines tilde_B .. R^0 and the partials of the first QR
+    // scaled right-hand sides, R0 and the partials of the first QR
     FOR_ITEMS {
         const Item m = item_of(a, it_);
         if (a.st[m.sys].done) continue;
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     }
     SYNC_OR_QUIT
 
-    // --- the iteration loop (lines Xi .. Sigma) for every active system
+    // --- the iteration loop (Xi to the new Sigma) for every active system
     for (int loop = 0; loop <= a.max_iter + 1; ++loop) {
         FOR_ITEMS {
             const Item m = item_of(a, it_);
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         if (blockIdx.x == 0 && threadIdx.x == 0) ctl->loops = loop + 1;
     }
 
-    // --- termination (lines hat_B .. x)
+    // --- termination (least-squares combination)
     FOR_ITEMS {
         const Item m = item_of(a, it_);
         if (a.st[m.sys].done != DONE_CONVERGED) continue;
@@ -716,6 +716,18 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         __syncthreads();
     }
 #undef SYNC_OR_QUIT
+}
+
+// the leading `head_words` 32-bit words of every system's state, packed for one
+// copy out
+__global__ void k_batch_state_pack(int nsys, const DevState* __restrict__ st, int head_words,
+                                   uint32_t* __restrict__ out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)nsys * head_words;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / head_words;
+        const int w = (int)(e % head_words);
+        out[e] = reinterpret_cast<const uint32_t*>(st + i)[w];
+    }
 }
 
 __global__ void k_batch_state_init(int nsys, DevState* st, const BSys* sys, int max_iter,
@@ -934,8 +946,13 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     }
     // results
     const size_t head = offsetof(DevState, Xi);
+    static_assert(offsetof(DevState, Xi) % 4 == 0, "state head");
     std::vector<char> hst(head * (size_t)nsys);
-    BCK(hipMemcpy2D(hst.data(), head, d_st, sizeof(DevState), head, nsys, hipMemcpyDeviceToHost));
+    uint32_t* d_pack = reinterpret_cast<uint32_t*>(d_part);   // the partials are free now
+    hipLaunchKernelGGL(k_batch_state_pack, dim3(std::min(nsys, 1024)), dim3(MB_BLOCK), 0, stream, nsys,
+                       d_st, (int)(head / 4), d_pack);
+    BCK(hipGetLastError());
+    BCK(hipMemcpyAsync(hst.data(), d_pack, head * (size_t)nsys, hipMemcpyDeviceToHost, stream));
     const hipMemcpyKind back = mem == MBPCG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     for (int i = 0; i < nsys; ++i)
         BCK(hipMemcpyAsync(systems[i].x, d_x + hs[i].vec_off, sizeof(double) * systems[i].n, back,

@@ -121,7 +121,7 @@ struct SxsWs {
 };
 
 // ---------------------------------------------------------------------------
-// line Xi: C = P^T A P from partials; inactive columns get an identity
+// step matrix: C = P^T A P from partials; inactive columns get an identity
 // row/column; Xi = C^-1 through C = L L^T; alpha = Xi Sigma.
 // ---------------------------------------------------------------------------
 template <int S>
@@ -181,8 +181,8 @@ __device__ void tail_xi_body(const double* __restrict__ part, int nwg, int strid
 }
 
 // ---------------------------------------------------------------------------
-// lines h, initial_tolerance, W_zeta (second half), Sigma; or, with setup,
-// line W^0_Sigma^0.  Partials hold the lower triangle of V^T V and then
+// best column h, stop test, second half of the Cholesky QR, Sigma update; or,
+// with setup, the first Cholesky QR (W0, Sigma0).  Partials hold the lower triangle of V^T V and then
 // nu_j = sum_r (d_r R_rj)^2.  Returns 1 when this call finished the system
 // (converged, stalled or failed), else 0.
 // ---------------------------------------------------------------------------
@@ -278,7 +278,7 @@ __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride
 }
 
 // ---------------------------------------------------------------------------
-// Least squares of the termination (line hat_c).  Columns m_0 = b,
+// Least squares of the termination (the combination c^).  Columns m_0 = b,
 // m_{j+1} = D R_j; K = M^T M (lower triangle from partials).  Minimise
 // ||M y|| subject to sum y = 1: with Delta = diag(||m_i||), K~ = Delta^-1 K
 // Delta^-1 and w = Delta^-1 1, y = Delta^-1 z / (w^T z) where K~ z = w,

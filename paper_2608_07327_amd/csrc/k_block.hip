@@ -20,7 +20,8 @@ struct Tiles {
 };
 
 // ---------------------------------------------------------------------------
-// K_B: lines tilde_X, R, h (partial norms) and the first half of W_zeta.
+// K_B: X~ += P alpha, R -= Q alpha, the column norms behind h, and
+// V = W - Q Xi with the Gram V^T V (first half of the Cholesky QR).
 //   X~ += P alpha,  R -= Q alpha,  V = W - Q Xi  (V overwrites W),
 //   partial lower triangle of V^T V and nu_j = sum_r (d_r R_rj)^2.
 // ---------------------------------------------------------------------------
@@ -120,9 +121,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// K_C: the second half of line W_zeta and line P.
+// K_C: W = V M (second half of the Cholesky QR) and P = W + P Z^T.
 //   W = V M  (M = inverse of the kept Cholesky factor),  P = W + P Z^T.
-// FIRST: line P^0 (P = W).  Optionally also writes P rounded to FP32 or BF16
+// FIRST: the first direction block P0 = W0.  Optionally also writes P rounded to FP32 or BF16
 // for the low-precision dense product.
 // ---------------------------------------------------------------------------
 template <int S, int FIRST, int LO>
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
 }
 
 // ---------------------------------------------------------------------------
-// Setup (Alg. 1, lines B .. P^0)
+// Setup (Alg. 1, from B = [b ... b] to the first direction block P0)
 // ---------------------------------------------------------------------------
 // b~ = D^-1 b; partial sums of b^2 and b~^2
 __global__ __launch_bounds__(MB_BLOCK) void k_rhs(int64_t n, const double* __restrict__ b,
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_rhs(int64_t n, const double* __res
 }
 
 // U_rj = 2 u - 1 with u the top 53 bits of SplitMix64 output number j*n + r
-// (Alg. 1, line U: iid Uniform(-1, 1)); padded columns are zero.
+// (Alg. 1, the random block U: iid Uniform(-1, 1)); padded columns are zero.
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
     uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_ynorm(int64_t n, const double* __r
     }
 }
 
-// X0 = gamma U;  R0 = B~ - gamma (A U);  X~0 = 0   (lines X^0 .. R^0)
+// X0 = gamma U;  R0 = B~ - gamma (A U);  X~0 = 0   (initial guess and residual)
 template <int S>
 __global__ void k_init(int64_t n, int s, const double* __restrict__ U, const double* __restrict__ Y,
                        const double* __restrict__ bbar, double* __restrict__ X0,
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* _
 }
 
 // ---------------------------------------------------------------------------
-// Termination (lines hat_B .. x, Proposition 1).  The least-squares problem
+// Termination (least-squares combination of Alg. 1, Proposition 1).  The least-squares problem
 // min_c ||b - B^ c|| with B^ = B - D R is solved in the equivalent form
 // min ||y0 b + (D R) c|| subject to y0 + sum c = 1, whose FP64 Gram over the
 // columns [b, D R] is formed here (one pass over R).

@@ -1,4 +1,4 @@
-// Dense block product Q = A P on the matrix cores (Alg. 1, line Xi for dense
+// Dense block product Q = A P on the matrix cores (the A P of Alg. 1 for dense
 // A; Sec. 3 keeps dense A column-major in FP64).
 //
 // A workgroup of four wavefronts owns 256 rows and one of KSPLIT column

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_ls(const double* __restri
     tail_ls_body<S>(part, nwg, tri_count(S + 1), st, sm, smi);
 }
 
-// ||r|| of the LS combination and the accept test (line convergence_tolerance)
+// ||r|| of the LS combination and the accept test (the stop test on the combination)
 __global__ void k_tail_accept(const double* __restrict__ part, int nwg, DevState* __restrict__ st) {
     __shared__ double out[1], tmp[TAIL_THREADS];
     reduce_partials(part, nwg, 1, 1, out, tmp);
@@ -53,7 +53,7 @@ __global__ void k_tail_true(const double* __restrict__ part, int nwg, DevState* 
     if (threadIdx.x == 0) st->rel_true = sqrt(out[0]) / st->bnorm;
 }
 
-// ||b||, ||b~||, ||A U||_F -> gamma (line X^0)
+// ||b||, ||b~||, ||A U||_F -> gamma (scale of the initial guess)
 __global__ void k_tail_gamma(const double* __restrict__ part_b, int nwg_b,
                              const double* __restrict__ part_y, int nwg_y,
                              DevState* __restrict__ st) {

@@ -210,7 +210,7 @@ static hipError_t launch_product(Ctx& c, const Plan& pl, const double* P, double
     return launch_dense_reduce(S, c.n, pl.ksplit, c.qpart, P, Q, part, pl.nwg_dred, st, c.stream);
 }
 
-// one iteration of Alg. 1's loop: lines Xi .. Sigma
+// one iteration of Alg. 1's loop, from Xi to the new Sigma
 static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist) {
     hipError_t e;
     if ((e = launch_product(c, pl, c.P, c.Q, c.part_a, c.st)) != hipSuccess) return e;
@@ -449,15 +449,15 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     CK(launch_state_init(c.st, s, (int)std::min<int64_t>(p.max_iter, INT32_MAX), p.tol, tol0, tau,
                          p.history ? (int)std::min<int64_t>(p.max_iter, INT32_MAX) : 0, c.stream));
     CKS(setup_scaling(c, pl, b, jac));
-    // line U
+    // random block U
     if (Udev) CK(launch_pad_block(S, c.n, s, Udev, c.U, c.stream));
     else CK(launch_uniform(S, c.n, s, p.seed, c.U, c.stream));
-    // line X^0: Y = A~ U, ||Y||_F
+    // initial guess: Y = A~ U, ||Y||_F
     if (kind != DENSE_F64) CK(launch_block_to_lo(kind, c.n, S, c.U, c.Plo, c.stream));
     CK(launch_product(c, pl, c.U, c.Y, nullptr, c.st));
     CK(launch_ynorm(S, pl.nwg_e, c.n, c.Y, c.part_a, c.stream));
     CK(launch_tail_gamma(pl.nwg_e, c.part_c, pl.nwg_e, c.part_a, c.st, c.stream));
-    // lines tilde_B .. R^0, W^0, P^0
+    // scaled right-hand sides, R0, first Cholesky QR, P0
     CK(launch_init(S, c.n, s, c.U, c.Y, c.bbar, c.X0, c.Xt, c.R, c.st, c.stream));
     CK(launch_gram_nu(S, pl.nwg_upd, c.n, c.R, c.d, c.part_b, c.stream));
     CK(launch_tail_qr(S, pl.nwg_upd, c.part_b, c.st, nullptr, 1, c.stream));

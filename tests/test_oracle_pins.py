@@ -299,7 +299,7 @@ def test_nan_rhs_is_nonfinite():
 
 
 def test_initial_block_normalisation():
-    # Alg. 1, line X^0: ||A X0||_F = ||B||_F (in the scaled system)
+    # Alg. 1, initial guess: ||A X0||_F = ||B||_F (in the scaled system)
     A = W.diffusion3d(10)
     b = W.rhs(A.n, 12)
     s = 3
@@ -312,7 +312,7 @@ def test_initial_block_normalisation():
     assert np.allclose(X0 / U, (X0 / U)[0, 0], rtol=1e-15)
     assert abs(np.linalg.norm(As @ X0) - math.sqrt(s) * np.linalg.norm(b / d)) <= \
         1e-13 * np.linalg.norm(As @ X0)
-    # R0 = B - A X0 (Alg. 1, lines tilde_B and R^0)
+    # R0 = B - A X0 (Alg. 1, initial residual)
     assert np.allclose(ex["R"], (b / d)[:, None] - As @ X0, atol=1e-13)
 
 
