@@ -45,7 +45,7 @@ DEFAULT_S = 4
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("k_sparse.hip", "dev_common.hpp", "dev_spmm.hpp", "kernels.hpp"):
+    for f in ("k_sparse.hip", "dev_common.hpp", "dev_spmm.hpp"):
         with open(os.path.join(ROOT, "paper_2608_07327_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

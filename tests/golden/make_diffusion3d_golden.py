@@ -8,6 +8,11 @@ iteration counts, exit diagnostics, the rounding-order noise floor
 inputs so a reader can tell whether its inputs are the same bytes.
 
     python tests/golden/make_diffusion3d_golden.py [--grid 128] [--s 1,2,4,8,16]
+    python tests/golden/make_diffusion3d_golden.py --merge OTHER.json
+
+--merge takes the block widths of another output of this script (written
+with --out, e.g. by a second process running other widths) whose input hash
+matches.
 """
 import argparse
 import hashlib
@@ -41,6 +46,7 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--s", default="1,2,4,8,16")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--merge", default=None)
     args = ap.parse_args()
     out = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                    f"diffusion3d_{args.grid}.json")
@@ -52,6 +58,15 @@ def main():
     rec.update({"grid": args.grid, "n": A.n, "nnz": A.nnz, "input_sha256": input_hash(A, b),
                 "sample_index": idx.tolist()})
     rec.setdefault("mbpcg", {})
+    if args.merge:
+        other = json.load(open(args.merge))
+        if other.get("input_sha256") != rec["input_sha256"] or other.get("sample_index") != rec["sample_index"]:
+            sys.exit("merge: inputs differ")
+        for k, v in other.get("mbpcg", {}).items():
+            rec["mbpcg"].setdefault(k, v)
+        json.dump(rec, open(out, "w"))
+        print("merged widths", sorted(rec["mbpcg"], key=int), flush=True)
+        return
     if "cg" not in rec:
         t = time.time()
         x, info, _ = O.cg_cg(M, b)

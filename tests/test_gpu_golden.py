@@ -1,0 +1,102 @@
+"""Full-size parity: the 128^3 diffusion system of the benchmark solved on the
+GPU, in the launch configuration the benchmark times (autotuned block
+product, event-timed profile mode and graph mode), against the oracle's
+stored results for the same seeded inputs.
+
+tests/golden/diffusion3d_128.json is written by make_diffusion3d_golden.py
+from the CPU oracle alone: for every block width it holds the oracle's
+iteration count with sequential and with blocked-pairwise reductions (their
+difference is the method's own rounding-order noise), the exit diagnostics,
+the noise floor |x_pairwise - x| / |x|, and x at 4096 fixed indices.  The
+bar is the one of the small parity tests: iteration counts within the
+oracle's band (at least 1 %), and where the counts agree, the sampled x
+within max(1e-10, 10 x noise floor).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2608_07327_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_07327_amd import mbpcg as M  # noqa: E402
+
+DEV = torch.device("cuda:0")
+GOLD_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "diffusion3d_128.json")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gold():
+    return json.load(open(GOLD_PATH))
+
+
+@pytest.fixture(scope="module")
+def system(gold):
+    A = W.diffusion3d(gold["grid"])
+    b = W.rhs(A.n, W.CFG_DIFFUSION3D)
+    h = hashlib.sha256()
+    for a in (A.rowptr, A.colind, A.vals, b):
+        h.update(np.ascontiguousarray(a).tobytes())
+    # the stored results belong to exactly these input bytes
+    assert h.hexdigest() == gold["input_sha256"]
+    solver = M.Solver.from_matrix(A)
+    bd = torch.as_tensor(b, device=DEV)
+    yield solver, bd, np.asarray(gold["sample_index"])
+    solver.close()
+
+
+def _band(o):
+    near = abs(o["rel_res_best"] - 1e-8) <= 1e-10
+    return max(abs(o["iterations"] - o["pairwise_iterations"]) + (1 if near else 0),
+               int(np.ceil(0.01 * o["iterations"])))
+
+
+@pytest.mark.parametrize("s", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("mode", ["profile", "graph"])
+def test_full_size_mbpcg_against_oracle_golden(gold, system, s, mode):
+    solver, bd, idx = system
+    o = gold["mbpcg"][str(s)]
+    say("golden 128^3", s, mode)
+    solver.autotune(s)
+    x, info = solver.solve(bd, s=s, seed=o["seed"], profile=1 if mode == "profile" else 0)
+    assert info["status"] == o["status"] == 0
+    assert abs(info["iterations"] - o["iterations"]) <= _band(o), (info["iterations"], o)
+    assert info["rel_res_true"] < 2e-8
+    if o["iterations"] == o["pairwise_iterations"]:
+        for key in ("final_width", "deflations", "used_fallback"):
+            assert info[key] == o[key], (key, info[key], o[key])
+    if info["iterations"] == o["iterations"] == o["pairwise_iterations"]:
+        xs = x.cpu().numpy()[idx]
+        xo = np.asarray(o["x_sample"])
+        err = np.linalg.norm(xs - xo) / np.linalg.norm(xo)
+        assert err <= max(1e-10, 10 * o["noise_floor"]), (err, o["noise_floor"])
+
+
+def test_full_size_cg_against_oracle_golden(gold, system):
+    solver, bd, idx = system
+    o = gold["cg"]
+    say("golden 128^3 CG")
+    x, info = solver.cg_solve(bd, profile=1)
+    assert info["status"] == 0
+    assert abs(info["iterations"] - o["iterations"]) <= int(np.ceil(0.01 * o["iterations"]))
+    assert info["rel_res_true"] < 2e-8
+    if info["iterations"] == o["iterations"]:
+        xs = x.cpu().numpy()[idx]
+        xo = np.asarray(o["x_sample"])
+        # the s = 1 block method on this system has a rounding-order noise
+        # floor of a few 1e-14; 1e-10 leaves four orders of margin
+        assert np.linalg.norm(xs - xo) / np.linalg.norm(xo) <= 1e-10
