@@ -9,6 +9,25 @@ namespace mb {
 
 #define TAIL_THREADS 256
 
+// First stage of a two-stage fixed-order sum of per-workgroup partials:
+// workgroup g adds partials [g c, (g + 1) c) of every entry (c = ceil(nwg / G))
+// and writes out[g * E + e].  The one-workgroup tails then add G partials
+// instead of nwg, so their latency-bound reduction no longer grows with the
+// producer's grid.
+__global__ __launch_bounds__(TAIL_THREADS) void k_part_reduce(const double* __restrict__ part,
+                                                              int nwg, int E,
+                                                              double* __restrict__ out,
+                                                              const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ double sums[PART_REDUCE_EMAX];
+    __shared__ double tmp[TAIL_THREADS];
+    const int G = gridDim.x, g = blockIdx.x;
+    const int c = (nwg + G - 1) / G;
+    const int w0 = min(nwg, g * c), w1 = min(nwg, w0 + c);
+    reduce_partials(part + (int64_t)w0 * E, w1 - w0, E, E, sums, tmp);
+    for (int e = threadIdx.x; e < E; e += blockDim.x) out[(int64_t)g * E + e] = sums[e];
+}
+
 template <int S>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail_xi(const double* __restrict__ part, int nwg,
                                                           DevState* __restrict__ st) {
@@ -181,6 +200,13 @@ __global__ void k_state_init(DevState* st, int s, int max_iter, double tol, doub
         case 32: { constexpr int SS = 32; CALL; } \
     }                               \
     return hipErrorInvalidValue;
+
+hipError_t launch_part_reduce(int nwg, int E, const double* part, double* out, int G,
+                              const DevState* st, hipStream_t s) {
+    if (E > PART_REDUCE_EMAX || G < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_part_reduce, dim3(G), dim3(TAIL_THREADS), 0, s, part, nwg, E, out, st);
+    return hipGetLastError();
+}
 
 hipError_t launch_tail_xi(int S, int nwg, const double* part, DevState* st, hipStream_t s) {
     MB_TAIL_S(S, {

@@ -123,6 +123,12 @@ hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* 
 // ---- tails (one workgroup): reductions of partials + s x s FP64 work
 hipError_t launch_tail_gamma(int nwg_b, const double* part_b, int nwg_y, const double* part_y,
                              DevState* st, hipStream_t s);
+// first stage of a two-stage partial sum: nwg partials of E entries (stride E)
+// -> G partials in out (stride E); E <= PART_REDUCE_EMAX
+constexpr int PART_REDUCE_EMAX = 1024;
+constexpr int PART_REDUCE_G = 32;
+hipError_t launch_part_reduce(int nwg, int E, const double* part, double* out, int G,
+                              const DevState* st, hipStream_t s);
 hipError_t launch_tail_xi(int S, int nwg, const double* part, DevState* st, hipStream_t s);
 hipError_t launch_tail_qr(int S, int nwg, const double* part, DevState* st, double* hist,
                           int setup, hipStream_t s);

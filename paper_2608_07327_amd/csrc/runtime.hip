@@ -48,7 +48,7 @@ Ctx::~Ctx() {
     dfree(A); dfree(Alo);
     dfree(d); dfree(bbar); dfree(bdev); dfree(xdev); dfree(rvec); dfree(xacc);
     dfree(U); dfree(Y); dfree(X0); dfree(Xt); dfree(R); dfree(W); dfree(P); dfree(Q); dfree(Plo);
-    dfree(qpart); dfree(part_a); dfree(part_b); dfree(part_c); dfree(st); dfree(hist);
+    dfree(qpart); dfree(part_a); dfree(part_b); dfree(part_r); dfree(part_c); dfree(st); dfree(hist);
     if (pinned) (void)hipHostFree(pinned);
     if (st_host) (void)hipHostFree(st_host);
     for (auto& e : ev_poll)
@@ -103,7 +103,7 @@ static mbpcg_status ensure_blocks(Ctx& c, int S) {
     if (c.Scap >= S) return MBPCG_OK;
     drop_graphs(c);
     dfree(c.U); dfree(c.Y); dfree(c.X0); dfree(c.Xt); dfree(c.R); dfree(c.W); dfree(c.P); dfree(c.Q);
-    dfree(c.Plo); dfree(c.part_a); dfree(c.part_b); dfree(c.part_c); dfree(c.qpart);
+    dfree(c.Plo); dfree(c.part_a); dfree(c.part_b); dfree(c.part_r); dfree(c.part_c); dfree(c.qpart);
     const size_t bb = sizeof(double) * (size_t)c.n * S;
     DALLOC(c.U, bb); DALLOC(c.Y, bb); DALLOC(c.X0, bb); DALLOC(c.Xt, bb);
     DALLOC(c.R, bb); DALLOC(c.W, bb); DALLOC(c.P, bb); DALLOC(c.Q, bb);
@@ -113,6 +113,7 @@ static mbpcg_status ensure_blocks(Ctx& c, int S) {
     c.part_elems = (int64_t)NWG_MAX * e;
     DALLOC(c.part_a, sizeof(double) * c.part_elems);
     DALLOC(c.part_b, sizeof(double) * c.part_elems);
+    DALLOC(c.part_r, sizeof(double) * PART_REDUCE_G * PART_REDUCE_EMAX);
     DALLOC(c.part_c, sizeof(double) * c.part_elems);
     if (c.dense) {
         c.qpart_elems = (int64_t)dense_ksplit(c.n) * c.n * S;
@@ -211,14 +212,36 @@ static hipError_t launch_product(Ctx& c, const Plan& pl, const double* P, double
 }
 
 // one iteration of Alg. 1's loop, from Xi to the new Sigma
+// Partials of E entries from nwg workgroups, as the one-workgroup tails should
+// read them: above 2 G partials they are first summed down to G by G
+// workgroups (fixed order) into c.part_r.
+static hipError_t staged_partials(Ctx& c, int nwg, int E, const double* part,
+                                  const double** use, int* use_nwg) {
+    if (nwg <= 2 * PART_REDUCE_G) {
+        *use = part;
+        *use_nwg = nwg;
+        return hipSuccess;
+    }
+    *use = c.part_r;
+    *use_nwg = PART_REDUCE_G;
+    return launch_part_reduce(nwg, E, part, c.part_r, PART_REDUCE_G, c.st, c.stream);
+}
+
 static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist) {
     hipError_t e;
+    const double* pr;
+    int pn;
     if ((e = launch_product(c, pl, c.P, c.Q, c.part_a, c.st)) != hipSuccess) return e;
-    if ((e = launch_tail_xi(pl.S, pl.nwg_prod, c.part_a, c.st, c.stream)) != hipSuccess) return e;
+    if ((e = staged_partials(c, pl.nwg_prod, tri_count(pl.S), c.part_a, &pr, &pn)) != hipSuccess)
+        return e;
+    if ((e = launch_tail_xi(pl.S, pn, pr, c.st, c.stream)) != hipSuccess) return e;
     if ((e = launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d, c.part_b, c.st,
                            c.stream)) != hipSuccess)
         return e;
-    if ((e = launch_tail_qr(pl.S, pl.nwg_upd, c.part_b, c.st, hist, 0, c.stream)) != hipSuccess)
+    if ((e = staged_partials(c, pl.nwg_upd, tri_count(pl.S) + pl.S, c.part_b, &pr, &pn)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_tail_qr(pl.S, pn, pr, c.st, hist, 0, c.stream)) != hipSuccess)
         return e;
     return launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st, c.stream);
 }

@@ -63,6 +63,7 @@ struct Ctx {
     // reductions
     double* part_a = nullptr;
     double* part_b = nullptr;
+    double* part_r = nullptr;   // first stage of a two-stage partial sum
     double* part_c = nullptr;
     int64_t part_elems = 0;
     DevState* st = nullptr;
