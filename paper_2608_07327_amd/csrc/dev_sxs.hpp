@@ -10,99 +10,134 @@
 namespace mb {
 
 // ---------------------------------------------------------------------------
-// lower Cholesky C = L L^T (S x S, reads the lower triangle).  Returns nonzero
-// when a pivot is not positive and finite.
+// The factorisations run on wavefront 0 with lane i holding row i of the
+// working matrix in registers (S <= 32 < 64 lanes); a pivot or a finished
+// column entry reaches the other lanes by readlane with a compile-time lane
+// index, so there is no barrier inside the elimination.  Results go to LDS
+// and the callers' remaining S^3 products use every thread.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// lower Cholesky C = L L^T (S x S, reads the lower triangle) into L (upper
+// part zero).  Returns nonzero when a pivot is not positive and finite.
 template <int S>
 __device__ int chol_lower(const double* C, double* L, int* flag) {
     const int t = threadIdx.x;
-    for (int e = t; e < S * S; e += blockDim.x) L[e] = 0.0;
-    if (t == 0) *flag = 0;
-    __syncthreads();
-    for (int j = 0; j < S; ++j) {
-        if (t == 0) {
-            double dd = C[j * S + j];
-            for (int k = 0; k < j; ++k) dd -= L[j * S + k] * L[j * S + k];
-            if (!(dd > 0.0) || !finite_d(dd)) {
-                *flag = 1;
-                dd = 1.0;
+    if (t < 64) {
+        const int i = t < S ? t : S - 1;
+        double w[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) w[k] = C[(i >= k ? i : k) * S + (i >= k ? k : i)];
+        int bad = 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            double d = lane_bcast(w[j], j);
+            if (!(d > 0.0) || !finite_d(d)) {
+                bad = 1;
+                d = 1.0;
             }
-            L[j * S + j] = sqrt(dd);
+            const double ljj = sqrt(d);
+            const double lij = t == j ? ljj : (t > j ? w[j] / ljj : 0.0);
+            w[j] = lij;
+#pragma unroll
+            for (int k = j + 1; k < S; ++k) w[k] -= lij * lane_bcast(lij, k);
         }
-        __syncthreads();
-        if (t > j && t < S) {
-            double v = C[t * S + j];
-            for (int k = 0; k < j; ++k) v -= L[t * S + k] * L[j * S + k];
-            L[t * S + j] = v / L[j * S + j];
+        if (t < S) {
+#pragma unroll
+            for (int k = 0; k < S; ++k) L[t * S + k] = k <= t ? w[k] : 0.0;
         }
-        __syncthreads();
+        if (t == 0) *flag = bad;
     }
+    __syncthreads();
     const int f = *flag;
     __syncthreads();
     return f;
+}
+
+// L^-1 of a lower-triangular L in LDS, one column per lane (forward
+// substitution on e_c; reads of L are wavefront broadcasts).
+template <int S>
+__device__ void lower_inverse(const double* L, double* Li) {
+    const int c = threadIdx.x;
+    if (c < S) {
+        double x[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = 0; m < i; ++m) v -= L[i * S + m] * x[m];
+            x[i] = v / L[i * S + i];
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) Li[i * S + c] = x[i];
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Cholesky QR factor with column dropping (Sec. 3 uses single-pass Cholesky
 // QR; the paper only needs independent columns).  G = U^T U column by column;
 // column l is kept iff G_ll > 0, finite, and delta_l > tau G_ll with
-// delta_l = G_ll - sum_{kept q < l} U_ql^2.  Writes U (upper), keep[S],
-// Z = kept rows of U (upper trapezoidal, dropped rows zero) and M = inverse
-// of the kept block (dropped rows and columns zero).  Returns the number of
-// kept columns.
+// delta_l = G_ll - sum_{kept q < l} U_ql^2 (the pivot of the Schur complement
+// left by the kept columns).  Writes U (upper, dropped rows zero), keep[S],
+// Z = U (upper trapezoidal) and M = inverse of the kept block (dropped rows
+// and columns zero).  Returns the number of kept columns.
 // ---------------------------------------------------------------------------
 template <int S>
 __device__ int cholqr_factor(const double* G, double tau, double* U, int* keep, double* Z,
                              double* M, int* cnt) {
     const int t = threadIdx.x;
-    for (int e = t; e < S * S; e += blockDim.x) {
-        U[e] = 0.0;
-        M[e] = 0.0;
+    if (t < 64) {
+        const int i = t < S ? t : S - 1;
+        double w[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) w[k] = G[i * S + k];
+        const double gdiag = G[i * S + i];
+        int kept = 0;
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            const double g = lane_bcast(gdiag, l);
+            const double dl = lane_bcast(w[l], l);
+            const bool k = (g > 0.0) && finite_d(dl) && (dl > tau * g);   // wave-uniform
+            double u = 0.0;
+            if (k) {
+                const double ul = sqrt(dl);
+                u = t == l ? ul : (t > l ? w[l] / ul : 0.0);
+#pragma unroll
+                for (int a = l + 1; a < S; ++a) w[a] -= u * lane_bcast(u, a);
+                ++kept;
+            }
+            if (t < S) U[l * S + t] = u;
+            if (t == 0) keep[l] = k ? 1 : 0;
+        }
+        if (t == 0) *cnt = kept;
     }
     __syncthreads();
-    for (int l = 0; l < S; ++l) {
-        if (t == 0) {
-            const double g = G[l * S + l];
-            double dl = g;
-            for (int q = 0; q < l; ++q)
-                if (keep[q]) dl -= U[q * S + l] * U[q * S + l];
-            const int k = (g > 0.0) && finite_d(dl) && (dl > tau * g);
-            keep[l] = k;
-            if (k) U[l * S + l] = sqrt(dl);
-        }
-        __syncthreads();
-        if (keep[l] && t > l && t < S) {
-            double v = G[l * S + t];
-            for (int q = 0; q < l; ++q)
-                if (keep[q]) v -= U[q * S + l] * U[q * S + t];
-            U[l * S + t] = v / U[l * S + l];
-        }
-        __syncthreads();
-    }
-    for (int e = t; e < S * S; e += blockDim.x) {
-        const int i = e / S, j = e % S;
-        Z[e] = (keep[i] && j >= i) ? U[e] : 0.0;
-    }
-    if (t < S && keep[t]) {
+    // M = (kept block of U)^-1, one column per lane by back substitution
+    if (t < S) {
         const int c = t;
-        M[c * S + c] = 1.0 / U[c * S + c];
-        for (int a = c - 1; a >= 0; --a) {
-            if (!keep[a]) continue;
-            double v = 0.0;
-            for (int b = a + 1; b <= c; ++b)
-                if (keep[b]) v -= U[a * S + b] * M[b * S + c];
-            M[a * S + c] = v / U[a * S + a];
+        double x[S];
+#pragma unroll
+        for (int a = S - 1; a >= 0; --a) {
+            double v = a == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int b2 = a + 1; b2 < S; ++b2) v -= U[a * S + b2] * x[b2];
+            x[a] = (keep[a] && keep[c] && a <= c) ? v / U[a * S + a] : 0.0;
         }
+#pragma unroll
+        for (int a = 0; a < S; ++a) M[a * S + c] = x[a];
     }
-    if (t == 0) {
-        int k = 0;
-        for (int l = 0; l < S; ++l) k += keep[l];
-        *cnt = k;
+    for (int e = t; e < S * S; e += blockDim.x) {
+        const int r = e / S, j = e % S;
+        Z[e] = (keep[r] && j >= r) ? U[e] : 0.0;
     }
     __syncthreads();
-    const int k = *cnt;
-    __syncthreads();
-    return k;
+    return *cnt;
 }
 
 template <int E>
@@ -149,19 +184,8 @@ __device__ void tail_xi_body(const double* __restrict__ part, int nwg, int strid
         if (t == 0) st->done = DONE_NOTSPD;
         return;
     }
-    // L^-1 by forward substitution, one column per thread
-    for (int e = t; e < S * S; e += blockDim.x) Li[e] = 0.0;
-    __syncthreads();
-    if (t < S) {
-        const int c = t;
-        Li[c * S + c] = 1.0 / L[c * S + c];
-        for (int i = c + 1; i < S; ++i) {
-            double v = 0.0;
-            for (int k = c; k < i; ++k) v -= L[i * S + k] * Li[k * S + c];
-            Li[i * S + c] = v / L[i * S + i];
-        }
-    }
-    __syncthreads();
+    // L^-1, one column per lane
+    lower_inverse<S>(L, Li);
     // Xi = L^-T L^-1
     for (int e = t; e < S * S; e += blockDim.x) {
         const int i = e / S, j = e % S;
