@@ -138,12 +138,51 @@ void or_uniform_block(uint64_t seed, int64_t n, int s, double* U)
 }
 
 /* ---------------------------------------------------------------------------
+ * Nearest BF16 (8 significant bits) with ties to even, straight from the
+ * double: the significand scaled to 8 integer bits and rounded by rint
+ * (round-half-even in the default rounding mode).  Normal range only, which
+ * covers every matrix and block this oracle rounds.
+ * ------------------------------------------------------------------------- */
+double or_round_bf16(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    double m = frexp(x, &e);          /* x = m 2^e, 0.5 <= |m| < 1 */
+    return ldexp(rint(ldexp(m, 8)), e - 8);
+}
+
+static double round_lo(int lo, double x)
+{
+    return lo == 1 ? (double)(float)x : or_round_bf16(x);
+}
+
+/* ---------------------------------------------------------------------------
  * Block product Y = A X (Alg. 1: A U for the initial block and A P in every iteration).  CSR rows
  * are summed in stored order; a dense product sums over columns in order.
+ * With A->lo set (dense only), A and X are rounded to FP32 or BF16 and each
+ * product is rounded to FP32 and added in FP32, as the mixed-precision
+ * extension's inner products accumulate.
  * ------------------------------------------------------------------------- */
 void or_matmul_block(const or_matrix* A, int k, const double* X, double* Y)
 {
     int64_t n = A->n;
+    if (A->dense && A->lo) {
+        float* acc = (float*)calloc((size_t)(n * k), sizeof(float));
+        float* xr = (float*)malloc(sizeof(float) * (size_t)k);
+        for (int64_t c = 0; c < n; ++c) {
+            const double* col = A->a + c * A->lda;
+            for (int j = 0; j < k; ++j) xr[j] = (float)round_lo(A->lo, X[c * k + j]);
+            for (int64_t r = 0; r < n; ++r) {
+                const float a = (float)round_lo(A->lo, col[r]);
+                float* yr = acc + r * k;
+                for (int j = 0; j < k; ++j) yr[j] = yr[j] + a * xr[j];
+            }
+        }
+        for (int64_t e = 0; e < n * k; ++e) Y[e] = (double)acc[e];
+        free(xr);
+        free(acc);
+        return;
+    }
     if (!A->dense) {
         for (int64_t r = 0; r < n; ++r)
             for (int j = 0; j < k; ++j) {

@@ -27,6 +27,10 @@ typedef struct {
     const double* vals;
     const double* a;           /* dense */
     int64_t lda;
+    int lo;                    /* dense products in low precision (mixed-precision
+                                  extension): 0 FP64, 1 FP32, 2 BF16 -- A and X
+                                  rounded to nearest even, products accumulated
+                                  in FP32 in column order.  CSR ignores it. */
 } or_matrix;
 
 enum {
@@ -71,6 +75,9 @@ void or_set_summation(int mode);
 uint64_t or_splitmix64(uint64_t seed, uint64_t k);
 /* U[r*s + j] = 2 * u - 1, u = (splitmix64(seed, j*n + r) >> 11) * 2^-53 */
 void or_uniform_block(uint64_t seed, int64_t n, int s, double* U);
+
+/* x rounded to the nearest BF16 value (ties to even), returned as a double */
+double or_round_bf16(double x);
 
 /* Y = A X for an n x k block */
 void or_matmul_block(const or_matrix* A, int k, const double* X, double* Y);

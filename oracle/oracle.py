@@ -31,7 +31,7 @@ def build(force: bool = False) -> str:
 class OrMatrix(C.Structure):
     _fields_ = [("n", C.c_int64), ("dense", C.c_int), ("rowptr", C.c_void_p),
                 ("colind", C.c_void_p), ("vals", C.c_void_p), ("a", C.c_void_p),
-                ("lda", C.c_int64)]
+                ("lda", C.c_int64), ("lo", C.c_int)]
 
 
 class OrParams(C.Structure):
@@ -67,6 +67,8 @@ def lib():
         L.or_splitmix64.restype = C.c_uint64
         L.or_uniform_block.argtypes = [C.c_uint64, i64, C.c_int, vp]
         L.or_matmul_block.argtypes = [vp, C.c_int, vp, vp]
+        L.or_round_bf16.argtypes = [dbl]
+        L.or_round_bf16.restype = dbl
         L.or_gram.argtypes = [i64, C.c_int, vp, C.c_int, vp, vp]
         L.or_cholesky.argtypes = [C.c_int, vp, vp]
         L.or_spd_inverse.argtypes = [C.c_int, vp, vp]
@@ -83,19 +85,25 @@ def _p(a):
     return None if a is None else a.ctypes.data
 
 
-class Matrix:
-    """Keeps the numpy arrays alive behind an OrMatrix."""
+LO_FP64, LO_FP32, LO_BF16 = 0, 1, 2
+OR_OK, OR_NOT_CONVERGED, OR_ERR_NOT_SPD, OR_ERR_BREAKDOWN, OR_ERR_NONFINITE = 0, 1, -2, -3, -4
 
-    def __init__(self, A):
+
+class Matrix:
+    """Keeps the numpy arrays alive behind an OrMatrix.  lo (dense only)
+    selects low-precision products: LO_FP32 or LO_BF16."""
+
+    def __init__(self, A, lo=LO_FP64):
         if isinstance(A, np.ndarray):
             self.a = np.asfortranarray(A, dtype=np.float64)
-            self.s = OrMatrix(A.shape[0], 1, None, None, None, self.a.ctypes.data, A.shape[0])
+            self.s = OrMatrix(A.shape[0], 1, None, None, None, self.a.ctypes.data, A.shape[0],
+                              int(lo))
         else:
             self.rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
             self.colind = np.ascontiguousarray(A.colind, dtype=np.int32)
             self.vals = np.ascontiguousarray(A.vals, dtype=np.float64)
             self.s = OrMatrix(A.n, 0, self.rowptr.ctypes.data, self.colind.ctypes.data,
-                              self.vals.ctypes.data, None, 0)
+                              self.vals.ctypes.data, None, 0, 0)
         self.n = int(self.s.n)
 
 
@@ -215,3 +223,54 @@ def hs_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=Fa
 
 def cg_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=False):
     return _cg(lib().or_cg_cg, A, b, x0, tol, max_iter, jacobi, want_history)
+
+
+def round_bf16(x: float) -> float:
+    return float(lib().or_round_bf16(float(x)))
+
+
+def ir_solve(A, b, s, lo, ir_tol=1e-10, inner_tol=5e-6, max_outer=50, seed=0, tau=1e-12):
+    """Mixed-precision iterative refinement around Algorithm 1 (an extension;
+    the paper runs FP64 only).  Dense A, no scaling.  x = 0, r = b; each
+    outer step runs Algorithm 1 on the rounded operator (lo = LO_FP32 or
+    LO_BF16: A and the blocks it multiplies rounded, products accumulated in
+    FP32, the rest FP64) for A d = r, to the relative tolerance
+    clamp(0.5 ir_tol / rel, inner_tol, 0.1) where rel = ||r|| / ||b||; then
+    x += d and r = b - A x in FP64.  It stops when rel <= ir_tol, and takes
+    the step back and stops when an outer step does not lower rel.  Inner
+    solve k (from 1) uses seed + (k - 1) * 7919.  Returns (x, info)."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    Mlo = Matrix(A, lo=lo)
+    bn = float(np.linalg.norm(b))
+    x = np.zeros_like(b)
+    info = {"outer_iterations": 0, "iterations": 0, "status": 0, "rel_res_true": 1.0,
+            "inner_iterations": []}
+    if bn == 0.0:
+        info["rel_res_true"] = 0.0
+        return x, info
+    r = b.copy()
+    rel = 1.0
+    stalled = False
+    for k in range(1, max_outer + 1):
+        tol_k = min(0.1, max(inner_tol, 0.5 * ir_tol / rel))
+        d, ii, _ = mbpcg_solve(Mlo, r, s, tol=tol_k, jacobi=False, seed=seed + (k - 1) * 7919,
+                               tau=tau)
+        info["iterations"] += ii["iterations"]
+        info["inner_iterations"].append(ii["iterations"])
+        info["outer_iterations"] = k
+        if ii["status"] in (OR_ERR_NOT_SPD, OR_ERR_NONFINITE):
+            break
+        x_new = x + d
+        r_new = b - A @ x_new
+        rel_new = float(np.linalg.norm(r_new)) / bn
+        if not rel_new < rel:
+            stalled = True
+            break
+        x, r, rel = x_new, r_new, rel_new
+        if rel <= ir_tol:
+            break
+    info["rel_res_true"] = rel
+    info["status"] = 0 if rel <= ir_tol else 1
+    info["stalled"] = stalled
+    return x, info

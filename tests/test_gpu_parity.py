@@ -375,6 +375,44 @@ def test_fp32_iterative_refinement_reaches_1e10():
     solver.close()
 
 
+def test_fp32_iterative_refinement_against_the_oracle():
+    # the oracle's refinement loop with FP32-rounded products (same inner
+    # tolerance rule, same inner seeds): equal outer steps, total inner
+    # iterations within 5 %, and both at the FP64 tolerance, so the two x
+    # differ by at most 2 kappa ir_tol
+    n = 1024
+    A = W.dense_spd(n, tag=(4, 60))
+    b = W.rng_for((4, 61)).standard_normal(n)
+    say("fp32 IR vs oracle", n)
+    xo, io = O.ir_solve(A, b, 8, O.LO_FP32, ir_tol=1e-10, seed=6)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(dev(b), s=8, precision=M.FP32_IR, precond=M.PRECOND_NONE,
+                           ir_tol=1e-10, seed=6)
+    x = x.cpu().numpy()
+    assert info["status"] == io["status"] == 0, (info, io)
+    assert info["outer_iterations"] == io["outer_iterations"], (info, io)
+    assert abs(info["iterations"] - io["iterations"]) <= np.ceil(0.05 * io["iterations"]), (info, io)
+    kappa = np.linalg.cond(A)
+    assert rel(x, xo) <= 2 * kappa * 1e-10
+    solver.close()
+
+
+def test_bf16_iterative_refinement_against_the_oracle():
+    A = W.tiny_spd(613, 20.0, tag=(4, 62))
+    b = W.rng_for((4, 63)).standard_normal(613)
+    say("bf16 IR vs oracle", 613)
+    xo, io = O.ir_solve(A, b, 8, O.LO_BF16, ir_tol=1e-10, seed=7)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(dev(b), s=8, precision=M.BF16_IR, precond=M.PRECOND_NONE,
+                           ir_tol=1e-10, seed=7)
+    x = x.cpu().numpy()
+    assert info["status"] == io["status"] == 0, (info, io)
+    assert abs(info["outer_iterations"] - io["outer_iterations"]) <= 1, (info, io)
+    assert abs(info["iterations"] - io["iterations"]) <= np.ceil(0.10 * io["iterations"]), (info, io)
+    assert rel(x, xo) <= 2 * np.linalg.cond(A) * 1e-10
+    solver.close()
+
+
 def test_bf16_iterative_refinement_reports_honestly():
     n = 256
     A = W.dense_spd(n, tag=(4, 52))

@@ -336,3 +336,78 @@ def test_duplicate_initial_columns_deflate_and_converge():
     x, info, _ = O.mbpcg_solve(A, b, 4, U=U)
     assert info["status"] == 0 and info["deflations"] >= 1
     assert info["rel_res_true"] < 2e-8
+
+
+# ------------------------------------------- mixed-precision extension (IR)
+def _bf16_reference(x):
+    """Nearest value with an 8-bit significand, ties to even, by exact
+    rational arithmetic on the two neighbours."""
+    from fractions import Fraction
+    if x == 0.0:
+        return 0.0
+    m, e = math.frexp(abs(x))                 # |x| = m 2^e, m in [0.5, 1)
+    q = Fraction(m) * 256                     # 8 significant bits
+    lo = math.floor(q)
+    d = q - lo
+    k = lo + (1 if d > Fraction(1, 2) or (d == Fraction(1, 2) and lo % 2 == 1) else 0)
+    return math.copysign(float(Fraction(k) / 256 * Fraction(2) ** e), x)
+
+
+def test_bf16_rounding_ties_to_even_and_brute_force():
+    assert O.round_bf16(1.0 + 2.0 ** -8) == 1.0                    # tie -> even
+    assert O.round_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6    # tie -> even (up)
+    assert O.round_bf16(1.0 + 2.0 ** -8 + 2.0 ** -30) == 1.0 + 2.0 ** -7
+    assert O.round_bf16(-3.0) == -3.0
+    rng = np.random.default_rng(7)
+    for v in rng.standard_normal(2000) * np.exp(rng.uniform(-20, 20, 2000)):
+        assert O.round_bf16(float(v)) == _bf16_reference(float(v)), v
+
+
+@pytest.mark.parametrize("lo", [O.LO_FP32, O.LO_BF16])
+def test_low_precision_dense_product_within_fp32_accumulation_bound(lo):
+    n, k = 300, 4
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((n, n))
+    X = rng.standard_normal((n, k))
+    rnd = (lambda v: v.astype(np.float32).astype(np.float64)) if lo == O.LO_FP32 else \
+        np.vectorize(O.round_bf16)
+    Ar, Xr = rnd(A), rnd(X)
+    Y = O.matmul_block(O.Matrix(A, lo=lo), X)
+    exact_rounded_inputs = Ar @ Xr
+    u32 = 2.0 ** -24
+    bound = (n + 1) * u32 * (np.abs(Ar) @ np.abs(Xr))
+    assert np.all(np.abs(Y - exact_rounded_inputs) <= bound)
+    # the inputs really were rounded: far from the FP64 product
+    assert np.max(np.abs(Y - A @ X)) > 1e3 * np.finfo(float).eps * np.max(np.abs(A @ X))
+
+
+def test_ir_fp32_reaches_1e10_and_the_direct_solution():
+    n = 512
+    A = W.dense_spd(n, tag=(4, 50))
+    b = W.rng_for((4, 51)).standard_normal(n)
+    x, info = O.ir_solve(A, b, 8, O.LO_FP32, ir_tol=1e-10, seed=4)
+    assert info["status"] == 0 and info["rel_res_true"] <= 1e-10
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-10
+    assert 2 <= info["outer_iterations"] <= 4
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= np.linalg.cond(A) * 1e-10
+
+
+def test_ir_bf16_contracts_on_a_well_conditioned_system():
+    A = W.tiny_spd(300, 20.0, tag=(4, 54, 300))
+    b = W.rng_for((4, 55, 300)).standard_normal(300)
+    x, info = O.ir_solve(A, b, 16, O.LO_BF16, ir_tol=1e-10, seed=5)
+    assert info["status"] == 0 and not info["stalled"]
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-10
+    # each outer step gains at least the BF16 operator's own accuracy factor
+    assert info["outer_iterations"] <= 8
+
+
+def test_ir_takes_back_a_step_that_does_not_help():
+    # BF16 rounding of this kappa ~ 4e3 matrix is larger than its smallest
+    # eigenvalue: the first outer step cannot lower the FP64 residual
+    A = W.dense_spd(256, tag=(4, 52))
+    b = W.rng_for((4, 53)).standard_normal(256)
+    x, info = O.ir_solve(A, b, 8, O.LO_BF16, ir_tol=1e-10, inner_tol=1e-2, seed=4)
+    assert info["stalled"] and info["status"] == 1
+    assert info["rel_res_true"] == 1.0 and not np.any(x)
