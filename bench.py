@@ -67,7 +67,7 @@ def traffic_from_profiles(s: int):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_baseline(A, b, s, seed, iters_gpu, budget_s):
+def cpu_baseline(A, b, s, seed, iters_gpu, budget_s, what="128^3 diffusion"):
     """The oracle (single thread) on a bounded sample of the same solve: it is
     run for 1, 3 and 3 + k iterations, the per-iteration time and the fixed
     cost are fitted, and the time-to-solution is projected to the GPU's
@@ -89,7 +89,7 @@ def cpu_baseline(A, b, s, seed, iters_gpu, budget_s):
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle MBPCG on the same 128^3 system, s={s}: runs of 1, 3 and {3 + k} "
+        "sample": (f"oracle MBPCG on the same {what} system, s={s}: runs of 1, 3 and {3 + k} "
                    f"iterations; fixed cost {fixed:.2f} s + {per:.3f} s/iteration, projected to "
                    f"the GPU's {iters_gpu} iterations"),
     }
@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="diffusion3d",
-                    choices=("diffusion3d", "dense", "dense-mixed", "batch"))
+                    choices=("diffusion3d", "poisson2d", "dense", "dense-mixed", "batch"))
     ap.add_argument("--s", type=int, default=DEFAULT_S)
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--n", type=int, default=0, help="dense order (default 8192 / 16384)")
@@ -138,7 +138,7 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "diffusion3d":
+    if args.workload in ("diffusion3d", "poisson2d"):
         bench_sparse(args)
     elif args.workload == "batch":
         bench_batch(args)
@@ -153,13 +153,15 @@ def bench_sparse(args):
     from paper_2608_07327_amd import mbpcg as M
     from paper_2608_07327_amd import workloads as W
 
-    A = W.diffusion3d(args.grid)
-    b = W.rhs(A.n, W.CFG_DIFFUSION3D)
+    pois = args.workload == "poisson2d"
+    cfg = W.CFG_POISSON2D if pois else W.CFG_DIFFUSION3D
+    A = W.poisson2d(64) if pois else W.diffusion3d(args.grid)
+    b = W.rhs(A.n, cfg)
     s = args.s
     S = 1
     while S < s:
         S *= 2
-    seed = W.uniform_block_seed(W.CFG_DIFFUSION3D, s)
+    seed = W.uniform_block_seed(cfg, s)
     dev = torch.device("cuda:0")
     solver = M.Solver.from_matrix(A)
     bd = torch.as_tensor(b, device=dev)
@@ -210,11 +212,17 @@ def bench_sparse(args):
         run(solver.solve, s=s, seed=seed)
     torch.cuda.synchronize()
     sec_graph = (time.perf_counter() - g0) / args.steps
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(args.steps):
+        run(solver.cg_solve)
+    torch.cuda.synchronize()
+    cg_sec_graph = (time.perf_counter() - g0) / args.steps
 
     spmm_ms = sum(i["ms_spmm"] for i in infos) / max(1, sum(i["spmm_launches"] for i in infos))
     bytes_alg = 12 * A.nnz + 4 * (A.n + 1) + 16 * A.n * S
     achieved = bytes_alg / (spmm_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(S)
+    traffic = None if pois else traffic_from_profiles(S)
     it = infos[-1]["iterations"]
     phases = [v / max(1, it) for v in infos[-1]["ms_phase"][:5]]
 
@@ -222,7 +230,7 @@ def bench_sparse(args):
     if not args.no_sweep:
         sweep = {}
         for sw in (1, 2, 4, 8, 16):
-            inf = run(solver.solve, s=sw, seed=W.uniform_block_seed(W.CFG_DIFFUSION3D, sw),
+            inf = run(solver.solve, s=sw, seed=W.uniform_block_seed(cfg, sw),
                       profile=1)
             Sw = 1
             while Sw < sw:
@@ -241,7 +249,8 @@ def bench_sparse(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(A, b, s, seed, it, args.cpu_seconds)
+        cpu = cpu_baseline(A, b, s, seed, it, args.cpu_seconds, "64^2 Poisson" if pois else
+                           f"{args.grid}^3 diffusion")
 
     out = {
         "metric": "time-to-solution at rel.res 1e-8 (MBPCG; plain CG on the same GPU beside it)",
@@ -257,7 +266,9 @@ def bench_sparse(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"diffusion3d {args.grid}^3 7-point, lognormal(sigma=1) coefficients, "
+            "workload": (f"poisson2d 64^2 5-point, b~N(0,1), Jacobi scaling, tol 1e-8, MBPCG s={s} "
+                         "(L2-resident: latency-bound, no meaningful HBM roofline)") if pois else
+                        f"diffusion3d {args.grid}^3 7-point, lognormal(sigma=1) coefficients, "
                         f"b~N(0,1), Jacobi scaling, tol 1e-8, MBPCG s={s}",
             "n": A.n, "nnz": A.nnz, "s": s,
         },
@@ -267,6 +278,8 @@ def bench_sparse(args):
         "cg_iterations": cg_infos[-1]["iterations"],
         "speedup_vs_cg": round(cg_sec / sec, 4),
         "seconds_graph_mode": round(sec_graph, 6),
+        "cg_seconds_graph_mode": round(cg_sec_graph, 6),
+        "speedup_vs_cg_graph_mode": round(cg_sec_graph / sec_graph, 4),
         "ms_per_iter_phases": dict(zip(["product", "xi", "update", "qr", "dir"],
                                        [round(v, 4) for v in phases])),
         "roofline": {
