@@ -140,7 +140,7 @@ typedef struct {
     int32_t cols_per_lane;   /* adjacent columns of P one lane gathers per nonzero (1, 2, 4) */
     int32_t loads_in_flight; /* gathers a lane issues before it consumes the first */
     int32_t workgroups;      /* grid of the block-product kernel */
-    int32_t reserved;
+    int32_t waves_per_simd;  /* occupancy the kernel was compiled for (0: compiler's choice) */
     double ms;               /* mean duration of one block product with this shape */
 } mbpcg_tile_shape;
 

@@ -255,6 +255,7 @@ mbpcg_status mbpcg_tile_shapes(int32_t s, mbpcg_tile_shape* out, int32_t cap, in
         out[i].lanes_per_row = mb::spmm_lanes_per_row(s, sh[i]);
         out[i].cols_per_lane = sh[i].V;
         out[i].loads_in_flight = sh[i].U;
+        out[i].waves_per_simd = sh[i].W;
     }
     if (count) *count = k;
     return MBPCG_OK;

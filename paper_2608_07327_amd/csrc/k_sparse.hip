@@ -17,7 +17,7 @@
 //  - S = 4: the tile's P rows (staged in LDS next to the row pointers) and Q
 //    rows (from the lanes) feed a per-thread fixed-order sum of one entry.
 //  - S >= 8: the same LDS tiles feed the 16 x 16 x 4 FP64 MFMA.
-// The tuned shape is (T, SL, V, U) plus the grid size.
+// The tuned shape is (T, SL, V, U, W) plus the grid size.
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -27,9 +27,10 @@
 
 namespace mb {
 
-template <int S_, int T_, int SL_, int V_, int U_>
+template <int S_, int T_, int SL_, int V_, int U_, int W_ = 0>
 struct BpShape {
     static constexpr int S = S_, T = T_, SL = SL_, V = V_, U = U_;
+    static constexpr int W = W_;                       // requested waves per SIMD (0: free)
     static constexpr int CPR = S / V;                  // lanes per row and slot
     static constexpr int LPR = CPR * SL;               // lanes per row
     static constexpr int RPP = MB_BLOCK / LPR;         // rows per pass of the block
@@ -66,7 +67,8 @@ __device__ __forceinline__ void store_cols(double* p, const double* x) {
 }
 
 template <class B>
-__global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ rowptr,
+__global__ __launch_bounds__(MB_BLOCK) __attribute__((amdgpu_waves_per_eu(B::W > 0 ? B::W : 1)))
+void k_spmm(const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ colind,
                                                    const double* __restrict__ vals, int64_t n,
                                                    const double* __restrict__ P,
@@ -249,20 +251,27 @@ __global__ __launch_bounds__(MB_BLOCK) void k_spmm(const int32_t* __restrict__ r
     }
 }
 
-// ---- compiled shapes (S, T, SL, V, U)
+// ---- compiled shapes (S, T, SL, V, U[, W]); W asks the compiler to fit W
+// wavefronts per SIMD (fewer registers, more gathers in flight per CU)
 using BpShapes = std::tuple<
     BpShape<1, 64, 1, 1, 8>, BpShape<1, 128, 1, 1, 8>, BpShape<1, 256, 1, 1, 8>,
     BpShape<1, 64, 2, 1, 4>, BpShape<1, 128, 2, 1, 4>, BpShape<1, 256, 2, 1, 4>,
     BpShape<2, 64, 1, 2, 8>, BpShape<2, 128, 1, 2, 8>, BpShape<2, 256, 1, 2, 8>,
     BpShape<2, 128, 1, 2, 4>, BpShape<2, 256, 1, 2, 4>, BpShape<2, 128, 2, 2, 4>,
+    BpShape<2, 128, 1, 2, 8, 8>,
     BpShape<4, 64, 1, 2, 4>, BpShape<4, 128, 1, 2, 4>, BpShape<4, 64, 1, 2, 8>,
     BpShape<4, 128, 1, 2, 8>, BpShape<4, 128, 1, 4, 4>, BpShape<4, 256, 1, 4, 4>,
     BpShape<4, 128, 2, 2, 4>,
+    BpShape<4, 64, 1, 2, 8, 8>, BpShape<4, 128, 1, 2, 8, 6>, BpShape<4, 64, 1, 4, 4, 8>,
+    BpShape<4, 128, 1, 4, 4, 6>,
     BpShape<8, 32, 1, 2, 8>, BpShape<8, 64, 1, 2, 8>, BpShape<8, 64, 1, 2, 4>,
     BpShape<8, 128, 1, 2, 4>, BpShape<8, 64, 1, 4, 4>, BpShape<8, 128, 1, 4, 4>,
+    BpShape<8, 32, 1, 2, 8, 8>, BpShape<8, 64, 1, 2, 8, 6>, BpShape<8, 64, 1, 4, 4, 6>,
     BpShape<16, 32, 1, 2, 8>, BpShape<16, 32, 1, 2, 4>, BpShape<16, 64, 1, 2, 8>,
     BpShape<16, 32, 1, 4, 4>, BpShape<16, 64, 1, 4, 4>,
-    BpShape<32, 32, 1, 2, 8>, BpShape<32, 32, 1, 2, 4>, BpShape<32, 32, 1, 4, 4>>;
+    BpShape<16, 32, 1, 2, 8, 6>, BpShape<16, 32, 1, 4, 4, 6>, BpShape<16, 32, 1, 2, 4, 8>,
+    BpShape<32, 32, 1, 2, 8>, BpShape<32, 32, 1, 2, 4>, BpShape<32, 32, 1, 4, 4>,
+    BpShape<32, 32, 1, 2, 8, 5>, BpShape<32, 32, 1, 4, 4, 5>>;
 
 template <class F, class... Bs>
 static bool any_shape(F&& f, std::tuple<Bs...>*) {
@@ -271,7 +280,8 @@ static bool any_shape(F&& f, std::tuple<Bs...>*) {
 
 template <class B>
 static bool shape_is(const B&, int S, const SpmmShape& sh) {
-    return B::S == S && B::T == sh.T && B::SL == sh.SL && B::V == sh.V && B::U == sh.U;
+    return B::S == S && B::T == sh.T && B::SL == sh.SL && B::V == sh.V && B::U == sh.U &&
+           B::W == sh.W;
 }
 
 bool spmm_valid_shape(int S, const SpmmShape& sh) {
@@ -283,7 +293,7 @@ int spmm_shape_list(int S, SpmmShape* out, int cap) {
     any_shape(
         [&](auto b) {
             using B = decltype(b);
-            if (B::S == S && k < cap) out[k++] = SpmmShape{B::T, B::SL, B::V, B::U};
+            if (B::S == S && k < cap) out[k++] = SpmmShape{B::T, B::SL, B::V, B::U, B::W};
             return false;
         },
         (BpShapes*)nullptr);

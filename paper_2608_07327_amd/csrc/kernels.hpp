@@ -31,9 +31,10 @@ __host__ __device__ constexpr int stream_tile(int S) { return 1024 / S; }
 
 // ---- block product Q = A P (+ lower triangle of P^T Q per workgroup).
 // Shape: T rows per tile, SL slots per row, V adjacent columns per lane, U
-// gathers in flight per lane; only the compiled combinations are valid.
+// gathers in flight per lane, W requested wavefronts per SIMD (0: the
+// compiler's choice); only the compiled combinations are valid.
 struct SpmmShape {
-    int T = 0, SL = 0, V = 0, U = 0;
+    int T = 0, SL = 0, V = 0, U = 0, W = 0;
 };
 hipError_t launch_spmm(int S, const SpmmShape& sh, int nwg, const CsrDev& A, const double* P,
                        double* Q, double* part, const DevState* st, hipStream_t stream);

@@ -256,7 +256,9 @@ static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist) {
 }
 
 static mbpcg_status get_graph(Ctx& c, const Plan& pl, int m, int cg, hipGraphExec_t* out) {
-    auto key = std::make_tuple(cg * 2 + c.dense, pl.S, m, pl.sp.T * 1000 + pl.sp.SL * 100 + pl.sp.V * 10 + pl.sp.U, pl.nwg_spmm, (int)pl.kind);
+    auto key = std::make_tuple(cg * 2 + c.dense, pl.S, m,
+                               pl.sp.T * 10000 + pl.sp.SL * 1000 + pl.sp.V * 100 + pl.sp.U * 10 + pl.sp.W,
+                               pl.nwg_spmm, (int)pl.kind);
     auto it = c.graphs.find(key);
     if (it != c.graphs.end()) {
         *out = it->second;
@@ -805,8 +807,8 @@ mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out) {
     CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
     Tuning best_t{pl.sp, pl.nwg_spmm};
     double best = 1e30;
-    SpmmShape shapes[32];
-    const int nsh = spmm_shape_list(S, shapes, 32);
+    SpmmShape shapes[64];
+    const int nsh = spmm_shape_list(S, shapes, 64);
     for (int k = 0; k < nsh; ++k) {
         const SpmmShape sh = shapes[k];
         const int64_t tiles = (c.n + sh.T - 1) / sh.T;
@@ -836,6 +838,7 @@ mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out) {
         out->lanes_per_row = spmm_lanes_per_row(S, best_t.sh);
         out->cols_per_lane = best_t.sh.V;
         out->loads_in_flight = best_t.sh.U;
+        out->waves_per_simd = best_t.sh.W;
         out->workgroups = best_t.nwg;
         out->ms = best;
     }
@@ -849,6 +852,7 @@ mbpcg_status set_shape_entry(Ctx& c, int s, const mbpcg_tile_shape& t) {
     sh.T = t.tile_rows;
     sh.V = t.cols_per_lane;
     sh.U = t.loads_in_flight;
+    sh.W = t.waves_per_simd;
     sh.SL = t.lanes_per_row * t.cols_per_lane / S;
     if (sh.SL * S != t.lanes_per_row * t.cols_per_lane || !spmm_valid_shape(S, sh))
         return MBPCG_ERR_UNSUPPORTED;

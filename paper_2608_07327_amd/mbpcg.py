@@ -62,10 +62,10 @@ class System(C.Structure):
 class TileShape(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("lanes_per_row", C.c_int32),
                 ("cols_per_lane", C.c_int32), ("loads_in_flight", C.c_int32),
-                ("workgroups", C.c_int32), ("reserved", C.c_int32), ("ms", C.c_double)]
+                ("workgroups", C.c_int32), ("waves_per_simd", C.c_int32), ("ms", C.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class MbpcgError(RuntimeError):

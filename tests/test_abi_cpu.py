@@ -119,6 +119,7 @@ def test_tile_shapes_listing():
             assert slots in (1, 2) and slots * s == L * V
             assert sh["tile_rows"] in (32, 64, 128, 256)
             assert sh["loads_in_flight"] in (4, 8)
+            assert sh["waves_per_simd"] in (0, 5, 6, 8)
     L = M.load()
     cnt = C.c_int32()
     assert L.mbpcg_tile_shapes(3, None, 0, C.byref(cnt)) == M.ERR_UNSUPPORTED
