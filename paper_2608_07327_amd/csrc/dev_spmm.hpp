@@ -1,5 +1,6 @@
 // One tile of the CSR block product Q = A P (row-major P, Q with S columns),
-// shared by the single-system kernel and the batched persistent kernel.
+// as the batched persistent kernel computes it (the single-system kernel in
+// k_sparse.hip has its own tile loop with vector gathers and tuned shapes).
 //
 // The tile's row pointers and then its slice of column indices and values
 // (one contiguous range of the CSR arrays) are copied into LDS with
