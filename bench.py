@@ -51,9 +51,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(s: int):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
+def shape_key(S: int, t: dict) -> str:
+    """S,T,SL,V,U,W of a tile shape as returned by Solver.autotune."""
+    slots = t["lanes_per_row"] * t["cols_per_lane"] // S
+    return ",".join(str(v) for v in (S, t["tile_rows"], slots, t["cols_per_lane"],
+                                     t["loads_in_flight"], t["waves_per_simd"]))
+
+
+def traffic_from_profiles(key: str):
+    """HBM bytes per launch of the block-product shape `key` from committed
+    rocprofv3 counter runs, if they were taken on the current kernel source;
+    else None."""
     path = os.path.join(ROOT, "profiles", "spmm_diffusion3d_128_traffic.json")
     if not os.path.exists(path):
         return None
@@ -63,7 +71,7 @@ def traffic_from_profiles(s: int):
         return None
     if rec.get("kernel_hash") != kernel_source_hash():
         return None
-    ent = rec.get("per_s", {}).get(str(s))
+    ent = rec.get("per_shape", {}).get(key)
     return None if ent is None else ent.get("bytes_per_launch")
 
 
@@ -222,7 +230,7 @@ def bench_sparse(args):
     spmm_ms = sum(i["ms_spmm"] for i in infos) / max(1, sum(i["spmm_launches"] for i in infos))
     bytes_alg = 12 * A.nnz + 4 * (A.n + 1) + 16 * A.n * S
     achieved = bytes_alg / (spmm_ms * 1e-3) / 1e9
-    traffic = None if pois else traffic_from_profiles(S)
+    traffic = None if pois else traffic_from_profiles(shape_key(S, tuned[s]))
     it = infos[-1]["iterations"]
     phases = [v / max(1, it) for v in infos[-1]["ms_phase"][:5]]
 
