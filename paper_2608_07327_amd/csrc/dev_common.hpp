@@ -63,6 +63,16 @@ __device__ __forceinline__ void tri_ij(int e, int& i, int& j) {
     j = e - r * (r + 1) / 2;
 }
 
+// Loads and stores of data that is touched once per iteration and not again
+// before a whole iteration (about a gigabyte at 128^3, s = 4) has streamed
+// past it -- the CSR arrays, X~ and R -- are non-temporal, so that the blocks
+// the next kernel reads again (P, Q, V, W) stay in the 256 MB last-level
+// cache.  Measured in a full solve: 10 % less time per iteration at s = 4.
+template <class T>
+__device__ __forceinline__ T stream_load(const T* p) { return __builtin_nontemporal_load(p); }
+template <class T>
+__device__ __forceinline__ void stream_store(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
 // ---------------------------------------------------------------------------
 // Work split of n rows, in tiles of T rows, over the grid.  On MI355X
 // consecutive workgroup ids land on different XCDs (8 of them, each with its

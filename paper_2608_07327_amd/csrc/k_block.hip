@@ -88,11 +88,11 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
                     trr += q * al[l];
                     tv += q * xi[l];
                 }
-                const double xn = Xt[g] + tx;
-                const double rn = R[g] - trr;
+                const double xn = stream_load(Xt + g) + tx;
+                const double rn = stream_load(R + g) - trr;
                 v = W[g] - tv;
-                Xt[g] = xn;
-                R[g] = rn;
+                stream_store(Xt + g, xn);
+                stream_store(R + g, rn);
                 W[g] = v;
                 const double dr = d[r0 + rl] * rn;
                 nu += dr * dr;

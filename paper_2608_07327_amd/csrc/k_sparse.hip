@@ -146,8 +146,17 @@ void k_spmm(const int32_t* __restrict__ rowptr,
         for (int cb = 0; cb < nzt; cb += NZC) {
             const int cn = min(NZC, nzt - cb);
             for (int e = tid; e < cn; e += MB_BLOCK) {
-                sC[e] = colind[nz0 + cb + e];
-                sV[e] = vals[nz0 + cb + e];
+                // S >= 2: the CSR slice is not read again before a whole
+                // block-CG iteration has evicted it; non-temporal loads keep
+                // P in the last-level cache instead.  S = 1 (CG) moves so
+                // little per iteration that A itself may stay cached.
+                if constexpr (S >= 2) {
+                    sC[e] = stream_load(colind + nz0 + cb + e);
+                    sV[e] = stream_load(vals + nz0 + cb + e);
+                } else {
+                    sC[e] = colind[nz0 + cb + e];
+                    sV[e] = vals[nz0 + cb + e];
+                }
             }
             __syncthreads();
 #pragma unroll
