@@ -452,6 +452,9 @@ def bench_batch(args):
                       "b": torch.as_tensor(y.b, device=dev),
                       "x": torch.empty(y.A.n, dtype=torch.float64, device=dev), "s": y.s})
     seed = 500
+    _, pinfo = M.solve_batch(items, seed=seed, profile=1)   # phase breakdown (stamped run)
+    phases = dict(zip(["product", "xi", "update", "qr", "dir", "termination", "setup", "other"],
+                      [round(v, 3) for v in pinfo[0]["ms_phase"]]))
     for _ in range(args.warmup):
         M.solve_batch(items, seed=seed)
     torch.cuda.synchronize()
@@ -492,6 +495,7 @@ def bench_batch(args):
         "worst_rel_res_true": worst,
         "sequential_seconds": round(seq, 4), "sequential_iterations_sum": sum(seq_its),
         "speedup_vs_sequential": round(seq / sec, 3),
+        "ms_phases_profiled_run": phases,
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out))

@@ -91,7 +91,10 @@ typedef struct {
     double ms_per_iter;        /* loop time / iterations                               */
     double ms_spmm;            /* profile mode: summed time of the block product       */
     int64_t spmm_launches;     /* profile mode: number of block-product launches       */
-    double ms_phase[8];        /* profile mode: product, Xi, updates, QR, P, LS, setup, other */
+    double ms_phase[8];        /* profile mode: product, Xi, updates, QR, P, LS, setup, other;
+                                  a batch reports the whole batch's phases (other =
+                                  kernel time outside them, or the kernel time when
+                                  not profiling) */
     int32_t status;            /* mbpcg_status of this solve (per system in a batch)   */
     int32_t reserved;
 } mbpcg_info;

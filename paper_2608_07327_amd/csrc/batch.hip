@@ -54,6 +54,7 @@ struct BArgs {
     double* bbar;
     double *U, *Y, *X0, *Xt, *R, *W, *P, *Q;
     double* part;
+    long long* tstamp;   // profile: steady-clock stamp after every grid barrier (or null)
 };
 
 // ---------------------------------------------------------------------------
@@ -536,8 +537,15 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     __shared__ int smi[48];
     int* flag = smi + 40;
     BCtl* ctl = a.ctl;
+    int nstamp = 0;
+    auto stamp = [&]() {
+        if (a.tstamp && blockIdx.x == 0 && threadIdx.x == 0) a.tstamp[nstamp] = wall_clock64();
+        ++nstamp;
+    };
+    stamp();
 #define SYNC_OR_QUIT \
-    if (!grid_sync(ctl, a.spin_limit, flag)) return;
+    if (!grid_sync(ctl, a.spin_limit, flag)) return; \
+    stamp();
 
     // --- setup: scaling, b~, ||b||
     FOR_ITEMS {
@@ -715,6 +723,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         if (threadIdx.x == 0) st->rel_true = st->done == DONE_ZERO_RHS ? 0.0 : sqrt(s2) / st->bnorm;
         __syncthreads();
     }
+    stamp();
 #undef SYNC_OR_QUIT
 }
 
@@ -900,6 +909,13 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     a.P = blocks[6];
     a.Q = blocks[7];
     a.part = d_part;
+    // profile: one steady-clock stamp per grid barrier (setup 7, 5 per
+    // iteration, 4 in the last, termination 6, plus start and end)
+    const int64_t max_loops = std::min<int64_t>(p.max_iter, INT32_MAX) + 2;
+    const int64_t nstamps = 1 + 7 + 5 * max_loops + 4 + 6 + 1;
+    long long* d_ts = nullptr;
+    if (p.profile) BCK(B.alloc(&d_ts, nstamps));
+    a.tstamp = d_ts;
 
     // grid: every workgroup co-resident (the barrier needs it)
     int per_cu = 0, cus = 0;
@@ -959,6 +975,23 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
                            stream));
     BCK(hipStreamSynchronize(stream));
     const double ms_kernel = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    // phase totals as in mbpcg_info.ms_phase: 0 block product, 1 Xi tail,
+    // 2 update, 3 QR tail, 4 direction update, 5 termination, 6 setup
+    double ph_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (d_ts) {
+        const int64_t L = hctl.loops;
+        const int64_t used = 1 + 7 + 5 * L + 4 + 6 + 1;
+        std::vector<long long> ts(used);
+        BCK(hipMemcpy(ts.data(), d_ts, sizeof(long long) * used, hipMemcpyDeviceToHost));
+        int khz = 0;
+        BCK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        const double ms_per_tick = khz > 0 ? 1.0 / khz : 0.0;
+        auto span = [&](int64_t i) { return (double)(ts[i] - ts[i - 1]) * ms_per_tick; };
+        for (int64_t i = 1; i <= 7; ++i) ph_ms[6] += span(i);
+        for (int64_t it = 0; it <= L; ++it)
+            for (int q = 0; q < (it < L ? 5 : 4); ++q) ph_ms[q] += span(8 + 5 * it + q);
+        for (int64_t i = 8 + 5 * L + 4; i < used; ++i) ph_ms[5] += span(i);
+    }
     const double ms_all = std::chrono::duration<double, std::milli>(t2 - t0).count();
     mbpcg_status worst = MBPCG_OK;
     for (int i = 0; i < nsys; ++i) {
@@ -987,7 +1020,12 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
             f.rel_res_true = s.rel_true;
             f.ms_total = ms_all;
             f.ms_per_iter = hctl.loops > 0 ? ms_kernel / hctl.loops : 0.0;
-            f.ms_phase[7] = ms_kernel;
+            double acc = 0.0;
+            for (int q = 0; q < 7; ++q) {
+                f.ms_phase[q] = ph_ms[q];
+                acc += ph_ms[q];
+            }
+            f.ms_phase[7] = d_ts ? std::max(0.0, ms_kernel - acc) : ms_kernel;
             f.status = st;
         }
     }
