@@ -785,6 +785,7 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     do {                                                                       \
         hipError_t _e = (expr);                                                \
         if (_e != hipSuccess) {                                                \
+            (void)hipGetLastError(); /* reported through the status */         \
             err = std::string(#expr) + ": " + hipGetErrorString(_e);          \
             return _e == hipErrorOutOfMemory ? MBPCG_ERR_OOM : MBPCG_ERR_HIP;  \
         }                                                                      \

@@ -14,6 +14,7 @@ namespace mb {
     do {                                                                              \
         hipError_t _e = (expr);                                                       \
         if (_e != hipSuccess) {                                                       \
+            (void)hipGetLastError(); /* the status is ours to report, not the caller's */ \
             c.err = std::string(#expr) + " failed: " + hipGetErrorString(_e);        \
             return _e == hipErrorOutOfMemory ? MBPCG_ERR_OOM : MBPCG_ERR_HIP;         \
         }                                                                             \
@@ -227,32 +228,57 @@ static hipError_t staged_partials(Ctx& c, int nwg, int E, const double* part,
     return launch_part_reduce(nwg, E, part, c.part_r, PART_REDUCE_G, c.st, c.stream);
 }
 
-static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist) {
+// One iteration of Alg. 1's loop, from Xi to the new Sigma.  With ev (six
+// events) the phase boundaries are recorded: ev[0] before the product, ev[1]
+// after it, ev[2] after the Xi tail, ev[3] after the update, ev[4] after the
+// QR tail, ev[5] after the direction update.
+static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist,
+                                   const hipEvent_t* ev = nullptr) {
     hipError_t e;
     const double* pr;
     int pn;
+    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], c.stream) : hipSuccess; };
+    if ((e = mark(0)) != hipSuccess) return e;
     if ((e = launch_product(c, pl, c.P, c.Q, c.part_a, c.st)) != hipSuccess) return e;
+    if ((e = mark(1)) != hipSuccess) return e;
     if ((e = staged_partials(c, pl.nwg_prod, tri_count(pl.S), c.part_a, &pr, &pn)) != hipSuccess)
         return e;
     if ((e = launch_tail_xi(pl.S, pn, pr, c.st, c.stream)) != hipSuccess) return e;
+    if ((e = mark(2)) != hipSuccess) return e;
     if ((e = launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d, c.part_b, c.st,
                            c.stream)) != hipSuccess)
         return e;
+    if ((e = mark(3)) != hipSuccess) return e;
     if ((e = staged_partials(c, pl.nwg_upd, tri_count(pl.S) + pl.S, c.part_b, &pr, &pn)) !=
         hipSuccess)
         return e;
-    if ((e = launch_tail_qr(pl.S, pn, pr, c.st, hist, 0, c.stream)) != hipSuccess)
+    if ((e = launch_tail_qr(pl.S, pn, pr, c.st, hist, 0, c.stream)) != hipSuccess) return e;
+    if ((e = mark(4)) != hipSuccess) return e;
+    if ((e = launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st,
+                              c.stream)) != hipSuccess)
         return e;
-    return launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st, c.stream);
+    return mark(5);
 }
 
-static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist) {
+// One CG-CG step.  With ev: ev[0] before the vector update, ev[1] after it,
+// ev[2] after the SpMV, ev[3..5] after the tail.
+static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist,
+                                      const hipEvent_t* ev = nullptr) {
     hipError_t e;
+    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], c.stream) : hipSuccess; };
+    if ((e = mark(0)) != hipSuccess) return e;
     if ((e = launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c, c.st,
                               c.stream)) != hipSuccess)
         return e;
+    if ((e = mark(1)) != hipSuccess) return e;
     if ((e = launch_product(c, pl, c.R, c.Q, c.part_a, c.st)) != hipSuccess) return e;
-    return launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, hist, c.stream);
+    if ((e = mark(2)) != hipSuccess) return e;
+    if ((e = launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, hist, c.stream)) !=
+        hipSuccess)
+        return e;
+    for (int k = 3; k < 6; ++k)
+        if ((e = mark(k)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 static mbpcg_status get_graph(Ctx& c, const Plan& pl, int m, int cg, hipGraphExec_t* out) {
@@ -307,51 +333,26 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
     const int m = p.poll_every > 0 ? p.poll_every : auto_poll(c, cg);
     const double t0 = now_ms();
     if (p.profile) {
-        // Direct launches with HIP events between the kernels of every
-        // iteration (the per-step timing of Sec. 3, Table 2), polled like the
-        // graph path so the host never waits inside an iteration.
+        // The iterations are launched directly, with HIP events between the
+        // kernels of every iteration (the per-step timing of Sec. 3, Table 2;
+        // events recorded inside graphs do not carry timestamps here), and
+        // polled like the graph path so the host never waits inside an
+        // iteration.
         constexpr int EV = 6;
         const int64_t max_it = p.max_iter + 2 * (int64_t)m + 2;
         int64_t issued = 0;
-        int64_t launched_batches = 0;
         auto issue_batch = [&](int slot) -> mbpcg_status {
             for (int i = 0; i < m && issued < max_it; ++i, ++issued) {
-                if ((int64_t)c.pev.size() < (issued + 1) * EV) {
-                    for (int k = 0; k < EV * 64; ++k) {
-                        hipEvent_t e;
-                        CK(hipEventCreate(&e));
-                        c.pev.push_back(e);
-                    }
+                while ((int64_t)c.pev.size() < (issued + 1) * EV) {
+                    hipEvent_t e;
+                    CK(hipEventCreate(&e));
+                    c.pev.push_back(e);
                 }
-                hipEvent_t* ev = &c.pev[issued * EV];
-                CK(hipEventRecord(ev[0], c.stream));
-                if (cg) {
-                    CK(launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c,
-                                        c.st, c.stream));
-                    CK(hipEventRecord(ev[1], c.stream));
-                    CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
-                    CK(hipEventRecord(ev[2], c.stream));
-                    CK(launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, c.hist,
-                                      c.stream));
-                    for (int k = 3; k < EV; ++k) CK(hipEventRecord(ev[k], c.stream));
-                } else {
-                    CK(launch_product(c, pl, c.P, c.Q, c.part_a, c.st));
-                    CK(hipEventRecord(ev[1], c.stream));
-                    CK(launch_tail_xi(pl.S, pl.nwg_prod, c.part_a, c.st, c.stream));
-                    CK(hipEventRecord(ev[2], c.stream));
-                    CK(launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d,
-                                     c.part_b, c.st, c.stream));
-                    CK(hipEventRecord(ev[3], c.stream));
-                    CK(launch_tail_qr(pl.S, pl.nwg_upd, c.part_b, c.st, c.hist, 0, c.stream));
-                    CK(hipEventRecord(ev[4], c.stream));
-                    CK(launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st,
-                                        c.stream));
-                    CK(hipEventRecord(ev[5], c.stream));
-                }
+                const hipEvent_t* ev = &c.pev[issued * EV];
+                CK(cg ? launch_cg_iteration(c, pl, c.hist, ev) : launch_iteration(c, pl, c.hist, ev));
             }
             CK(hipMemcpyAsync(c.pinned + 2 * slot, c.st, 8, hipMemcpyDeviceToHost, c.stream));
             CK(hipEventRecord(c.ev_poll[slot], c.stream));
-            ++launched_batches;
             return MBPCG_OK;
         };
         CKS(issue_batch(0));
@@ -364,22 +365,22 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
             CKS(issue_batch(slot));
         }
         CK(hipStreamSynchronize(c.stream));
+        *ms_loop = now_ms() - t0;
         CKS(read_state(c));
         const int64_t ran = std::min<int64_t>(c.st_host->iter, issued);
         for (int64_t i = 0; i < ran; ++i) {
-            hipEvent_t* ev = &c.pev[i * EV];
-            float ms = 0.f;
-            const int prod_a = cg ? 1 : 0, prod_b = cg ? 2 : 1;
-            CK(hipEventElapsedTime(&ms, ev[prod_a], ev[prod_b]));
-            *prof_ms += ms;
-            *prof_n += 1.0;
+            const hipEvent_t* ev = &c.pev[i * EV];
             for (int k = 0; k + 1 < EV; ++k) {
+                float ms = 0.f;
                 CK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
-                const int ph = cg ? (k == 1 ? 0 : (k == 0 ? 2 : 7)) : k;
-                c.phase_ms[ph] += ms;
+                const int q = cg ? (k == 1 ? 0 : (k == 0 ? 2 : 7)) : k;
+                c.phase_ms[q] += ms;
+                if (k == (cg ? 1 : 0)) {
+                    *prof_ms += ms;
+                    *prof_n += 1.0;
+                }
             }
         }
-        *ms_loop = now_ms() - t0;
         return MBPCG_OK;
     }
     hipGraphExec_t g = nullptr;
