@@ -109,3 +109,19 @@ def test_batch_matches_single_solves():
         if i1["iterations"] == info["iterations"]:
             xb = it["x"].cpu().numpy()
             assert np.linalg.norm(xb - x1.cpu().numpy()) <= 1e-9 * np.linalg.norm(xb)
+
+
+def test_width_selector_measures_on_the_gpu():
+    # the measurement half of the width model runs end to end and records
+    # converged CG and MBPCG solves (fitting is covered on the CPU)
+    from paper_2608_07327_amd import selector as SEL
+    say("width selector")
+    recs = SEL.measure([("poisson2d m=24", lambda: W.poisson2d(24)),
+                        ("dense n=200", lambda: W.dense_spd(200, tag=(6, 1)))],
+                       widths=(2, 4), reps=1)
+    assert len(recs) == 2
+    for r in recs:
+        assert r["cg_status"] == 0 and r["cg_iterations"] > 0 and r["cg_seconds"] > 0
+        for s in ("2", "4"):
+            m = r["mbpcg"][s]
+            assert m["status"] == 0 and m["rel_res_true"] < 2e-8 and m["seconds"] > 0
