@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--n", type=int, default=0, help="dense order (default 8192 / 16384)")
     ap.add_argument("--count", type=int, default=512, help="systems of the batch workload")
+    ap.add_argument("--shift", type=float, default=1e-3,
+                    help="dense workloads: the shift of G G^T / n + shift I (1e-3 as configured; "
+                         "smaller is harder for CG)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sweep", action="store_true")
@@ -312,7 +315,7 @@ def bench_sparse(args):
     print(json.dumps(out))
 
 
-def dense_on_device(n, tag, torch, dev, shift=1e-3):
+def dense_on_device(n, tag, torch, dev, shift):
     """workloads.dense_spd's recipe with the n^3 product done on the GPU: G iid
     N(0,1) from the same seeded stream, A = G G^T / n with the lower triangle
     mirrored (bitwise symmetric), + shift I.  Input generation only."""
@@ -338,7 +341,7 @@ def bench_dense(args, mixed):
     dev = torch.device("cuda:0")
     n = args.n or (16384 if mixed else 8192)
     cfg = W.CFG_DENSE_MIXED if mixed else W.CFG_DENSE
-    A = dense_on_device(n, cfg, torch, dev)
+    A = dense_on_device(n, cfg, torch, dev, args.shift)
     bd = torch.as_tensor(W.rhs(n, cfg), device=dev)
     x = torch.empty_like(bd)
     solver = M.Solver.from_dense(A)
@@ -410,8 +413,9 @@ def bench_dense(args, mixed):
         "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": prec if prec != "fp64" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"dense SPD A = G G^T/n + 1e-3 I, n={n}, b~N(0,1), no precond, "
-                               f"tol {tol:g}, best of {sorted(runs)}: {pick}", "n": n, "s": sw},
+        "config": {"workload": f"dense SPD A = G G^T/n + {args.shift:g} I, n={n}, b~N(0,1), "
+                               f"no precond, tol {tol:g}, best of {sorted(runs)}: {pick}",
+                   "n": n, "s": sw, "shift": args.shift},
         "iterations": info["iterations"], "rel_res_true": r,
         "cg_seconds": round(cg_sec, 6), "cg_iterations": cg_info["iterations"],
         "cg_rel_res_true": cg_r, "speedup_vs_cg": round(cg_sec / sec, 4),

@@ -83,7 +83,12 @@ typedef struct {
     int32_t best_column;       /* h of Alg. 1 at exit                                  */
     int32_t final_width;       /* columns left after deflation                         */
     int32_t deflations;        /* columns dropped by Cholesky QR                       */
-    int32_t used_fallback;     /* 1: x is the best column, not the LS combination      */
+    int32_t used_fallback;     /* 1: x is the best column, not the LS combination:     */
+                               /* the combination was not finite, missed the tolerance */
+                               /* on B^ c, or (FP64 solves) missed it on its true       */
+                               /* residual while the best column's true residual was    */
+                               /* lower (its coefficients can amplify the rounding      */
+                               /* drift between A X and B - R of Proposition 1)         */
     double rel_res_best_basis; /* ||R_h|| / ||b|| at exit                              */
     double rel_res_ls;         /* ||b - B^ c|| / ||b|| of the LS combination           */
     double rel_res_true;       /* ||b - A x|| / ||b|| recomputed in FP64 on A          */

@@ -52,6 +52,9 @@ typedef struct {
     double* X_out;        /* optional n x s: X = X~ + X0 at exit (scaled space) */
     double* R_out;        /* optional n x s: R at exit (scaled space) */
     double* prop1_gap;    /* optional [max_iter]: ||A X - (B - R)||_F / ||B||_F (scaled) */
+    int check_true;       /* 1: an accepted combination whose true residual is not below
+                             tol gives way to the best column when that column's true
+                             residual is lower (the fallback after Proposition 1) */
 } or_params;
 
 typedef struct {

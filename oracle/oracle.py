@@ -39,7 +39,7 @@ class OrParams(C.Structure):
                 ("max_iter", C.c_int64), ("jacobi", C.c_int), ("seed", C.c_uint64),
                 ("U", C.c_void_p), ("tau", C.c_double), ("ls_scaled", C.c_int),
                 ("history", C.c_void_p), ("X_out", C.c_void_p), ("R_out", C.c_void_p),
-                ("prop1_gap", C.c_void_p)]
+                ("prop1_gap", C.c_void_p), ("check_true", C.c_int)]
 
 
 class OrInfo(C.Structure):
@@ -176,8 +176,11 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -2: "NOT_SPD", -3: "BREAKDOWN", -4: "NONF
 
 def mbpcg_solve(A, b, s, tol=1e-8, tol_initial=0.0, max_iter=100000, jacobi=True, seed=0,
                 U=None, tau=1e-12, ls_scaled=False, want_history=False, want_X=False,
-                want_prop1=False):
-    """Run Algorithm 1 on the CPU.  Returns (x, info dict, extras dict)."""
+                want_prop1=False, check_true=True):
+    """Run Algorithm 1 on the CPU.  Returns (x, info dict, extras dict).
+    check_true: an accepted least-squares combination whose true residual
+    is not below tol gives way to the best column if that column's true
+    residual is lower (used_fallback = 1)."""
     M = A if isinstance(A, Matrix) else Matrix(A)
     n = M.n
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -188,7 +191,7 @@ def mbpcg_solve(A, b, s, tol=1e-8, tol_initial=0.0, max_iter=100000, jacobi=True
     gap = np.full(max_iter, np.nan) if want_prop1 else None
     Uc = None if U is None else np.ascontiguousarray(U, dtype=np.float64)
     p = OrParams(s, tol, tol_initial, max_iter, int(bool(jacobi)), seed, _p(Uc), tau,
-                 int(bool(ls_scaled)), _p(hist), _p(Xo), _p(Ro), _p(gap))
+                 int(bool(ls_scaled)), _p(hist), _p(Xo), _p(Ro), _p(gap), int(bool(check_true)))
     info = OrInfo()
     lib().or_mbpcg_solve(C.byref(M.s), b.ctypes.data, C.byref(p), x.ctypes.data, C.byref(info))
     d = info.as_dict()
@@ -255,7 +258,7 @@ def ir_solve(A, b, s, lo, ir_tol=1e-10, inner_tol=5e-6, max_outer=50, seed=0, ta
     for k in range(1, max_outer + 1):
         tol_k = min(0.1, max(inner_tol, 0.5 * ir_tol / rel))
         d, ii, _ = mbpcg_solve(Mlo, r, s, tol=tol_k, jacobi=False, seed=seed + (k - 1) * 7919,
-                               tau=tau)
+                               tau=tau, check_true=False)
         info["iterations"] += ii["iterations"]
         info["inner_iterations"].append(ii["iterations"])
         info["outer_iterations"] = k

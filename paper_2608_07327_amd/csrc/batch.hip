@@ -22,6 +22,7 @@ namespace mb {
 
 constexpr int BT = 128;        // rows per item
 constexpr int PSTRIDE = 48;    // doubles of partial sums per item
+constexpr int BATCH_TERM_BARRIERS = 9;  // grid barriers of the termination
 constexpr int BSM = 4096;    // LDS doubles of the persistent kernel (32 KB)
 
 struct BSys {
@@ -522,6 +523,46 @@ __device__ void ph_resid(const BArgs& a, const Item& m, double* sm) {
     if (threadIdx.x == 0) a.part[it * PSTRIDE + 1] = tot;
 }
 
+// ||b - A x_h||^2 partial into part[2], x_h = D^-1 (X~ + X0)_h read from the
+// blocks (the best column, when the accepted combination misses the tolerance)
+template <int S>
+__device__ void ph_resid_best(const BArgs& a, const Item& m, double* sm) {
+    const BSys& y = a.sys[m.sys];
+    const int32_t* rp = a.rowptr + y.rp_off;
+    const int32_t* ci = a.colind + y.nz_off;
+    const double* va = a.vals + y.nz_off;
+    const double* b = a.b + y.vec_off;
+    const double* d = a.d + y.vec_off;
+    const double* Xt = a.Xt + y.blk_off;
+    const double* X0 = a.X0 + y.blk_off;
+    const int h = a.st[m.sys].h;
+    double s2 = 0.0;
+    for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK) {
+        const int64_t r = m.r0 + rl;
+        double acc = 0.0;
+        for (int k = rp[r]; k < rp[r + 1]; ++k) {
+            const int64_t c = ci[k];
+            acc += va[k] * ((Xt[c * S + h] + X0[c * S + h]) / d[c]);
+        }
+        const double e = b[r] - acc;
+        s2 += e * e;
+    }
+    const int64_t it = y.item_off + m.r0 / BT;
+    const double tot = block_sum(s2, sm);
+    if (threadIdx.x == 0) a.part[it * PSTRIDE + 2] = tot;
+}
+
+// an accepted combination whose true residual misses the tolerance
+__device__ inline bool needs_pick(const DevState* st) {
+    return st->done == DONE_CONVERGED && st->accepted && !(st->rel_true < st->tol);
+}
+
+// the combination passed the test on B - R but gave way to the best column
+__device__ inline bool was_picked(const DevState* st) {
+    return st->done == DONE_CONVERGED && !st->accepted && st->ls_ok && finite_d(st->rel_ls) &&
+           st->rel_ls < st->tol;
+}
+
 // sum of part[slot] over a system's items (fixed order), result to thread 0
 __device__ double sys_sum(const BArgs& a, const BSys& y, int slot, double* sm) {
     reduce_partials(a.part + (int64_t)y.item_off * PSTRIDE + slot, y.ntile, 1, PSTRIDE, sm,
@@ -723,6 +764,33 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         if (threadIdx.x == 0) st->rel_true = st->done == DONE_ZERO_RHS ? 0.0 : sqrt(s2) / st->bnorm;
         __syncthreads();
     }
+    SYNC_OR_QUIT
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        if (!needs_pick(a.st + m.sys)) continue;
+        DISPATCH_S(a.sys[m.sys].S, ph_resid_best<SS>(a, m, sm))
+    }
+    SYNC_OR_QUIT
+    FOR_SYS {
+        const BSys& y = a.sys[sy_];
+        DevState* st = a.st + sy_;
+        if (!needs_pick(st)) continue;
+        const double s2 = sys_sum(a, y, 2, sm);
+        if (threadIdx.x == 0) {
+            const double rel_h = sqrt(s2) / st->bnorm;
+            if (rel_h < st->rel_true) {
+                st->accepted = 0;
+                st->rel_true = rel_h;
+            }
+        }
+        __syncthreads();
+    }
+    SYNC_OR_QUIT
+    FOR_ITEMS {
+        const Item m = item_of(a, it_);
+        if (!was_picked(a.st + m.sys)) continue;
+        DISPATCH_S(a.sys[m.sys].S, ph_select<SS>(a, m))
+    }
     stamp();
 #undef SYNC_OR_QUIT
 }
@@ -911,9 +979,9 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     a.Q = blocks[7];
     a.part = d_part;
     // profile: one steady-clock stamp per grid barrier (setup 7, 5 per
-    // iteration, 4 in the last, termination 6, plus start and end)
+    // iteration, 4 in the last, termination 9, plus start and end)
     const int64_t max_loops = std::min<int64_t>(p.max_iter, INT32_MAX) + 2;
-    const int64_t nstamps = 1 + 7 + 5 * max_loops + 4 + 6 + 1;
+    const int64_t nstamps = 1 + 7 + 5 * max_loops + 4 + BATCH_TERM_BARRIERS + 1;
     long long* d_ts = nullptr;
     if (p.profile) BCK(B.alloc(&d_ts, nstamps));
     a.tstamp = d_ts;
@@ -981,7 +1049,7 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     double ph_ms[7] = {0, 0, 0, 0, 0, 0, 0};
     if (d_ts) {
         const int64_t L = hctl.loops;
-        const int64_t used = 1 + 7 + 5 * L + 4 + 6 + 1;
+        const int64_t used = 1 + 7 + 5 * L + 4 + BATCH_TERM_BARRIERS + 1;
         std::vector<long long> ts(used);
         BCK(hipMemcpy(ts.data(), d_ts, sizeof(long long) * used, hipMemcpyDeviceToHost));
         int khz = 0;

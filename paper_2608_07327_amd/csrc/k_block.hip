@@ -415,12 +415,13 @@ __global__ __launch_bounds__(MB_BLOCK) void k_ls_apply(int64_t n, const double* 
     }
 }
 
-// fallback to the best column: x = D^-1 (X~ + X0)_h when the combination is not accepted
+// fallback to the best column: x = D^-1 (X~ + X0)_h when the combination is
+// not accepted (force: unconditionally, for the true-residual comparison)
 template <int S>
 __global__ void k_select(int64_t n, const double* __restrict__ Xt, const double* __restrict__ X0,
                          const double* __restrict__ d, double* __restrict__ x,
-                         const DevState* __restrict__ st) {
-    if (st->accepted) return;
+                         const DevState* __restrict__ st, int force) {
+    if (!force && st->accepted) return;
     const int h = st->h;
     const bool ready = st->ready;  // a system that failed in setup returns x = 0
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
@@ -653,10 +654,11 @@ hipError_t launch_ls_apply(int S, int nwg, int64_t n, const double* Xt, const do
 }
 
 hipError_t launch_select(int S, int64_t n, const double* Xt, const double* X0, const double* d,
-                         double* x, const DevState* st, hipStream_t s) {
+                         double* x, const DevState* st, int force, hipStream_t s) {
     const int g = grid_for(n, 4096);
     MB_DISPATCH_S(S, {
-        hipLaunchKernelGGL(k_select<SS>, dim3(g), dim3(MB_BLOCK), 0, s, n, Xt, X0, d, x, st);
+        hipLaunchKernelGGL(k_select<SS>, dim3(g), dim3(MB_BLOCK), 0, s, n, Xt, X0, d, x, st,
+                           force);
         return hipGetLastError();
     })
 }

@@ -72,6 +72,21 @@ __global__ void k_tail_true(const double* __restrict__ part, int nwg, DevState* 
     if (threadIdx.x == 0) st->rel_true = sqrt(out[0]) / st->bnorm;
 }
 
+// true residual of the best column against that of the accepted combination:
+// the column replaces the combination when it is lower (the combination's
+// coefficients can amplify the rounding drift between A X and B - R)
+__global__ void k_tail_pick(const double* __restrict__ part, int nwg, DevState* __restrict__ st) {
+    __shared__ double out[1], tmp[TAIL_THREADS];
+    reduce_partials(part, nwg, 1, 1, out, tmp);
+    if (threadIdx.x == 0) {
+        const double rel_h = sqrt(out[0]) / st->bnorm;
+        if (rel_h < st->rel_true) {
+            st->accepted = 0;
+            st->rel_true = rel_h;
+        }
+    }
+}
+
 // ||b||, ||b~||, ||A U||_F -> gamma (scale of the initial guess)
 __global__ void k_tail_gamma(const double* __restrict__ part_b, int nwg_b,
                              const double* __restrict__ part_y, int nwg_y,
@@ -238,6 +253,11 @@ hipError_t launch_tail_accept(int nwg, const double* part, DevState* st, hipStre
 
 hipError_t launch_tail_true(int nwg, const double* part, DevState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_tail_true, dim3(1), dim3(TAIL_THREADS), 0, s, part, nwg, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_pick(int nwg, const double* part, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_tail_pick, dim3(1), dim3(TAIL_THREADS), 0, s, part, nwg, st);
     return hipGetLastError();
 }
 

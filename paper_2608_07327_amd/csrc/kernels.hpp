@@ -109,7 +109,7 @@ hipError_t launch_ls_apply(int S, int nwg, int64_t n, const double* Xt, const do
                            const double* R, const double* b, const double* d, double* x,
                            double* part, const DevState* st, hipStream_t s);
 hipError_t launch_select(int S, int64_t n, const double* Xt, const double* X0, const double* d,
-                         double* x, const DevState* st, hipStream_t s);
+                         double* x, const DevState* st, int force, hipStream_t s);
 hipError_t launch_resid_csr(int nwg, const CsrDev& A, const double* b, const double* x,
                             double* part, hipStream_t s);
 
@@ -136,6 +136,7 @@ hipError_t launch_tail_qr(int S, int nwg, const double* part, DevState* st, doub
 hipError_t launch_tail_ls(int S, int nwg, const double* part, DevState* st, hipStream_t s);
 hipError_t launch_tail_accept(int nwg, const double* part, DevState* st, hipStream_t s);
 hipError_t launch_tail_true(int nwg, const double* part, DevState* st, hipStream_t s);
+hipError_t launch_tail_pick(int nwg, const double* part, DevState* st, hipStream_t s);
 hipError_t launch_tail_cg0(int nwg_b, const double* part_b, int nwg_s, const double* part_s,
                            DevState* st, hipStream_t s);
 hipError_t launch_tail_cg(int nwg_u, const double* part_u, int nwg_s, const double* part_s,

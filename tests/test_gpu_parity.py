@@ -79,7 +79,17 @@ def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_ite
     assert info["status"] == io["status"], (info, io)
     assert abs(info["iterations"] - io["iterations"]) <= band, \
         (info["iterations"], io["iterations"], ip["iterations"])
-    if info["iterations"] == io["iterations"]:
+    # The choice between the combination and the best column on their true
+    # residuals rests on rounding-sensitive numbers (the combination's
+    # coefficients amplify the drift between A X and B - R, and the two
+    # sides compute the least squares differently): where the oracle's
+    # combination passed the test on B^ c but it returned the best column,
+    # the GPU may keep its own combination, provided that meets tol.
+    picked = io["status"] == 0 and io["used_fallback"] == 1 and io["rel_res_ls"] < tol
+    differ = picked and info["used_fallback"] != io["used_fallback"]
+    if differ:
+        assert info["used_fallback"] == 0 and info["rel_res_true"] < tol, info
+    if info["iterations"] == io["iterations"] and not differ:
         if same:
             bound = max(1e-10, 10 * f)
             assert rel(x, xo) <= bound, (rel(x, xo), bound, f)
@@ -233,6 +243,41 @@ def test_dense_against_oracle(s):
     A = W.dense_spd(600, tag=(3, 41))
     b = W.rng_for((3, 42)).standard_normal(600)
     check_against_oracle(A, b, s, jacobi=False, seed=W.uniform_block_seed(3, s))
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("s", [2, 4, 8])
+def test_near_singular_systems_fall_back_on_the_true_residual(kind, s):
+    # kappa ~ 4e6 dense and a graph Laplacian shifted by 1e-6: the accepted
+    # combination misses tol on its true residual, the best column meets it
+    if kind == "dense":
+        A = W.dense_spd(256, tag=(W.CFG_DENSE, 95, 256), shift=1e-6)
+        b = W.rng_for((96, 256)).standard_normal(256)
+        jac = False
+    else:
+        A = W.graph_laplacian(2000, 8, 1e-6, W.rng_for((W.CFG_BATCH, 91, 2000, 6)))
+        b = W.rng_for((93, 2000)).standard_normal(2000)
+        jac = True
+    x, info, xo, io = check_against_oracle(A, b, s, jacobi=jac, seed=W.uniform_block_seed(97, s))
+    assert io["used_fallback"] == 1 and io["rel_res_true"] < 1e-8
+    assert info["rel_res_true"] < 1e-8
+
+
+@pytest.mark.parametrize("s", [4, 8, 16])
+def test_ill_conditioned_dense_meets_tol_on_the_true_residual(s):
+    # A = G G^T / n + 1e-5 I, n = 2048 (kappa ~ 4e5): here the GPU's own
+    # combination misses tol on its true residual by 6-70x, so the best
+    # column is returned; the residual is recomputed on the host
+    n = 2048
+    A = W.dense_spd(n, tag=(W.CFG_DENSE, 92, n), shift=1e-5)
+    b = W.rng_for((93, 7)).standard_normal(n)
+    say("ill-conditioned dense", n, "s", s)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(dev(b), s=s, precond=M.PRECOND_NONE, seed=W.uniform_block_seed(94, s))
+    solver.close()
+    assert info["status"] == 0 and info["used_fallback"] == 1, info
+    t = np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b)
+    assert t < 1e-8 and abs(info["rel_res_true"] - t) <= 1e-3 * t, (t, info["rel_res_true"])
 
 
 def test_explicit_block_with_duplicate_columns_deflates():

@@ -226,6 +226,40 @@ def test_proposition1_and_best_column_bound():
     assert gap < 1e-12
 
 
+def test_combination_gives_way_to_the_best_column_on_its_true_residual():
+    # A = G G^T / n + 1e-6 I (kappa ~ 4e6).  Every column of X meets the
+    # tolerance on its own true residual, but the columns approach the same
+    # x, the least-squares coefficients grow large and amplify the rounding
+    # drift between A X and B - R (Proposition 1 holds in exact arithmetic
+    # only): X c^ misses the tolerance.  The fallback returns the best column.
+    n = 256
+    A = W.dense_spd(n, tag=(W.CFG_DENSE, 95, n), shift=1e-6)
+    b = W.rng_for((96, n)).standard_normal(n)
+    nb = np.linalg.norm(b)
+    for s in (2, 4, 8):
+        kw = dict(jacobi=False, seed=W.uniform_block_seed(97, s), want_X=True)
+        x0, i0, e0 = O.mbpcg_solve(A, b, s, check_true=False, **kw)
+        x1, i1, _ = O.mbpcg_solve(A, b, s, **kw)
+        assert i0["status"] == i1["status"] == 0
+        assert i0["iterations"] == i1["iterations"] and i0["used_fallback"] == 0
+        X = e0["X"]
+        cols = np.linalg.norm(b[:, None] - A @ X, axis=0) / nb
+        assert cols.max() < 1e-8, cols
+        assert np.linalg.norm(b - A @ x0) / nb > 1e-8
+        h = i1["best_column"]
+        assert i1["used_fallback"] == 1 and np.array_equal(x1, X[:, h])
+        t1 = np.linalg.norm(b - A @ x1) / nb
+        # b - A x cancels to ~1e-8 |b| from |A| |x| ~ 1e6 |b|: two summation
+        # orders agree on it to ~eps * 1e14 relative
+        assert t1 < 1e-8 and abs(i1["rel_res_true"] - t1) <= 1e-3 * t1
+    # a well-conditioned system keeps the combination untouched
+    A = W.poisson2d(32)
+    b = W.rhs(A.n, 41)
+    xa, ia, _ = O.mbpcg_solve(A, b, 4, seed=3, check_true=False)
+    xb, ib, _ = O.mbpcg_solve(A, b, 4, seed=3)
+    assert ib["used_fallback"] == 0 and np.array_equal(xa, xb)
+
+
 def test_solution_matches_direct_solve():
     A = W.poisson2d(64)
     b = W.rhs(A.n, W.CFG_POISSON2D)
