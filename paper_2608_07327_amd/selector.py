@@ -89,7 +89,8 @@ def measure(systems=None, widths=WIDTHS, tol=1e-8, max_iter=20000, reps=2, log=s
         pc = M.PRECOND_NONE if dense else M.PRECOND_JACOBI
         t_cg, icg = _timed(solver.cg_solve, bd, reps, tol=tol, max_iter=max_iter, precond=pc)
         rec = {"name": name, "n": n, "nnz": nnz, "dense": dense, "cg_seconds": t_cg,
-               "cg_iterations": icg["iterations"], "cg_status": icg["status"], "mbpcg": {}}
+               "cg_iterations": icg["iterations"], "cg_status": icg["status"],
+               "cg_rel_res_true": icg["rel_res_true"], "mbpcg": {}}
         for s in widths:
             if not dense:
                 solver.autotune(s)
@@ -118,17 +119,21 @@ def _lstsq(X, y):
     return coef, r2, r2_adj
 
 
-def fit(recs, widths=WIDTHS):
+def fit(recs, widths=WIDTHS, tol=1e-8):
     """Per width, the three model forms of Sec. 5 by least squares on the
     converged pairs: log10 speedup ~ [1, log10 n, log10 nnz, log10 t],
     iteration ratio ~ [1, log10 n, log10 t], log10 per-iteration time ratio
-    ~ [1, log10 n, log10 nnz]."""
+    ~ [1, log10 n, log10 nnz].  A pair counts as converged when both solves
+    report success and their true residuals are below 2 tol."""
     models = {}
     for s in widths:
         rows = []
         for r in recs:
             m = r["mbpcg"].get(str(s))
             if m is None or m["status"] != 0 or r["cg_status"] != 0:
+                continue
+            if not (m.get("rel_res_true", 0.0) < 2 * tol
+                    and r.get("cg_rel_res_true", 0.0) < 2 * tol):
                 continue
             if m["iterations"] <= 0 or r["cg_iterations"] <= 0:
                 continue

@@ -60,6 +60,11 @@ def test_fit_skips_unconverged_pairs_and_small_samples():
     for r in recs[:3]:
         r["mbpcg"]["4"]["status"] = 1
     assert SEL.fit(recs, widths=(4,)) == {}          # 3 usable pairs < 5
+    recs = _records(coef, {4: (0.6, 0.0, 0.0)}, {4: (0.1, 0.0, 0.0)}, widths=(4,), count=7)
+    recs[0]["mbpcg"]["4"]["rel_res_true"] = 5e-7     # reported success, missed tol
+    recs[1]["cg_rel_res_true"] = 3e-8
+    recs[2]["cg_rel_res_true"] = 1e-9
+    assert SEL.fit(recs, widths=(4,))["4"]["samples"] == 5
 
 
 def test_choose_width_prefers_cg_when_nothing_wins():
