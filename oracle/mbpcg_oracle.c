@@ -271,13 +271,13 @@ void or_spd_inverse(int m, const double* L, double* Xi)
  * so V = W Z up to the dropped parts and the recurrences of Alg. 1 keep
  * their form with a rectangular Z.
  * ------------------------------------------------------------------------- */
-int or_cholqr_deflate(int64_t n, int m, const double* V, double tau,
-                      double* W, double* Z, int* keep)
+/* The factorisation half: from the Gram G (m x m; the entries G[l][j], l < j,
+ * and the diagonal are read) to the kept set J (nk columns, keep[] flags),
+ * Z = rows J of U and Mi = U_JJ^{-1} (nk x nk, upper triangular). */
+static int cholqr_factor(int m, const double* G, double tau, double* Z, int* keep, int* J,
+                         double* Mi)
 {
-    double* G = (double*)xcalloc((size_t)(m * m), sizeof(double));
     double* U = (double*)xcalloc((size_t)(m * m), sizeof(double));
-    int* J = (int*)xcalloc((size_t)m, sizeof(int));
-    or_gram(n, m, V, m, V, G);
     int nk = 0;
     for (int j = 0; j < m; ++j) {
         for (int a = 0; a < nk; ++a) {
@@ -301,25 +301,73 @@ int or_cholqr_deflate(int64_t n, int m, const double* V, double tau,
     for (int a = 0; a < nk; ++a)
         for (int j = 0; j < m; ++j) Z[a * m + j] = (j >= J[a]) ? U[J[a] * m + j] : 0.0;
     /* Minv = U_JJ^{-1} by back substitution, column by column */
-    double* Mi = (double*)xcalloc((size_t)(nk * nk + 1), sizeof(double));
     for (int c = 0; c < nk; ++c)
         for (int a = c; a >= 0; --a) {
             double v = (a == c) ? 1.0 : 0.0;
             for (int b = a + 1; b <= c; ++b) v -= U[J[a] * m + J[b]] * Mi[b * nk + c];
             Mi[a * nk + c] = v / U[J[a] * m + J[a]];
         }
+    free(U);
+    return nk;
+}
+
+/* W = V_J Mi (n x nk) for the kept set J of an n x m block V */
+static void apply_kept_inverse(int64_t n, int m, int nk, const int* J, const double* Mi,
+                               const double* V, double* W)
+{
     for (int64_t r = 0; r < n; ++r)
         for (int c = 0; c < nk; ++c) {
             double acc = 0.0;
             for (int a = 0; a <= c; ++a) acc += V[r * m + J[a]] * Mi[a * nk + c];
             W[r * nk + c] = acc;
         }
-    free(Mi);
+}
+
+int or_cholqr_deflate(int64_t n, int m, const double* V, double tau,
+                      double* W, double* Z, int* keep)
+{
+    double* G = (double*)xcalloc((size_t)(m * m), sizeof(double));
+    double* Mi = (double*)xcalloc((size_t)(m * m + 1), sizeof(double));
+    int* J = (int*)xcalloc((size_t)m, sizeof(int));
+    or_gram(n, m, V, m, V, G);
+    int nk = cholqr_factor(m, G, tau, Z, keep, J, Mi);
+    apply_kept_inverse(n, m, nk, J, Mi, V, W);
     free(J);
-    free(U);
+    free(Mi);
     free(G);
     return nk;
 }
+
+/* ---------------------------------------------------------------------------
+ * Preconditioned Cholesky QR (the preconditioned form of Dubrulle-R that the
+ * paper says its method admits, Sec. 2).  With an SPD preconditioner M the
+ * residual basis W is orthonormal in the M^-1 inner product, W^T M^-1 W = I,
+ * and the directions are built from M^-1 W.  Given V and Y = M^-1 V, factor
+ * the Gram V^T Y = U^T U (with the dropping rule of or_cholqr_deflate) and
+ * return W = V_J U_JJ^{-1} and MW = Y_J U_JJ^{-1} (= M^-1 W).  V^T Y is
+ * symmetric in exact arithmetic; the entry used for the pair (i > j) is
+ * V_i^T Y_j.
+ * ------------------------------------------------------------------------- */
+int or_cholqr_deflate_prec(int64_t n, int m, const double* V, const double* Y, double tau,
+                           double* W, double* MW, double* Z, int* keep)
+{
+    double* H = (double*)xcalloc((size_t)(m * m), sizeof(double));
+    double* G = (double*)xcalloc((size_t)(m * m), sizeof(double));
+    double* Mi = (double*)xcalloc((size_t)(m * m + 1), sizeof(double));
+    int* J = (int*)xcalloc((size_t)m, sizeof(int));
+    or_gram(n, m, V, m, Y, H);                 /* H[i][j] = V_i^T Y_j */
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) G[i * m + j] = (i >= j) ? H[i * m + j] : H[j * m + i];
+    int nk = cholqr_factor(m, G, tau, Z, keep, J, Mi);
+    apply_kept_inverse(n, m, nk, J, Mi, V, W);
+    apply_kept_inverse(n, m, nk, J, Mi, Y, MW);
+    free(J);
+    free(Mi);
+    free(G);
+    free(H);
+    return nk;
+}
+
 
 /* ---------------------------------------------------------------------------
  * Least squares min_c ||b - B c|| (Alg. 1, the combination c^ of the termination).  The paper writes
@@ -425,6 +473,93 @@ static void free_scaled(scaled_t* S)
     free(S->d);
 }
 
+/* ---------------------------------------------------------------------------
+ * Block-Jacobi preconditioner: M = the block diagonal of the (scaled) matrix
+ * with blocks of bs consecutive rows (the last one shorter when bs does not
+ * divide n).  Each block is factored by the textbook Cholesky; M^-1 X is
+ * formed block by block by forward and back substitution.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int bs;
+    int64_t n, nblk;
+    double* L; /* nblk blocks of bs x bs, lower factor, row-major */
+} bjac_t;
+
+static int bjac_setup(const or_matrix* A, int bs, bjac_t* M)
+{
+    int64_t n = A->n;
+    M->bs = bs;
+    M->n = n;
+    M->nblk = (n + bs - 1) / bs;
+    M->L = (double*)xcalloc((size_t)(M->nblk * bs * bs), sizeof(double));
+    double* B = (double*)xcalloc((size_t)(bs * bs), sizeof(double));
+    int rc = OR_OK;
+    for (int64_t k = 0; k < M->nblk && rc == OR_OK; ++k) {
+        int64_t lo = k * bs, hi = lo + bs < n ? lo + bs : n;
+        int nb = (int)(hi - lo);
+        memset(B, 0, sizeof(double) * (size_t)(bs * bs));
+        for (int64_t r = lo; r < hi; ++r) {
+            if (A->dense) {
+                for (int64_t c = lo; c < hi; ++c) B[(r - lo) * nb + (c - lo)] = A->a[c * A->lda + r];
+            } else {
+                for (int32_t e = A->rowptr[r]; e < A->rowptr[r + 1]; ++e) {
+                    int64_t c = A->colind[e];
+                    if (c >= lo && c < hi) B[(r - lo) * nb + (c - lo)] += A->vals[e];
+                }
+            }
+        }
+        if (or_cholesky(nb, B, M->L + k * bs * bs) != 0) rc = OR_ERR_NOT_SPD;
+    }
+    free(B);
+    return rc;
+}
+
+/* Y = M^-1 X for an n x m row-major block */
+static void bjac_apply(const bjac_t* M, int m, const double* X, double* Y)
+{
+    int bs = M->bs;
+    double* z = (double*)xcalloc((size_t)bs, sizeof(double));
+    for (int64_t k = 0; k < M->nblk; ++k) {
+        int64_t lo = k * bs, hi = lo + bs < M->n ? lo + bs : M->n;
+        int nb = (int)(hi - lo);
+        const double* L = M->L + k * bs * bs;
+        for (int j = 0; j < m; ++j) {
+            for (int i = 0; i < nb; ++i) {      /* L z = x */
+                double v = X[(lo + i) * m + j];
+                for (int c = 0; c < i; ++c) v -= L[i * nb + c] * z[c];
+                z[i] = v / L[i * nb + i];
+            }
+            for (int i = nb - 1; i >= 0; --i) { /* L^T y = z */
+                double v = z[i];
+                for (int c = i + 1; c < nb; ++c) v -= L[c * nb + i] * Y[(lo + c) * m + j];
+                Y[(lo + i) * m + j] = v / L[i * nb + i];
+            }
+        }
+    }
+    free(z);
+}
+
+static void bjac_free(bjac_t* M)
+{
+    free(M->L);
+    M->L = NULL;
+}
+
+/* y = M^-1 x for the preconditioner of a solve; identity when bs < 2 */
+void or_block_jacobi_apply(const or_matrix* A, int jacobi, int bs, int m, const double* X,
+                           double* Y, int* status)
+{
+    scaled_t S;
+    int rc = make_scaled(A, jacobi, &S);
+    bjac_t M;
+    memset(&M, 0, sizeof(M));
+    if (rc == OR_OK) rc = bjac_setup(&S.As, bs, &M);
+    if (rc == OR_OK) bjac_apply(&M, m, X, Y);
+    bjac_free(&M);
+    free_scaled(&S);
+    if (status) *status = rc;
+}
+
 static double true_rel_residual(const or_matrix* A, const double* b, const double* x, double bnorm)
 {
     int64_t n = A->n;
@@ -485,8 +620,13 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
     }
 
     scaled_t S;
+    bjac_t BJ;
+    memset(&BJ, 0, sizeof(BJ));
+    const int prec = p->bj_block >= 2;
     int rc = make_scaled(A, p->jacobi, &S);
+    if (rc == OR_OK && prec) rc = bjac_setup(&S.As, p->bj_block, &BJ);
     if (rc != OR_OK) {
+        bjac_free(&BJ);
         free_scaled(&S);
         inf.status = rc;
         if (info) *info = inf;
@@ -507,6 +647,8 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
     double* Q = (double*)xcalloc(blk, sizeof(double));
     double* V = (double*)xcalloc(blk, sizeof(double));
     double* Pn = (double*)xcalloc(blk, sizeof(double));
+    double* Yp = (double*)xcalloc(blk, sizeof(double)); /* M^-1 V (preconditioned) */
+    double* MW = (double*)xcalloc(blk, sizeof(double)); /* M^-1 W (preconditioned) */
     double* Sig = (double*)xcalloc((size_t)(s * s), sizeof(double));
     double* Sn = (double*)xcalloc((size_t)(s * s), sizeof(double));
     double* Z = (double*)xcalloc((size_t)(s * s), sizeof(double));
@@ -545,12 +687,19 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
     }
     if (!isfinite(gamma)) { rc = OR_ERR_NONFINITE; goto fallback_none; }
 
-    /* first Cholesky QR (W0, Sigma0) and P0 = W0 */
-    int m = or_cholqr_deflate(n, s, R, tau, W, Z, keep);
+    /* first Cholesky QR (W0, Sigma0) and P0 = W0 (preconditioned: the QR in
+     * the M^-1 inner product and P0 = M^-1 W0) */
+    int m;
+    if (prec) {
+        bjac_apply(&BJ, s, R, Yp);
+        m = or_cholqr_deflate_prec(n, s, R, Yp, tau, W, MW, Z, keep);
+    } else {
+        m = or_cholqr_deflate(n, s, R, tau, W, Z, keep);
+    }
     inf.deflations = s - m;
     memcpy(Sig, Z, sizeof(double) * (size_t)(m * s));
     for (int64_t r = 0; r < n; ++r)
-        for (int c = 0; c < m; ++c) P[r * m + c] = W[r * m + c];
+        for (int c = 0; c < m; ++c) P[r * m + c] = prec ? MW[r * m + c] : W[r * m + c];
     inf.seconds_setup = now_s() - t0;
 
     int64_t it = 0;
@@ -650,14 +799,21 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
                 for (int a = 0; a < m; ++a) acc += Q[r * m + a] * Xi[a * m + c];
                 V[r * m + c] = W[r * m + c] - acc;
             }
-        int mn = or_cholqr_deflate(n, m, V, tau, W, Z, keep);
+        int mn;
+        if (prec) {
+            bjac_apply(&BJ, m, V, Yp);
+            mn = or_cholqr_deflate_prec(n, m, V, Yp, tau, W, MW, Z, keep);
+        } else {
+            mn = or_cholqr_deflate(n, m, V, tau, W, Z, keep);
+        }
         inf.deflations += m - mn;
-        /* P = W + P Z^T, Sigma = Z Sigma */
+        /* P = W + P Z^T (preconditioned: M^-1 W + P Z^T), Sigma = Z Sigma */
+        const double* Wd = prec ? MW : W;
         for (int64_t r = 0; r < n; ++r)
             for (int c = 0; c < mn; ++c) {
                 double acc = 0.0;
                 for (int a = 0; a < m; ++a) acc += P[r * m + a] * Z[c * m + a];
-                Pn[r * mn + c] = W[r * mn + c] + acc;
+                Pn[r * mn + c] = Wd[r * mn + c] + acc;
             }
         memcpy(P, Pn, sizeof(double) * (size_t)(n * mn));
         for (int c = 0; c < mn; ++c)
@@ -721,7 +877,8 @@ fallback_none:
 done:
     free(keep); free(chat); free(nu); free(al); free(Xi); free(L); free(C); free(Z);
     free(Sn); free(Sig); free(Pn); free(V); free(Q); free(P); free(W); free(R);
-    free(Xt); free(X0); free(Y); free(U); free(bbar);
+    free(Xt); free(X0); free(Y); free(U); free(bbar); free(Yp); free(MW);
+    bjac_free(&BJ);
     free_scaled(&S);
     if (info) *info = inf;
     return rc;
@@ -732,7 +889,8 @@ done:
  * s = 1 special case of Alg. 1 reduces to it in exact arithmetic.
  * ------------------------------------------------------------------------- */
 int or_hs_cg(const or_matrix* A, const double* b, const double* x0, double tol,
-             int64_t max_iter, int jacobi, double* x, double* history, or_info* info)
+             int64_t max_iter, int jacobi, int bj_block, double* x, double* history,
+             or_info* info)
 {
     int64_t n = A->n;
     or_info inf;
@@ -745,16 +903,31 @@ int or_hs_cg(const or_matrix* A, const double* b, const double* x0, double tol,
         return OR_OK;
     }
     scaled_t S;
+    bjac_t BJ;
+    memset(&BJ, 0, sizeof(BJ));
+    const int prec = bj_block >= 2;
     int rc = make_scaled(A, jacobi, &S);
-    if (rc != OR_OK) { free_scaled(&S); inf.status = rc; if (info) *info = inf; return rc; }
+    if (rc == OR_OK && prec) rc = bjac_setup(&S.As, bj_block, &BJ);
+    if (rc != OR_OK) {
+        bjac_free(&BJ);
+        free_scaled(&S);
+        inf.status = rc;
+        if (info) *info = inf;
+        return rc;
+    }
     double* xs = (double*)xcalloc((size_t)n, sizeof(double));
     double* r = (double*)xcalloc((size_t)n, sizeof(double));
+    double* z = (double*)xcalloc((size_t)n, sizeof(double));
     double* pv = (double*)xcalloc((size_t)n, sizeof(double));
     double* q = (double*)xcalloc((size_t)n, sizeof(double));
     for (int64_t i = 0; i < n; ++i) xs[i] = x0 ? x0[i] * S.d[i] : 0.0;
     or_matmul_block(&S.As, 1, xs, q);
-    for (int64_t i = 0; i < n; ++i) { r[i] = b[i] / S.d[i] - q[i]; pv[i] = r[i]; }
-    double gam = dot_strided(n, r, 1, r, 1);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] / S.d[i] - q[i];
+    /* preconditioned residual z = M^-1 r (z = r without a preconditioner) */
+    if (prec) bjac_apply(&BJ, 1, r, z);
+    else memcpy(z, r, sizeof(double) * (size_t)n);
+    memcpy(pv, z, sizeof(double) * (size_t)n);
+    double gam = dot_strided(n, r, 1, z, 1);
     int64_t it;
     double rel = NAN;
     int conv = 0;
@@ -767,10 +940,12 @@ int or_hs_cg(const or_matrix* A, const double* b, const double* x0, double tol,
         rel = sqrt(e2) / bnorm;
         if (history) history[it - 1] = rel;
         if (rel < tol) { conv = 1; break; }
-        double gn = dot_strided(n, r, 1, r, 1);
+        if (prec) bjac_apply(&BJ, 1, r, z);
+        else memcpy(z, r, sizeof(double) * (size_t)n);
+        double gn = dot_strided(n, r, 1, z, 1);
         double beta = gn / gam;
         gam = gn;
-        for (int64_t i = 0; i < n; ++i) pv[i] = r[i] + beta * pv[i];
+        for (int64_t i = 0; i < n; ++i) pv[i] = z[i] + beta * pv[i];
     }
     inf.iterations = conv ? it : max_iter;
     inf.status = conv ? OR_OK : OR_NOT_CONVERGED;
@@ -779,7 +954,8 @@ int or_hs_cg(const or_matrix* A, const double* b, const double* x0, double tol,
     for (int64_t i = 0; i < n; ++i) x[i] = xs[i] / S.d[i];
     inf.seconds = now_s() - t0;
     inf.rel_res_true = true_rel_residual(A, b, x, bnorm);
-    free(q); free(pv); free(r); free(xs);
+    free(q); free(pv); free(z); free(r); free(xs);
+    bjac_free(&BJ);
     free_scaled(&S);
     if (info) *info = inf;
     return inf.status;
@@ -792,7 +968,8 @@ int or_hs_cg(const or_matrix* A, const double* b, const double* x0, double tol,
  * equals CG's p^T A p in exact arithmetic.
  * ------------------------------------------------------------------------- */
 int or_cg_cg(const or_matrix* A, const double* b, const double* x0, double tol,
-             int64_t max_iter, int jacobi, double* x, double* history, or_info* info)
+             int64_t max_iter, int jacobi, int bj_block, double* x, double* history,
+             or_info* info)
 {
     int64_t n = A->n;
     or_info inf;
@@ -805,26 +982,40 @@ int or_cg_cg(const or_matrix* A, const double* b, const double* x0, double tol,
         return OR_OK;
     }
     scaled_t S;
+    bjac_t BJ;
+    memset(&BJ, 0, sizeof(BJ));
+    const int prec = bj_block >= 2;
     int rc = make_scaled(A, jacobi, &S);
-    if (rc != OR_OK) { free_scaled(&S); inf.status = rc; if (info) *info = inf; return rc; }
+    if (rc == OR_OK && prec) rc = bjac_setup(&S.As, bj_block, &BJ);
+    if (rc != OR_OK) {
+        bjac_free(&BJ);
+        free_scaled(&S);
+        inf.status = rc;
+        if (info) *info = inf;
+        return rc;
+    }
     double* xs = (double*)xcalloc((size_t)n, sizeof(double));
     double* r = (double*)xcalloc((size_t)n, sizeof(double));
+    double* u = (double*)xcalloc((size_t)n, sizeof(double));
     double* w = (double*)xcalloc((size_t)n, sizeof(double));
     double* pv = (double*)xcalloc((size_t)n, sizeof(double));
     double* sv = (double*)xcalloc((size_t)n, sizeof(double));
     for (int64_t i = 0; i < n; ++i) xs[i] = x0 ? x0[i] * S.d[i] : 0.0;
     or_matmul_block(&S.As, 1, xs, w);
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] / S.d[i] - w[i];
-    or_matmul_block(&S.As, 1, r, w);
-    double gam = dot_strided(n, r, 1, r, 1);
-    double del = dot_strided(n, w, 1, r, 1);
+    /* u = M^-1 r (u = r without a preconditioner), w = A u */
+    if (prec) bjac_apply(&BJ, 1, r, u);
+    else memcpy(u, r, sizeof(double) * (size_t)n);
+    or_matmul_block(&S.As, 1, u, w);
+    double gam = dot_strided(n, r, 1, u, 1);
+    double del = dot_strided(n, w, 1, u, 1);
     double alpha = gam / del, beta = 0.0;
     int64_t it;
     double rel = NAN;
     int conv = 0;
     for (it = 1; it <= max_iter; ++it) {
         for (int64_t i = 0; i < n; ++i) {
-            pv[i] = r[i] + beta * pv[i];
+            pv[i] = u[i] + beta * pv[i];
             sv[i] = w[i] + beta * sv[i];
             xs[i] += alpha * pv[i];
             r[i] -= alpha * sv[i];
@@ -834,9 +1025,11 @@ int or_cg_cg(const or_matrix* A, const double* b, const double* x0, double tol,
         rel = sqrt(e2) / bnorm;
         if (history) history[it - 1] = rel;
         if (rel < tol) { conv = 1; break; }
-        or_matmul_block(&S.As, 1, r, w);
-        double gn = dot_strided(n, r, 1, r, 1);
-        del = dot_strided(n, w, 1, r, 1);
+        if (prec) bjac_apply(&BJ, 1, r, u);
+        else memcpy(u, r, sizeof(double) * (size_t)n);
+        or_matmul_block(&S.As, 1, u, w);
+        double gn = dot_strided(n, r, 1, u, 1);
+        del = dot_strided(n, w, 1, u, 1);
         beta = gn / gam;
         alpha = gn / (del - beta * gn / alpha);
         gam = gn;
@@ -848,7 +1041,8 @@ int or_cg_cg(const or_matrix* A, const double* b, const double* x0, double tol,
     for (int64_t i = 0; i < n; ++i) x[i] = xs[i] / S.d[i];
     inf.seconds = now_s() - t0;
     inf.rel_res_true = true_rel_residual(A, b, x, bnorm);
-    free(sv); free(pv); free(w); free(r); free(xs);
+    free(sv); free(pv); free(w); free(u); free(r); free(xs);
+    bjac_free(&BJ);
     free_scaled(&S);
     if (info) *info = inf;
     return inf.status;

@@ -55,6 +55,9 @@ typedef struct {
     int check_true;       /* 1: an accepted combination whose true residual is not below
                              tol gives way to the best column when that column's true
                              residual is lower (the fallback after Proposition 1) */
+    int bj_block;         /* >= 2: block-Jacobi preconditioner with blocks of bj_block
+                             consecutive rows of the (scaled) matrix, in the
+                             preconditioned Dubrulle-R form; < 2: none */
 } or_params;
 
 typedef struct {
@@ -95,6 +98,14 @@ void or_spd_inverse(int m, const double* L, double* Xi);
  * width m_out.  W and Z must hold n*m and m*m doubles. */
 int or_cholqr_deflate(int64_t n, int m, const double* V, double tau,
                       double* W, double* Z, int* keep);
+/* Cholesky QR in the M^-1 inner product: Gram V^T Y (Y = M^-1 V; entry
+ * (i > j) taken as V_i^T Y_j), W = V_J U_JJ^-1, MW = Y_J U_JJ^-1 */
+int or_cholqr_deflate_prec(int64_t n, int m, const double* V, const double* Y, double tau,
+                           double* W, double* MW, double* Z, int* keep);
+/* Y = M^-1 X (n x m) for the block-Jacobi preconditioner of block size bs on
+ * the matrix scaled as a solve with this jacobi flag would scale it */
+void or_block_jacobi_apply(const or_matrix* A, int jacobi, int bs, int m, const double* X,
+                           double* Y, int* status);
 /* min_c ||b - B c||_2 for B n x m (row-major) by Householder QR.
  * Writes c[m]; returns 0, or -1 when R has a zero diagonal. */
 int or_lstsq(int64_t n, int m, const double* B, const double* b, double* c);
@@ -105,10 +116,10 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
 /* textbook Hestenes-Stiefel CG on the scaled system from x0 (original space,
  * may be NULL for zero); stop test ||D r|| / ||b|| < tol */
 int or_hs_cg(const or_matrix* A, const double* b, const double* x0, double tol,
-             int64_t max_iter, int jacobi, double* x, double* history, or_info* info);
+             int64_t max_iter, int jacobi, int bj_block, double* x, double* history, or_info* info);
 /* Chronopoulos-Gear CG (x0 = 0 in the paper's baseline) */
 int or_cg_cg(const or_matrix* A, const double* b, const double* x0, double tol,
-             int64_t max_iter, int jacobi, double* x, double* history, or_info* info);
+             int64_t max_iter, int jacobi, int bj_block, double* x, double* history, or_info* info);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,7 @@ class OrParams(C.Structure):
                 ("max_iter", C.c_int64), ("jacobi", C.c_int), ("seed", C.c_uint64),
                 ("U", C.c_void_p), ("tau", C.c_double), ("ls_scaled", C.c_int),
                 ("history", C.c_void_p), ("X_out", C.c_void_p), ("R_out", C.c_void_p),
-                ("prop1_gap", C.c_void_p), ("check_true", C.c_int)]
+                ("prop1_gap", C.c_void_p), ("check_true", C.c_int), ("bj_block", C.c_int)]
 
 
 class OrInfo(C.Structure):
@@ -73,10 +73,12 @@ def lib():
         L.or_cholesky.argtypes = [C.c_int, vp, vp]
         L.or_spd_inverse.argtypes = [C.c_int, vp, vp]
         L.or_cholqr_deflate.argtypes = [i64, C.c_int, vp, dbl, vp, vp, vp]
+        L.or_cholqr_deflate_prec.argtypes = [i64, C.c_int, vp, vp, dbl, vp, vp, vp, vp]
+        L.or_block_jacobi_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
         L.or_lstsq.argtypes = [i64, C.c_int, vp, vp, vp]
         L.or_mbpcg_solve.argtypes = [vp, vp, vp, vp, vp]
-        L.or_hs_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, vp, vp, vp]
-        L.or_cg_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, vp, vp, vp]
+        L.or_hs_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, C.c_int, vp, vp, vp]
+        L.or_cg_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, C.c_int, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -163,6 +165,35 @@ def cholqr_deflate(V, tau=1e-12):
     return W[: n * k].reshape(n, k), Z[: k * m].reshape(k, m), keep.astype(bool)
 
 
+def cholqr_deflate_prec(V, Y, tau=1e-12):
+    """Cholesky QR in the M^-1 inner product (Y = M^-1 V): returns W, M^-1 W,
+    Z and the kept-column flags."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    n, m = V.shape
+    W = np.empty(n * m)
+    MW = np.empty(n * m)
+    Z = np.empty(m * m)
+    keep = np.zeros(m, dtype=np.int32)
+    k = lib().or_cholqr_deflate_prec(n, m, V.ctypes.data, Y.ctypes.data, tau, W.ctypes.data,
+                                     MW.ctypes.data, Z.ctypes.data, keep.ctypes.data)
+    return (W[: n * k].reshape(n, k), MW[: n * k].reshape(n, k), Z[: k * m].reshape(k, m),
+            keep.astype(bool))
+
+
+def block_jacobi_apply(A, X, bs, jacobi=True):
+    """M^-1 X for the block-Jacobi preconditioner (blocks of bs rows) of the
+    matrix as a solve scales it; returns (Y, status)."""
+    M = A if isinstance(A, Matrix) else Matrix(A)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    X2 = X.reshape(M.n, -1)
+    Y = np.zeros_like(X2)
+    st = C.c_int(0)
+    lib().or_block_jacobi_apply(C.byref(M.s), int(bool(jacobi)), int(bs), X2.shape[1],
+                                X2.ctypes.data, Y.ctypes.data, C.byref(st))
+    return Y.reshape(X.shape), st.value
+
+
 def lstsq(B, b):
     B = np.ascontiguousarray(B, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -176,11 +207,13 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -2: "NOT_SPD", -3: "BREAKDOWN", -4: "NONF
 
 def mbpcg_solve(A, b, s, tol=1e-8, tol_initial=0.0, max_iter=100000, jacobi=True, seed=0,
                 U=None, tau=1e-12, ls_scaled=False, want_history=False, want_X=False,
-                want_prop1=False, check_true=True):
+                want_prop1=False, check_true=True, block_jacobi=0):
     """Run Algorithm 1 on the CPU.  Returns (x, info dict, extras dict).
     check_true: an accepted least-squares combination whose true residual
     is not below tol gives way to the best column if that column's true
-    residual is lower (used_fallback = 1)."""
+    residual is lower (used_fallback = 1).  block_jacobi >= 2: the
+    preconditioned form with the block-Jacobi preconditioner of that block
+    size on the (scaled) matrix."""
     M = A if isinstance(A, Matrix) else Matrix(A)
     n = M.n
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -191,7 +224,8 @@ def mbpcg_solve(A, b, s, tol=1e-8, tol_initial=0.0, max_iter=100000, jacobi=True
     gap = np.full(max_iter, np.nan) if want_prop1 else None
     Uc = None if U is None else np.ascontiguousarray(U, dtype=np.float64)
     p = OrParams(s, tol, tol_initial, max_iter, int(bool(jacobi)), seed, _p(Uc), tau,
-                 int(bool(ls_scaled)), _p(hist), _p(Xo), _p(Ro), _p(gap), int(bool(check_true)))
+                 int(bool(ls_scaled)), _p(hist), _p(Xo), _p(Ro), _p(gap), int(bool(check_true)),
+                 int(block_jacobi))
     info = OrInfo()
     lib().or_mbpcg_solve(C.byref(M.s), b.ctypes.data, C.byref(p), x.ctypes.data, C.byref(info))
     d = info.as_dict()
@@ -207,25 +241,29 @@ def mbpcg_solve(A, b, s, tol=1e-8, tol_initial=0.0, max_iter=100000, jacobi=True
     return x, d, extra
 
 
-def _cg(fn, A, b, x0, tol, max_iter, jacobi, want_history):
+def _cg(fn, A, b, x0, tol, max_iter, jacobi, want_history, block_jacobi=0):
     M = A if isinstance(A, Matrix) else Matrix(A)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(M.n)
     hist = np.full(max_iter, np.nan) if want_history else None
     x0c = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     info = OrInfo()
-    fn(C.byref(M.s), b.ctypes.data, _p(x0c), tol, max_iter, int(bool(jacobi)), x.ctypes.data,
-       _p(hist), C.byref(info))
+    fn(C.byref(M.s), b.ctypes.data, _p(x0c), tol, max_iter, int(bool(jacobi)), int(block_jacobi),
+       x.ctypes.data, _p(hist), C.byref(info))
     d = info.as_dict()
     return x, d, (hist[: int(d["iterations"])] if want_history else None)
 
 
-def hs_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=False):
-    return _cg(lib().or_hs_cg, A, b, x0, tol, max_iter, jacobi, want_history)
+def hs_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=False,
+          block_jacobi=0):
+    """Textbook (preconditioned, when block_jacobi >= 2) CG."""
+    return _cg(lib().or_hs_cg, A, b, x0, tol, max_iter, jacobi, want_history, block_jacobi)
 
 
-def cg_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=False):
-    return _cg(lib().or_cg_cg, A, b, x0, tol, max_iter, jacobi, want_history)
+def cg_cg(A, b, x0=None, tol=1e-8, max_iter=100000, jacobi=True, want_history=False,
+          block_jacobi=0):
+    """Chronopoulos-Gear CG (preconditioned, when block_jacobi >= 2)."""
+    return _cg(lib().or_cg_cg, A, b, x0, tol, max_iter, jacobi, want_history, block_jacobi)
 
 
 def round_bf16(x: float) -> float:

@@ -193,6 +193,137 @@ def test_finite_termination_in_ceil_n_over_s_steps(n, s, cond):
     assert np.linalg.norm(x - xs) <= 1e-4 * np.linalg.norm(xs)
 
 
+# ------------------------------------------------------- block-Jacobi preconditioner
+def _scaled_dense(A, jacobi=True):
+    Ad = A.to_scipy().toarray() if hasattr(A, "to_scipy") else np.asarray(A, dtype=np.float64)
+    if not jacobi:
+        return Ad
+    d = np.sqrt(np.diag(Ad))
+    return Ad / d[:, None] / d[None, :]
+
+
+def _block_inverse_apply(As, X, bs):
+    """M^-1 X with numpy: each diagonal block of As solved by LAPACK."""
+    Y = np.empty_like(X)
+    n = As.shape[0]
+    for lo in range(0, n, bs):
+        hi = min(n, lo + bs)
+        Y[lo:hi] = np.linalg.solve(As[lo:hi, lo:hi], X[lo:hi])
+    return Y
+
+
+@pytest.mark.parametrize("bs", [2, 4, 8, 16])
+def test_block_jacobi_apply_matches_blockwise_solves(bs):
+    A = W.diffusion3d(7)                      # n = 343: a ragged last block for every bs
+    X = W.rng_for((60, bs)).standard_normal((A.n, 3))
+    Y, st = O.block_jacobi_apply(A, X, bs)
+    assert st == 0
+    Yr = _block_inverse_apply(_scaled_dense(A), X, bs)
+    assert np.linalg.norm(Y - Yr) <= 1e-13 * np.linalg.norm(Yr)
+    Ad = W.dense_spd(50, tag=(61, bs))         # dense storage, no scaling
+    Yd, st = O.block_jacobi_apply(Ad, X[:50], bs, jacobi=False)
+    assert st == 0
+    assert np.linalg.norm(Yd - _block_inverse_apply(Ad, X[:50], bs)) <= 1e-12 * np.linalg.norm(Yd)
+
+
+def test_block_jacobi_reports_an_indefinite_block():
+    Ad = np.eye(8)
+    Ad[0, 1] = Ad[1, 0] = 2.0                   # block [[1, 2], [2, 1]] is indefinite
+    _, st = O.block_jacobi_apply(Ad, np.ones((8, 1)), 4, jacobi=False)
+    assert st == O.OR_ERR_NOT_SPD
+
+
+def test_preconditioned_cholqr_is_orthonormal_in_the_inverse_inner_product():
+    A = W.diffusion3d(6)
+    V = W.rng_for((62,)).standard_normal((A.n, 5))
+    V[:, 4] = V[:, 0] - 2.0 * V[:, 2]           # a dependent column to drop
+    As = _scaled_dense(A)
+    Y = _block_inverse_apply(As, V, 8)
+    Wq, MW, Z, keep = O.cholqr_deflate_prec(V, Y)
+    assert keep.tolist() == [True, True, True, True, False]
+    assert np.allclose(Wq.T @ _block_inverse_apply(As, Wq, 8), np.eye(4), atol=1e-12)
+    assert np.linalg.norm(MW - _block_inverse_apply(As, Wq, 8)) <= 1e-12 * np.linalg.norm(MW)
+    assert np.linalg.norm(Wq @ Z - V) <= 1e-12 * np.linalg.norm(V)
+
+
+def _numpy_pcg(As, bbar, x0, bs, d, nb, tol=1e-8, maxit=2000):
+    """Textbook preconditioned CG (Hestenes-Stiefel) on the scaled system,
+    stop test on ||D r|| / ||b||."""
+    x = x0.copy()
+    r = bbar - As @ x
+    z = _block_inverse_apply(As, r[:, None], bs)[:, 0]
+    p = z.copy()
+    rz = r @ z
+    hist = []
+    for it in range(1, maxit + 1):
+        q = As @ p
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        hist.append(np.linalg.norm(d * r) / nb)
+        if hist[-1] < tol:
+            break
+        z = _block_inverse_apply(As, r[:, None], bs)[:, 0]
+        rz2 = r @ z
+        p = z + (rz2 / rz) * p
+        rz = rz2
+    return x, np.asarray(hist)
+
+
+def test_preconditioned_s1_equals_textbook_pcg_from_the_same_start():
+    A = W.poisson2d(24)
+    b = W.rhs(A.n, 63)
+    bs = 8
+    U = O.uniform_block(12, A.n, 1)
+    x, info, ex = O.mbpcg_solve(A, b, 1, U=U, block_jacobi=bs, want_history=True)
+    Ad = A.to_scipy().toarray()
+    d = np.sqrt(np.diag(Ad))
+    As = Ad / d[:, None] / d[None, :]
+    bbar = b / d
+    gamma = np.linalg.norm(bbar) / np.linalg.norm(As @ U[:, 0])
+    xr, hr = _numpy_pcg(As, bbar, gamma * U[:, 0], bs, d, np.linalg.norm(b))
+    assert info["iterations"] == len(hr)
+    k = min(60, len(hr))
+    assert np.max(np.abs(ex["history"][:k] - hr[:k]) / hr[:k]) < 1e-8
+    assert np.linalg.norm(x - xr / d) <= 1e-8 * np.linalg.norm(x)
+    # the oracle's own PCG baselines follow the same recurrence from x0 = 0
+    x0r, h0 = _numpy_pcg(As, bbar, np.zeros(A.n), bs, d, np.linalg.norm(b))
+    _, ih, hh = O.hs_cg(A, b, block_jacobi=bs, want_history=True)
+    _, ic, hc = O.cg_cg(A, b, block_jacobi=bs, want_history=True)
+    assert ih["iterations"] == len(h0)
+    assert np.max(np.abs(hh[:k] - h0[:k]) / h0[:k]) < 1e-8
+    assert abs(ic["iterations"] - len(h0)) <= 1
+    assert np.max(np.abs(np.log10(hc[:k]) - np.log10(h0[:k]))) < 0.01
+
+
+def test_whole_matrix_as_the_block_converges_in_one_step():
+    # one block covering all of A: M = A~, M^-1 A~ = I, one step suffices
+    A = W.tiny_spd(40, 1e4, tag=(64,))
+    b = W.rng_for((65,)).standard_normal(40)
+    for s in (1, 3):
+        x, info, _ = O.mbpcg_solve(A, b, s, jacobi=False, seed=4, block_jacobi=64)
+        assert info["status"] == 0 and info["iterations"] == 1, info
+        assert info["rel_res_true"] < 1e-10
+    for fn in (O.hs_cg, O.cg_cg):
+        _, ic, _ = fn(A, b, jacobi=False, block_jacobi=64)
+        assert ic["status"] == 0 and ic["iterations"] == 1
+
+
+@pytest.mark.parametrize("n,s,bs", [(12, 3, 4), (16, 4, 8), (10, 2, 4)])
+def test_preconditioned_finite_termination(n, s, bs):
+    A = W.tiny_spd(n, 1e3, tag=(66, n, s))
+    b = W.rng_for((67, n)).standard_normal(n)
+    k = math.ceil(n / s)
+    x, info, ex = O.mbpcg_solve(A, b, s, tol=1e-14, max_iter=k, jacobi=False, seed=6,
+                                block_jacobi=bs, want_history=True)
+    h = ex["history"]
+    assert len(h) == k and h[k - 1] < 1e-6
+    if k > 1:
+        assert h[k - 2] > 1e-4
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-4 * np.linalg.norm(xs)
+
+
 def test_non_dividing_width_deflates_exactly():
     n, s = 10, 3
     A = W.tiny_spd(n, 50.0, tag=(92,))
