@@ -140,6 +140,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--block-jacobi", default="8,16,32",
+                    help="sparse workloads: block sizes of the block-Jacobi leg (MBPCG at --s and "
+                         "preconditioned CG, graph mode), '' to skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB mbpcg_stream_copy (reference for byte counters)")
     args = ap.parse_args()
@@ -256,6 +259,36 @@ def bench_sparse(args):
                 "rel_res_true": inf["rel_res_true"],
             }
 
+    # block-Jacobi preconditioner (the preconditioned form of the method): the
+    # same solve and the preconditioned CG, graph mode, and one profiled solve
+    # for the per-iteration phases
+    bj = None
+    sizes = [int(v) for v in args.block_jacobi.split(",") if v.strip()]
+    if sizes:
+        bj = {}
+        for bs in sizes:
+            pre = dict(precond=M.PRECOND_BLOCK_JACOBI, block_size=bs)
+            run(solver.solve, s=s, seed=seed, **pre)
+            run(solver.cg_solve, **pre)
+            torch.cuda.synchronize()
+            q0 = time.perf_counter()
+            ib = run(solver.solve, s=s, seed=seed, **pre)
+            torch.cuda.synchronize()
+            q1 = time.perf_counter()
+            ic = run(solver.cg_solve, **pre)
+            torch.cuda.synchronize()
+            q2 = time.perf_counter()
+            ip = run(solver.solve, s=s, seed=seed, profile=1, **pre)
+            bj[str(bs)] = {
+                "seconds_graph_mode": round(q1 - q0, 6), "iterations": ib["iterations"],
+                "rel_res_true": ib["rel_res_true"],
+                "cg_seconds_graph_mode": round(q2 - q1, 6), "cg_iterations": ic["iterations"],
+                "cg_rel_res_true": ic["rel_res_true"],
+                "ms_per_iter_phases": dict(zip(["product", "xi", "update", "qr", "dir"],
+                                               [round(v / max(1, ip["iterations"]), 4)
+                                                for v in ip["ms_phase"][:5]])),
+            }
+
     copy_gbs = copy_bandwidth(M, torch, dev)
 
     cpu = None
@@ -310,6 +343,7 @@ def bench_sparse(args):
         },
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "block_jacobi": bj,
     }
     solver.close()
     print(json.dumps(out))

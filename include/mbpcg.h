@@ -46,7 +46,19 @@ typedef enum {
     MBPCG_ERR_UNSUPPORTED = -7   /* e.g. s > 32, or a mode the library lacks    */
 } mbpcg_status;
 
-typedef enum { MBPCG_PRECOND_NONE = 0, MBPCG_PRECOND_JACOBI = 1 } mbpcg_precond;
+/* NONE: A as given.  JACOBI: the symmetric diagonal scaling of Sec. 1.
+ * BLOCK_JACOBI: that scaling, then the block-Jacobi preconditioner M (the
+ * diagonal blocks of block_size consecutive rows of the scaled matrix, the
+ * last block shorter when block_size does not divide n) in the
+ * preconditioned form of the method that Sec. 2 says it admits: the residual
+ * basis is orthonormal in the M^-1 inner product (Cholesky QR of V^T M^-1 V)
+ * and the directions are built from M^-1 W.  FP64 single-system solves and
+ * the CG baseline only. */
+typedef enum {
+    MBPCG_PRECOND_NONE = 0,
+    MBPCG_PRECOND_JACOBI = 1,
+    MBPCG_PRECOND_BLOCK_JACOBI = 2
+} mbpcg_precond;
 
 /* Arithmetic of the block product A P.  FP64 everywhere is the paper's
  * (Sec. 3).  The two IR modes round a copy of dense A to FP32 or BF16, run the
@@ -62,7 +74,7 @@ typedef struct {
     double tol;             /* convergence tolerance on ||b - A x|| / ||b|| (Alg. 1)     */
     double tol_initial;     /* best-column tolerance; <= 0 means tol (the paper's setting) */
     int64_t max_iter;       /* iteration cap (inner cap in IR mode)                      */
-    mbpcg_precond precond;  /* NONE, or JACOBI: the symmetric diagonal scaling of Sec. 1 */
+    mbpcg_precond precond;  /* NONE, JACOBI (Sec. 1 scaling) or BLOCK_JACOBI (above)     */
     uint64_t seed;          /* SplitMix64 seed of the Uniform(-1,1) initial block         */
     const double* U;        /* optional n x s row-major initial block, same mem as b     */
     double tau;             /* deflation threshold of Cholesky QR; <= 0 means 1e-12      */
@@ -75,6 +87,7 @@ typedef struct {
     double* history;        /* optional host array [max_iter]: ||R_h|| / ||b|| per step  */
     int32_t poll_every;     /* iterations per graph launch between host checks; 0 = auto */
     int32_t profile;        /* 1: time each phase with HIP events (no graphs)            */
+    int32_t block_size;     /* BLOCK_JACOBI: rows per diagonal block, 4, 8, 16 or 32     */
 } mbpcg_params;
 
 typedef struct {

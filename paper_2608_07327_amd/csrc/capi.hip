@@ -48,6 +48,7 @@ void mbpcg_default_params(mbpcg_params* p) {
     p->history = nullptr;
     p->poll_every = 0;
     p->profile = 0;
+    p->block_size = 8;
 }
 
 const char* mbpcg_status_str(mbpcg_status st) {
@@ -163,7 +164,10 @@ static mbpcg_status check_params(mbpcg_ctx ctx, const double* b, double* x, mbpc
     if (mem != MBPCG_MEM_HOST && mem != MBPCG_MEM_DEVICE) return MBPCG_ERR_INVALID_ARG;
     if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return MBPCG_ERR_INVALID_ARG;
     if (p->max_iter < 1 || p->max_iter > (int64_t)INT32_MAX) return MBPCG_ERR_INVALID_ARG;
-    if (p->precond != MBPCG_PRECOND_NONE && p->precond != MBPCG_PRECOND_JACOBI)
+    if (p->precond != MBPCG_PRECOND_NONE && p->precond != MBPCG_PRECOND_JACOBI &&
+        p->precond != MBPCG_PRECOND_BLOCK_JACOBI)
+        return MBPCG_ERR_INVALID_ARG;
+    if (p->precond == MBPCG_PRECOND_BLOCK_JACOBI && !mb::bjac_supported(p->block_size))
         return MBPCG_ERR_INVALID_ARG;
     if (p->poll_every < 0 || p->poll_every > 4096) return MBPCG_ERR_INVALID_ARG;
     if (cg) return MBPCG_OK;
@@ -177,6 +181,7 @@ static mbpcg_status check_params(mbpcg_ctx ctx, const double* b, double* x, mbpc
         return MBPCG_ERR_INVALID_ARG;
     if (p->precision != MBPCG_FP64) {
         if (!ctx->c.dense) return MBPCG_ERR_UNSUPPORTED;
+        if (p->precond == MBPCG_PRECOND_BLOCK_JACOBI) return MBPCG_ERR_UNSUPPORTED;
         if (!(p->ir_tol > 0.0) || !(p->inner_tol > 0.0) || p->max_outer < 0)
             return MBPCG_ERR_INVALID_ARG;
     }
@@ -275,6 +280,7 @@ mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
     if (!(common->tol > 0.0) || !std::isfinite(common->tol) || common->max_iter < 1 ||
         common->max_iter > (int64_t)INT32_MAX)
         return MBPCG_ERR_INVALID_ARG;
+    if (common->precond == MBPCG_PRECOND_BLOCK_JACOBI) return MBPCG_ERR_UNSUPPORTED;
     for (int32_t i = 0; i < nsys; ++i) {
         const mbpcg_system& y = systems[i];
         if (y.n < 1 || y.n >= (int64_t)INT32_MAX || y.nnz < 0 || y.nnz >= (int64_t)INT32_MAX)

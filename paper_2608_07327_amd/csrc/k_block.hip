@@ -19,13 +19,30 @@ struct Tiles {
     static constexpr int T = stream_tile(S);   // 4 passes per tile
 };
 
+// Row rl of a tile of M^-1 X for the block-Jacobi preconditioner with blocks
+// of BS rows: the tile starts at a multiple of BS (T is one), so the block of
+// row r0 + rl is the tile rows (rl / BS) * BS ..; sX holds the tile of X
+// (zero beyond n), inv row r the matching row of the block's inverse.
+template <int S, int BS>
+__device__ __forceinline__ double bj_row(const double* __restrict__ inv, int64_t r,
+                                         const double* sX, int rl, int j) {
+    static_assert(BS > 0 && Tiles<S>::T % BS == 0, "tiles must hold whole blocks");
+    const double* iv = inv + r * BS;
+    const int b0 = (rl / BS) * BS;
+    double y = 0.0;
+#pragma unroll
+    for (int c = 0; c < BS; ++c) y += iv[c] * sX[(b0 + c) * S + j];
+    return y;
+}
+
 // ---------------------------------------------------------------------------
 // K_B: X~ += P alpha, R -= Q alpha, the column norms behind h, and
 // V = W - Q Xi with the Gram V^T V (first half of the Cholesky QR).
 //   X~ += P alpha,  R -= Q alpha,  V = W - Q Xi  (V overwrites W),
 //   partial lower triangle of V^T V and nu_j = sum_r (d_r R_rj)^2.
 // ---------------------------------------------------------------------------
-template <int S>
+// BS > 0 (preconditioned form): also Y = M^-1 V into Yp, and the Gram is V^T Y.
+template <int S, int BS>
 __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __restrict__ P,
                                                      const double* __restrict__ Q,
                                                      double* __restrict__ Xt,
@@ -33,13 +50,16 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
                                                      double* __restrict__ W,
                                                      const double* __restrict__ d,
                                                      double* __restrict__ part,
-                                                     const DevState* __restrict__ st) {
+                                                     const DevState* __restrict__ st,
+                                                     const double* __restrict__ inv,
+                                                     double* __restrict__ Yp) {
     if (st->done) return;
     constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
     constexpr int E = tri_count(S);
     __shared__ double sP[T * S];
     __shared__ double sQ[T * S];
     __shared__ double sV[T * S];
+    __shared__ double sY[BS > 0 ? T * S : 1];
     __shared__ double red[MB_BLOCK];
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
     double al[S], xi[S];
@@ -100,11 +120,23 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
             sV[rl * S + j] = v;
         }
         __syncthreads();
+        if constexpr (BS > 0) {
+            for (int rl = rl0; rl < T; rl += RPP) {
+                double y = 0.0;
+                if (rl < rows) {
+                    y = bj_row<S, BS>(inv, r0 + rl, sV, rl, j);
+                    Yp[(r0 + rl) * S + j] = y;
+                }
+                sY[rl * S + j] = y;
+            }
+            __syncthreads();
+        }
+        const double* sG = BS > 0 ? sY : sV;   // second Gram operand
         if constexpr (MF)
             gm.add_tile(rows, [&](int r, int c) { return sV[r * S + c]; },
-                        [&](int r, int c) { return sV[r * S + c]; });
+                        [&](int r, int c) { return sG[r * S + c]; });
         else
-            gs.add_rows(rows, [&](int k, int r) { return sV[r * S + gi[k]] * sV[r * S + gj[k]]; });
+            gs.add_rows(rows, [&](int k, int r) { return sV[r * S + gi[k]] * sG[r * S + gj[k]]; });
         __syncthreads();
     }
     double* out = part + (int64_t)blockIdx.x * (E + S);
@@ -126,15 +158,19 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
 // FIRST: the first direction block P0 = W0.  Optionally also writes P rounded to FP32 or BF16
 // for the low-precision dense product.
 // ---------------------------------------------------------------------------
-template <int S, int FIRST, int LO>
+// PREC (preconditioned form): P = Yp M + P Z^T with Yp = M^-1 V (W = V M as
+// before).
+template <int S, int FIRST, int LO, int PREC>
 __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __restrict__ W,
                                                         double* __restrict__ P,
                                                         void* __restrict__ Plo,
-                                                        const DevState* __restrict__ st) {
+                                                        const DevState* __restrict__ st,
+                                                        const double* __restrict__ Yp) {
     if (st->done) return;
     constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
     __shared__ double sV[T * S];
     __shared__ double sP[T * S];
+    __shared__ double sY[PREC ? T * S : 1];
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
     double m[S], z[S];
 #pragma unroll
@@ -151,6 +187,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
             const bool in = e < rows * S;
             sV[e] = in ? W[r0 * S + e] : 0.0;
             if (!FIRST) sP[e] = in ? P[r0 * S + e] : 0.0;
+            if (PREC) sY[e] = in ? Yp[r0 * S + e] : 0.0;
         }
         __syncthreads();
         for (int rl = rl0; rl < rows; rl += RPP) {
@@ -158,11 +195,17 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
 #pragma unroll
             for (int l = 0; l < S; ++l) w += sV[rl * S + l] * m[l];
             double p = w;
+            if (PREC) {
+                double yw = 0.0;
+#pragma unroll
+                for (int l = 0; l < S; ++l) yw += sY[rl * S + l] * m[l];
+                p = yw;
+            }
             if (!FIRST) {
                 double acc = 0.0;
 #pragma unroll
                 for (int l = 0; l < S; ++l) acc += sP[rl * S + l] * z[l];
-                p = w + acc;
+                p = p + acc;
             }
             const int64_t g = (r0 + rl) * S + j;
             W[g] = w;
@@ -279,13 +322,17 @@ __global__ void k_init(int64_t n, int s, const double* __restrict__ U, const dou
 }
 
 // partial lower triangle of X^T X and nu_j = sum_r (d_r X_rj)^2 (same layout as k_update)
-template <int S>
+// BS > 0 (preconditioned form): also Y = M^-1 X into Yp, and the Gram is X^T Y.
+template <int S, int BS>
 __global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* __restrict__ X,
                                                       const double* __restrict__ d,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part,
+                                                      const double* __restrict__ inv,
+                                                      double* __restrict__ Yp) {
     constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
     constexpr int E = tri_count(S);
     __shared__ double sX[T * S];
+    __shared__ double sY[BS > 0 ? T * S : 1];
     __shared__ double red[MB_BLOCK];
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
     constexpr bool MF = S >= 8;
@@ -314,11 +361,23 @@ __global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* _
             const double v = d[r0 + rl] * sX[rl * S + j];
             nu += v * v;
         }
+        if constexpr (BS > 0) {
+            for (int rl = rl0; rl < T; rl += RPP) {
+                double y = 0.0;
+                if (rl < rows) {
+                    y = bj_row<S, BS>(inv, r0 + rl, sX, rl, j);
+                    Yp[(r0 + rl) * S + j] = y;
+                }
+                sY[rl * S + j] = y;
+            }
+            __syncthreads();
+        }
+        const double* sG = BS > 0 ? sY : sX;
         if constexpr (MF)
             gm.add_tile(rows, [&](int r, int c) { return sX[r * S + c]; },
-                        [&](int r, int c) { return sX[r * S + c]; });
+                        [&](int r, int c) { return sG[r * S + c]; });
         else
-            gs.add_rows(rows, [&](int k, int r) { return sX[r * S + gi[k]] * sX[r * S + gj[k]]; });
+            gs.add_rows(rows, [&](int k, int r) { return sX[r * S + gi[k]] * sG[r * S + gj[k]]; });
         __syncthreads();
     }
     double* out = part + (int64_t)blockIdx.x * (E + S);
@@ -444,6 +503,10 @@ __global__ void k_cg_init(int64_t n, const double* __restrict__ bbar, double* __
     }
 }
 
+// Rows go in chunks of MB_BLOCK (one per workgroup and pass), so a chunk holds
+// whole preconditioner blocks.  BS > 0 (preconditioned form): p = u + beta p,
+// then u = M^-1 r from the new r (into u), partials (||D r||^2, r^T u).
+template <int BS>
 __global__ __launch_bounds__(MB_BLOCK) void k_cg_update(int64_t n, double* __restrict__ p,
                                                         double* __restrict__ sv,
                                                         double* __restrict__ x,
@@ -451,23 +514,47 @@ __global__ __launch_bounds__(MB_BLOCK) void k_cg_update(int64_t n, double* __res
                                                         const double* __restrict__ w,
                                                         const double* __restrict__ d,
                                                         double* __restrict__ part,
-                                                        const DevState* __restrict__ st) {
+                                                        const DevState* __restrict__ st,
+                                                        const double* __restrict__ inv,
+                                                        double* __restrict__ u) {
+    static_assert(MB_BLOCK % (BS > 0 ? BS : 1) == 0, "chunks must hold whole blocks");
     if (st->done) return;
     __shared__ double red[2 * MB_BLOCK];
+    __shared__ double sR[BS > 0 ? MB_BLOCK : 1];
+    const int t = threadIdx.x;
     const double alpha = st->cg_alpha, beta = st->cg_beta;
     double e2 = 0.0, g2 = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)MB_BLOCK + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * MB_BLOCK) {
-        const double pn = r[i] + beta * p[i];
-        const double sn = w[i] + beta * sv[i];
-        x[i] = x[i] + alpha * pn;
-        const double rn = r[i] - alpha * sn;
-        p[i] = pn;
-        sv[i] = sn;
-        r[i] = rn;
-        const double dr = d[i] * rn;
-        e2 += dr * dr;
-        g2 += rn * rn;
+    for (int64_t base = blockIdx.x * (int64_t)MB_BLOCK; base < n;
+         base += (int64_t)gridDim.x * MB_BLOCK) {
+        const int64_t i = base + t;
+        const bool in = i < n;
+        double rn = 0.0;
+        if (in) {
+            const double pn = (BS > 0 ? u[i] : r[i]) + beta * p[i];
+            const double sn = w[i] + beta * sv[i];
+            x[i] = x[i] + alpha * pn;
+            rn = r[i] - alpha * sn;
+            p[i] = pn;
+            sv[i] = sn;
+            r[i] = rn;
+            const double dr = d[i] * rn;
+            e2 += dr * dr;
+            if (BS == 0) g2 += rn * rn;
+        }
+        if constexpr (BS > 0) {
+            sR[t] = rn;
+            __syncthreads();
+            if (in) {
+                const double* iv = inv + i * BS;
+                const int b0 = (t / BS) * BS;
+                double un = 0.0;
+#pragma unroll
+                for (int c = 0; c < BS; ++c) un += iv[c] * sR[b0 + c];
+                u[i] = un;
+                g2 += rn * un;
+            }
+            __syncthreads();
+        }
     }
     red[threadIdx.x] = e2;
     red[MB_BLOCK + threadIdx.x] = g2;
@@ -476,6 +563,47 @@ __global__ __launch_bounds__(MB_BLOCK) void k_cg_update(int64_t n, double* __res
         double s = 0.0;
         for (int k = 0; k < MB_BLOCK; ++k) s += red[threadIdx.x * MB_BLOCK + k];
         part[blockIdx.x * 2 + threadIdx.x] = s;
+    }
+}
+
+// u = M^-1 r and partials (||D r||^2, r^T u): the start of the preconditioned CG
+template <int BS>
+__global__ __launch_bounds__(MB_BLOCK) void k_cg_prec(int64_t n, const double* __restrict__ r,
+                                                      const double* __restrict__ d,
+                                                      double* __restrict__ part,
+                                                      const double* __restrict__ inv,
+                                                      double* __restrict__ u) {
+    __shared__ double red[2 * MB_BLOCK];
+    __shared__ double sR[MB_BLOCK];
+    const int t = threadIdx.x;
+    double e2 = 0.0, g2 = 0.0;
+    for (int64_t base = blockIdx.x * (int64_t)MB_BLOCK; base < n;
+         base += (int64_t)gridDim.x * MB_BLOCK) {
+        const int64_t i = base + t;
+        const bool in = i < n;
+        const double ri = in ? r[i] : 0.0;
+        sR[t] = ri;
+        __syncthreads();
+        if (in) {
+            const double* iv = inv + i * BS;
+            const int b0 = (t / BS) * BS;
+            double un = 0.0;
+#pragma unroll
+            for (int c = 0; c < BS; ++c) un += iv[c] * sR[b0 + c];
+            u[i] = un;
+            const double dr = d[i] * ri;
+            e2 += dr * dr;
+            g2 += ri * un;
+        }
+        __syncthreads();
+    }
+    red[t] = e2;
+    red[MB_BLOCK + t] = g2;
+    __syncthreads();
+    if (t < 2) {
+        double s = 0.0;
+        for (int k = 0; k < MB_BLOCK; ++k) s += red[t * MB_BLOCK + k];
+        part[blockIdx.x * 2 + t] = s;
     }
 }
 
@@ -545,46 +673,65 @@ static inline int grid_for(int64_t work, int cap) {
     }                                   \
     return hipErrorInvalidValue;
 
-hipError_t launch_update(int S, int nwg, int64_t n, const double* P, const double* Q, double* Xt,
-                         double* R, double* W, const double* d, double* part, const DevState* st,
-                         hipStream_t stream) {
-    MB_DISPATCH_S(S, {
-        hipLaunchKernelGGL(k_update<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n, P, Q, Xt, R, W,
-                           d, part, st);
+// block size of the preconditioner (0: none) as a compile-time BB
+#define MB_DISPATCH_BS(BS, CALL)                \
+    switch (BS) {                               \
+        case 0: { constexpr int BB = 0; CALL; }  \
+        case 4: { constexpr int BB = 4; CALL; }  \
+        case 8: { constexpr int BB = 8; CALL; }  \
+        case 16: { constexpr int BB = 16; CALL; } \
+        case 32: { constexpr int BB = 32; CALL; } \
+    }                                           \
+    return hipErrorInvalidValue;
+
+template <int S>
+static hipError_t update_s(int nwg, int64_t n, const double* P, const double* Q, double* Xt,
+                           double* R, double* W, const double* d, double* part,
+                           const DevState* st, hipStream_t stream, const BjArgs& bj) {
+    MB_DISPATCH_BS(bj.bs, {
+        hipLaunchKernelGGL((k_update<S, BB>), dim3(nwg), dim3(MB_BLOCK), 0, stream, n, P, Q, Xt, R,
+                           W, d, part, st, bj.inv, bj.Y);
         return hipGetLastError();
     })
 }
 
-template <int S>
-static hipError_t dirupdate_s(int nwg, int64_t n, double* W, double* P, void* Plo, DenseKind lo,
-                              int first, const DevState* st, hipStream_t stream) {
-    if (first) {
-        if (lo == DENSE_F32)
-            hipLaunchKernelGGL((k_dirupdate<S, 1, DENSE_F32>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
-                               n, W, P, Plo, st);
-        else if (lo == DENSE_BF16)
-            hipLaunchKernelGGL((k_dirupdate<S, 1, DENSE_BF16>), dim3(nwg), dim3(MB_BLOCK), 0,
-                               stream, n, W, P, Plo, st);
-        else
-            hipLaunchKernelGGL((k_dirupdate<S, 1, DENSE_F64>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
-                               n, W, P, Plo, st);
+hipError_t launch_update(int S, int nwg, int64_t n, const double* P, const double* Q, double* Xt,
+                         double* R, double* W, const double* d, double* part, const DevState* st,
+                         hipStream_t stream, const BjArgs& bj) {
+    MB_DISPATCH_S(S, return update_s<SS>(nwg, n, P, Q, Xt, R, W, d, part, st, stream, bj))
+}
+
+template <int S, int FIRST>
+static hipError_t dirupdate_sf(int nwg, int64_t n, double* W, double* P, void* Plo, DenseKind lo,
+                               const DevState* st, hipStream_t stream, const double* Yp) {
+    if (Yp) {
+        if (lo != DENSE_F64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_F64, 1>), dim3(nwg), dim3(MB_BLOCK), 0,
+                           stream, n, W, P, Plo, st, Yp);
+    } else if (lo == DENSE_F32) {
+        hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_F32, 0>), dim3(nwg), dim3(MB_BLOCK), 0,
+                           stream, n, W, P, Plo, st, Yp);
+    } else if (lo == DENSE_BF16) {
+        hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_BF16, 0>), dim3(nwg), dim3(MB_BLOCK), 0,
+                           stream, n, W, P, Plo, st, Yp);
     } else {
-        if (lo == DENSE_F32)
-            hipLaunchKernelGGL((k_dirupdate<S, 0, DENSE_F32>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
-                               n, W, P, Plo, st);
-        else if (lo == DENSE_BF16)
-            hipLaunchKernelGGL((k_dirupdate<S, 0, DENSE_BF16>), dim3(nwg), dim3(MB_BLOCK), 0,
-                               stream, n, W, P, Plo, st);
-        else
-            hipLaunchKernelGGL((k_dirupdate<S, 0, DENSE_F64>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
-                               n, W, P, Plo, st);
+        hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_F64, 0>), dim3(nwg), dim3(MB_BLOCK), 0,
+                           stream, n, W, P, Plo, st, Yp);
     }
     return hipGetLastError();
 }
 
+template <int S>
+static hipError_t dirupdate_s(int nwg, int64_t n, double* W, double* P, void* Plo, DenseKind lo,
+                              int first, const DevState* st, hipStream_t stream, const double* Yp) {
+    return first ? dirupdate_sf<S, 1>(nwg, n, W, P, Plo, lo, st, stream, Yp)
+                 : dirupdate_sf<S, 0>(nwg, n, W, P, Plo, lo, st, stream, Yp);
+}
+
 hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, void* Plo,
-                            DenseKind lo_kind, int first, const DevState* st, hipStream_t stream) {
-    MB_DISPATCH_S(S, return dirupdate_s<SS>(nwg, n, W, P, Plo, lo_kind, first, st, stream))
+                            DenseKind lo_kind, int first, const DevState* st, hipStream_t stream,
+                            const double* Yp) {
+    MB_DISPATCH_S(S, return dirupdate_s<SS>(nwg, n, W, P, Plo, lo_kind, first, st, stream, Yp))
 }
 
 hipError_t launch_rhs(int nwg, int64_t n, const double* b, const double* d, double* bbar,
@@ -627,12 +774,19 @@ hipError_t launch_init(int S, int64_t n, int s, const double* U, const double* Y
     })
 }
 
-hipError_t launch_gram_nu(int S, int nwg, int64_t n, const double* X, const double* d, double* part,
-                          hipStream_t stream) {
-    MB_DISPATCH_S(S, {
-        hipLaunchKernelGGL(k_gram_nu<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n, X, d, part);
+template <int S>
+static hipError_t gram_nu_s(int nwg, int64_t n, const double* X, const double* d, double* part,
+                            hipStream_t stream, const BjArgs& bj) {
+    MB_DISPATCH_BS(bj.bs, {
+        hipLaunchKernelGGL((k_gram_nu<S, BB>), dim3(nwg), dim3(MB_BLOCK), 0, stream, n, X, d, part,
+                           bj.inv, bj.Y);
         return hipGetLastError();
     })
+}
+
+hipError_t launch_gram_nu(int S, int nwg, int64_t n, const double* X, const double* d, double* part,
+                          hipStream_t stream, const BjArgs& bj) {
+    MB_DISPATCH_S(S, return gram_nu_s<SS>(nwg, n, X, d, part, stream, bj))
 }
 
 hipError_t launch_ls_gram(int S, int nwg, int64_t n, const double* b, const double* R,
@@ -672,10 +826,22 @@ hipError_t launch_cg_init(int64_t n, const double* bbar, double* x, double* r, d
 
 hipError_t launch_cg_update(int nwg, int64_t n, double* p, double* sv, double* x, double* r,
                             const double* w, const double* d, double* part, const DevState* st,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(nwg), dim3(MB_BLOCK), 0, s, n, p, sv, x, r, w, d, part,
-                       st);
-    return hipGetLastError();
+                            hipStream_t s, const BjArgs& bj) {
+    MB_DISPATCH_BS(bj.bs, {
+        hipLaunchKernelGGL(k_cg_update<BB>, dim3(nwg), dim3(MB_BLOCK), 0, s, n, p, sv, x, r, w, d,
+                           part, st, bj.inv, bj.Y);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_cg_prec(int nwg, int64_t n, const double* r, const double* d, double* part,
+                          const BjArgs& bj, hipStream_t s) {
+    if (bj.bs == 0) return hipErrorInvalidValue;
+    MB_DISPATCH_BS(bj.bs, {
+        hipLaunchKernelGGL(k_cg_prec<(BB > 0 ? BB : 4)>, dim3(nwg), dim3(MB_BLOCK), 0, s, n, r, d,
+                           part, bj.inv, bj.Y);
+        return hipGetLastError();
+    })
 }
 
 hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* x, hipStream_t s) {

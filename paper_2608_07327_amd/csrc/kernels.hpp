@@ -77,12 +77,33 @@ hipError_t launch_cast_dense(DenseKind kind, int64_t n, const double* A, int64_t
 hipError_t launch_dense_resid_reduce(int64_t n, int ksplit, const double* qpart, const double* b,
                                      double* r_out, double* part, int nwg, hipStream_t stream);
 
+// ---- block-Jacobi preconditioner (the preconditioned form of Sec. 2)
+// M = diagonal blocks of bs consecutive rows of the scaled matrix; inv holds
+// M^-1 row by row: inv[r * bs + c] = (block inverse)[r - lo][c], lo = r / bs * bs,
+// zero for columns beyond n.  bs = 0 means no preconditioner.
+inline bool bjac_supported(int bs) { return bs == 4 || bs == 8 || bs == 16 || bs == 32; }
+struct BjArgs {
+    int bs = 0;               // 0: none
+    const double* inv = nullptr;
+    double* Y = nullptr;      // n x S output M^-1 V (or M^-1 r for CG)
+};
+// inv from the CSR (A.vals = scaled values) or dense column-major matrix;
+// a block that is not SPD sets st->done = DONE_NOTSPD
+hipError_t launch_bjac_setup_csr(int bs, const CsrDev& A, double* inv, DevState* st,
+                                 hipStream_t s);
+hipError_t launch_bjac_setup_dense(int bs, int64_t n, const double* A, int64_t lda, double* inv,
+                                   DevState* st, hipStream_t s);
+
 // ---- fused updates of one iteration
+// With bj.bs: also Y = M^-1 V into bj.Y and the Gram V^T Y (entry (i >= j) =
+// V_i^T Y_j) instead of V^T V.
 hipError_t launch_update(int S, int nwg, int64_t n, const double* P, const double* Q, double* Xt,
                          double* R, double* W, const double* d, double* part, const DevState* st,
-                         hipStream_t stream);
+                         hipStream_t stream, const BjArgs& bj = BjArgs());
+// With Yp (the preconditioned path, FP64 only): W = V M and P = Yp M + P Z^T.
 hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, void* Plo,
-                            DenseKind lo_kind, int first, const DevState* st, hipStream_t stream);
+                            DenseKind lo_kind, int first, const DevState* st, hipStream_t stream,
+                            const double* Yp = nullptr);
 
 // ---- setup
 hipError_t launch_diag_csr(const CsrDev& A, int jacobi, double* d, DevState* st, hipStream_t s);
@@ -100,7 +121,7 @@ hipError_t launch_init(int S, int64_t n, int s, const double* U, const double* Y
                        const double* bbar, double* X0, double* Xt, double* R, const DevState* st,
                        hipStream_t stream);
 hipError_t launch_gram_nu(int S, int nwg, int64_t n, const double* X, const double* d, double* part,
-                          hipStream_t stream);
+                          hipStream_t stream, const BjArgs& bj = BjArgs());
 
 // ---- termination
 hipError_t launch_ls_gram(int S, int nwg, int64_t n, const double* b, const double* R,
@@ -116,9 +137,14 @@ hipError_t launch_resid_csr(int nwg, const CsrDev& A, const double* b, const dou
 // ---- Chronopoulos-Gear CG
 hipError_t launch_cg_init(int64_t n, const double* bbar, double* x, double* r, double* p,
                           double* sv, hipStream_t s);
+// With bj.bs: p = u + beta p with u = M^-1 r (bj.Y), then the new u from the new
+// r; partials (||D r||^2, r^T u) instead of (||D r||^2, r^T r)
 hipError_t launch_cg_update(int nwg, int64_t n, double* p, double* sv, double* x, double* r,
                             const double* w, const double* d, double* part, const DevState* st,
-                            hipStream_t s);
+                            hipStream_t s, const BjArgs& bj = BjArgs());
+// u = M^-1 r into bj.Y and partials (||D r||^2, r^T u) (the preconditioned CG start)
+hipError_t launch_cg_prec(int nwg, int64_t n, const double* r, const double* d, double* part,
+                          const BjArgs& bj, hipStream_t s);
 hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* x, hipStream_t s);
 
 // ---- tails (one workgroup): reductions of partials + s x s FP64 work

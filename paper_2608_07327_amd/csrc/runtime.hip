@@ -47,7 +47,7 @@ Ctx::~Ctx() {
     if (As && As != A) dfree(As);
     As = nullptr;
     dfree(A); dfree(Alo);
-    dfree(d); dfree(bbar); dfree(bdev); dfree(xdev); dfree(rvec); dfree(xacc);
+    dfree(d); dfree(bbar); dfree(bdev); dfree(xdev); dfree(rvec); dfree(xacc); dfree(bjinv);
     dfree(U); dfree(Y); dfree(X0); dfree(Xt); dfree(R); dfree(W); dfree(P); dfree(Q); dfree(Plo);
     dfree(qpart); dfree(part_a); dfree(part_b); dfree(part_r); dfree(part_c); dfree(st); dfree(hist);
     if (pinned) (void)hipHostFree(pinned);
@@ -139,6 +139,7 @@ static mbpcg_status ensure_hist(Ctx& c, int64_t cap) {
 // ---------------------------------------------------------------------------
 struct Plan {
     int s = 1, S = 1;
+    int bs = 0;            // block-Jacobi block size (0: none)
     DenseKind kind = DENSE_F64;
     SpmmShape sp;          // sparse block-product tile shape
     int nwg_prod = 1;    // partials of the block product's Gram
@@ -228,6 +229,33 @@ static hipError_t staged_partials(Ctx& c, int nwg, int E, const double* part,
     return launch_part_reduce(nwg, E, part, c.part_r, PART_REDUCE_G, c.st, c.stream);
 }
 
+// block-Jacobi arguments of a plan: inverse rows in bjinv, M^-1 blocks in Y
+static BjArgs bj_of(const Ctx& c, const Plan& pl) {
+    BjArgs a;
+    if (pl.bs) {
+        a.bs = pl.bs;
+        a.inv = c.bjinv;
+        a.Y = c.Y;
+    }
+    return a;
+}
+
+// The block-Jacobi inverse of the scaled matrix (after setup_scaling).
+static mbpcg_status setup_bjac(Ctx& c, const Plan& pl) {
+    if (!pl.bs) return MBPCG_OK;
+    if (!c.bjinv || c.bjinv_bs < pl.bs) {
+        dfree(c.bjinv);
+        c.bjinv = nullptr;
+        c.bjinv_bs = 0;
+        DALLOC(c.bjinv, sizeof(double) * (size_t)c.n * pl.bs);
+        c.bjinv_bs = pl.bs;
+        drop_graphs(c);
+    }
+    if (!c.dense) CK(launch_bjac_setup_csr(pl.bs, csr_of(c, true), c.bjinv, c.st, c.stream));
+    else CK(launch_bjac_setup_dense(pl.bs, c.n, c.As, c.n, c.bjinv, c.st, c.stream));
+    return MBPCG_OK;
+}
+
 // One iteration of Alg. 1's loop, from Xi to the new Sigma.  With ev (six
 // events) the phase boundaries are recorded: ev[0] before the product, ev[1]
 // after it, ev[2] after the Xi tail, ev[3] after the update, ev[4] after the
@@ -246,7 +274,7 @@ static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist,
     if ((e = launch_tail_xi(pl.S, pn, pr, c.st, c.stream)) != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
     if ((e = launch_update(pl.S, pl.nwg_upd, c.n, c.P, c.Q, c.Xt, c.R, c.W, c.d, c.part_b, c.st,
-                           c.stream)) != hipSuccess)
+                           c.stream, bj_of(c, pl))) != hipSuccess)
         return e;
     if ((e = mark(3)) != hipSuccess) return e;
     if ((e = staged_partials(c, pl.nwg_upd, tri_count(pl.S) + pl.S, c.part_b, &pr, &pn)) !=
@@ -255,7 +283,7 @@ static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist,
     if ((e = launch_tail_qr(pl.S, pn, pr, c.st, hist, 0, c.stream)) != hipSuccess) return e;
     if ((e = mark(4)) != hipSuccess) return e;
     if ((e = launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st,
-                              c.stream)) != hipSuccess)
+                              c.stream, pl.bs ? c.Y : nullptr)) != hipSuccess)
         return e;
     return mark(5);
 }
@@ -268,10 +296,11 @@ static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist,
     auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], c.stream) : hipSuccess; };
     if ((e = mark(0)) != hipSuccess) return e;
     if ((e = launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c, c.st,
-                              c.stream)) != hipSuccess)
+                              c.stream, bj_of(c, pl))) != hipSuccess)
         return e;
     if ((e = mark(1)) != hipSuccess) return e;
-    if ((e = launch_product(c, pl, c.R, c.Q, c.part_a, c.st)) != hipSuccess) return e;
+    // the product of the (preconditioned) residual: u = M^-1 r lives in Y
+    if ((e = launch_product(c, pl, pl.bs ? c.Y : c.R, c.Q, c.part_a, c.st)) != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
     if ((e = launch_tail_cg(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, hist, c.stream)) !=
         hipSuccess)
@@ -282,7 +311,7 @@ static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist,
 }
 
 static mbpcg_status get_graph(Ctx& c, const Plan& pl, int m, int cg, hipGraphExec_t* out) {
-    auto key = std::make_tuple(cg * 2 + c.dense, pl.S, m,
+    auto key = std::make_tuple((cg * 2 + c.dense) * 64 + pl.bs, pl.S, m,
                                pl.sp.T * 10000 + pl.sp.SL * 1000 + pl.sp.V * 100 + pl.sp.U * 10 + pl.sp.W,
                                pl.nwg_spmm, (int)pl.kind);
     auto it = c.graphs.find(key);
@@ -463,10 +492,11 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
                               mbpcg_info& info) {
     const int s = p.s;
     Plan pl = make_plan(c, s, kind);
+    pl.bs = p.precond == MBPCG_PRECOND_BLOCK_JACOBI ? p.block_size : 0;
     const int S = pl.S;
     CKS(ensure_blocks(c, S));
     CKS(ensure_hist(c, p.history ? p.max_iter : 1));
-    const int jac = p.precond == MBPCG_PRECOND_JACOBI;
+    const int jac = p.precond != MBPCG_PRECOND_NONE;
     const double tol0 = p.tol_initial > 0 ? p.tol_initial : p.tol;
     const double tau = p.tau > 0 ? p.tau : 1e-12;
     const double t0 = now_ms();
@@ -475,6 +505,7 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     CK(launch_state_init(c.st, s, (int)std::min<int64_t>(p.max_iter, INT32_MAX), p.tol, tol0, tau,
                          p.history ? (int)std::min<int64_t>(p.max_iter, INT32_MAX) : 0, c.stream));
     CKS(setup_scaling(c, pl, b, jac));
+    CKS(setup_bjac(c, pl));
     // random block U
     if (Udev) CK(launch_pad_block(S, c.n, s, Udev, c.U, c.stream));
     else CK(launch_uniform(S, c.n, s, p.seed, c.U, c.stream));
@@ -485,11 +516,13 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     CK(launch_tail_gamma(pl.nwg_e, c.part_c, pl.nwg_e, c.part_a, c.st, c.stream));
     // scaled right-hand sides, R0, first Cholesky QR, P0
     CK(launch_init(S, c.n, s, c.U, c.Y, c.bbar, c.X0, c.Xt, c.R, c.st, c.stream));
-    CK(launch_gram_nu(S, pl.nwg_upd, c.n, c.R, c.d, c.part_b, c.stream));
+    // (preconditioned: Y = M^-1 R0, Gram R0^T Y, P0 = M^-1 W0 = Y M)
+    CK(launch_gram_nu(S, pl.nwg_upd, c.n, c.R, c.d, c.part_b, c.stream, bj_of(c, pl)));
     CK(launch_tail_qr(S, pl.nwg_upd, c.part_b, c.st, nullptr, 1, c.stream));
     CK(hipMemcpyAsync(c.W, c.R, sizeof(double) * (size_t)c.n * S, hipMemcpyDeviceToDevice,
                       c.stream));
-    CK(launch_dirupdate(S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, kind, 1, c.st, c.stream));
+    CK(launch_dirupdate(S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, kind, 1, c.st, c.stream,
+                        pl.bs ? c.Y : nullptr));
     const double t_setup = now_ms();
 
     double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
@@ -567,16 +600,24 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
 static mbpcg_status run_cg(Ctx& c, const double* b, double* x, const mbpcg_params& p,
                            mbpcg_info& info) {
     Plan pl = make_plan(c, 1, DENSE_F64);
+    pl.bs = p.precond == MBPCG_PRECOND_BLOCK_JACOBI ? p.block_size : 0;
     CKS(ensure_blocks(c, 1));
     CKS(ensure_hist(c, p.history ? p.max_iter : 1));
-    const int jac = p.precond == MBPCG_PRECOND_JACOBI;
+    const int jac = p.precond != MBPCG_PRECOND_NONE;
     const double t0 = now_ms();
     memset(c.st_host, 0, sizeof(DevState));
     CK(launch_state_init(c.st, 1, (int)std::min<int64_t>(p.max_iter, INT32_MAX), p.tol, p.tol, 1e-12,
                          p.history ? (int)std::min<int64_t>(p.max_iter, INT32_MAX) : 0, c.stream));
     CKS(setup_scaling(c, pl, b, jac));
+    CKS(setup_bjac(c, pl));
     CK(launch_cg_init(c.n, c.bbar, c.Xt, c.R, c.P, c.W, c.stream));
-    CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
+    if (pl.bs) {
+        // u = M^-1 r0 and (||b||^2, r0^T u) in place of the right-hand side sums
+        CK(launch_cg_prec(pl.nwg_e, c.n, c.R, c.d, c.part_c, bj_of(c, pl), c.stream));
+        CK(launch_product(c, pl, c.Y, c.Q, c.part_a, c.st));
+    } else {
+        CK(launch_product(c, pl, c.R, c.Q, c.part_a, c.st));
+    }
     CK(launch_tail_cg0(pl.nwg_e, c.part_c, pl.nwg_prod, c.part_a, c.st, c.stream));
     double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
     for (double& v : c.phase_ms) v = 0.0;

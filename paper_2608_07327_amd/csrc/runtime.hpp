@@ -51,6 +51,8 @@ struct Ctx {
     double* xdev = nullptr;
     double* rvec = nullptr;     // IR residual
     double* xacc = nullptr;     // IR accumulated solution
+    double* bjinv = nullptr;    // block-Jacobi inverse rows, n x bjinv_bs
+    int bjinv_bs = 0;
 
     // blocks, capacity Scap columns
     int Scap = 0;

@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mbpcg.h")
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID_ARG, ERR_NOT_SPD, ERR_BREAKDOWN, ERR_NONFINITE = -1, -2, -3, -4
 ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = -5, -6, -7
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 0, 1, 2
 FP64, FP32_IR, BF16_IR = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 
@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("max_iter", C.c_int64), ("precond", C.c_int), ("seed", C.c_uint64),
                 ("U", C.c_void_p), ("tau", C.c_double), ("precision", C.c_int),
                 ("ir_tol", C.c_double), ("inner_tol", C.c_double), ("max_outer", C.c_int32),
-                ("history", C.c_void_p), ("poll_every", C.c_int32), ("profile", C.c_int32)]
+                ("history", C.c_void_p), ("poll_every", C.c_int32), ("profile", C.c_int32),
+                ("block_size", C.c_int32)]
 
 
 class Info(C.Structure):

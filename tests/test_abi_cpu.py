@@ -32,6 +32,7 @@ def test_default_params():
     p = M.default_params()
     assert p.s == 4 and p.tol == 1e-8 and p.max_iter == 100000
     assert p.precond == M.PRECOND_JACOBI and p.tau == 1e-12 and p.precision == M.FP64
+    assert p.block_size == 8
 
 
 def test_status_strings():
@@ -95,6 +96,10 @@ def test_batch_validation():
     sysv[0].s = 0
     assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_INVALID_ARG
     assert L.mbpcg_solve_batch(0, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_INVALID_ARG
+    # the batched kernel has no block-Jacobi path (checked before any HIP call)
+    sysv[0].s = 1
+    p.precond = M.PRECOND_BLOCK_JACOBI
+    assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_UNSUPPORTED
 
 
 def test_stream_copy_rejects_null():

@@ -50,7 +50,8 @@ def oracle_band(A, b, s, **kw):
     return xs, i_s, xp, i_p
 
 
-def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_iter=100000):
+def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_iter=100000,
+                         block_jacobi=0):
     """Parity contract (FP64):
       * status equal;
       * iteration count within max(|it_seq - it_pairwise| + [deciding
@@ -63,15 +64,20 @@ def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_ite
         orderings took the same number of steps), and used_fallback /
         final_width equal wherever the two oracle orderings agree on them;
       * converged solves: true residual < 2 tol."""
-    say("mbpcg", getattr(A, "n", None) or A.shape[0], "s", s, "seed", seed)
-    kw = dict(tol=tol, jacobi=jacobi, seed=seed, U=U, max_iter=max_iter)
+    say("mbpcg", getattr(A, "n", None) or A.shape[0], "s", s, "seed", seed, "bj", block_jacobi)
+    kw = dict(tol=tol, jacobi=jacobi, seed=seed, U=U, max_iter=max_iter,
+              block_jacobi=block_jacobi)
     xo, io, xp, ip = oracle_band(A, b, s, **kw)
     same = io["iterations"] == ip["iterations"]
     f = rel(xp, xo) if same else np.inf
     solver = M.Solver.from_matrix(A)
     Ud = None if U is None else dev(U)
-    x, info = solver.solve(dev(b), s=s, tol=tol, seed=seed, U=Ud, max_iter=max_iter,
-                           precond=M.PRECOND_JACOBI if jacobi else M.PRECOND_NONE)
+    if block_jacobi:
+        assert jacobi
+        pre = dict(precond=M.PRECOND_BLOCK_JACOBI, block_size=block_jacobi)
+    else:
+        pre = dict(precond=M.PRECOND_JACOBI if jacobi else M.PRECOND_NONE)
+    x, info = solver.solve(dev(b), s=s, tol=tol, seed=seed, U=Ud, max_iter=max_iter, **pre)
     x = x.cpu().numpy()
     near = abs(io["rel_res_best"] - tol) <= 0.01 * tol
     band = max(abs(io["iterations"] - ip["iterations"]) + (1 if near else 0),
@@ -278,6 +284,74 @@ def test_ill_conditioned_dense_meets_tol_on_the_true_residual(s):
     assert info["status"] == 0 and info["used_fallback"] == 1, info
     t = np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b)
     assert t < 1e-8 and abs(info["rel_res_true"] - t) <= 1e-3 * t, (t, info["rel_res_true"])
+
+
+# ------------------------------------------------------- block-Jacobi preconditioner
+@pytest.mark.parametrize("s,bs", [(1, 8), (2, 4), (4, 8), (4, 32), (8, 16), (16, 8), (32, 4),
+                                  (3, 16)])
+def test_block_jacobi_against_oracle(s, bs):
+    # 21^3 = 9261 rows: a ragged last block for every block size, several tiles
+    A = W.diffusion3d(21)
+    b = W.rhs(A.n, 71)
+    _, info, _, io = check_against_oracle(A, b, s, seed=W.uniform_block_seed(71, s),
+                                          block_jacobi=bs)
+    assert info["status"] == 0
+
+
+@pytest.mark.parametrize("s,bs", [(4, 8), (16, 32)])
+def test_block_jacobi_dense_against_oracle(s, bs):
+    A = W.dense_spd(600, tag=(3, 41))          # 600 rows: 600 % 32 = 24, ragged
+    b = W.rng_for((3, 42)).standard_normal(600)
+    check_against_oracle(A, b, s, seed=W.uniform_block_seed(72, s), block_jacobi=bs)
+
+
+@pytest.mark.parametrize("bs", [4, 16])
+def test_block_jacobi_cg_baseline_against_oracle(bs):
+    A = W.diffusion3d(21)
+    b = W.rhs(A.n, 73)
+    say("pcg", A.n, bs)
+    xo, io, _ = O.cg_cg(A, b, block_jacobi=bs)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.cg_solve(dev(b), precond=M.PRECOND_BLOCK_JACOBI, block_size=bs)
+    solver.close()
+    assert info["status"] == io["status"] == 0
+    assert abs(info["iterations"] - io["iterations"]) <= max(1, int(np.ceil(0.01 * io["iterations"])))
+    assert info["rel_res_true"] < 2e-8
+    if info["iterations"] == io["iterations"]:
+        assert rel(x.cpu().numpy(), xo) <= 1e-9
+
+
+def test_block_jacobi_lowers_the_iteration_count():
+    A = W.diffusion3d(21)
+    b = W.rhs(A.n, 74)
+    solver = M.Solver.from_matrix(A)
+    _, i1 = solver.solve(dev(b), s=4, seed=5)
+    _, i2 = solver.solve(dev(b), s=4, seed=5, precond=M.PRECOND_BLOCK_JACOBI, block_size=16)
+    solver.close()
+    assert i2["status"] == 0 and i2["iterations"] < i1["iterations"]
+
+
+def test_block_jacobi_reports_an_indefinite_block_and_rejects_bad_sizes():
+    # positive diagonal (the scaling succeeds) but the first 4 x 4 block is
+    # indefinite: the setup reports NOT_SPD, as the oracle does
+    A = np.eye(64)
+    A[0, 1] = A[1, 0] = 2.0
+    b = np.ones(64)
+    _, io, _ = O.mbpcg_solve(A, b, 2, block_jacobi=4)
+    assert io["status"] == O.OR_ERR_NOT_SPD
+    say("indefinite block")
+    solver = M.Solver.from_matrix(A)
+    _, info = solver.solve(dev(b), s=2, precond=M.PRECOND_BLOCK_JACOBI, block_size=4)
+    assert info["status"] == M.ERR_NOT_SPD
+    _, info = solver.cg_solve(dev(b), precond=M.PRECOND_BLOCK_JACOBI, block_size=4)
+    assert info["status"] == M.ERR_NOT_SPD
+    for bad in (0, 2, 3, 64):
+        with pytest.raises(M.MbpcgError):
+            solver.solve(dev(b), s=2, precond=M.PRECOND_BLOCK_JACOBI, block_size=bad)
+    with pytest.raises(M.MbpcgError):
+        solver.solve(dev(b), s=2, precond=M.PRECOND_BLOCK_JACOBI, block_size=8,
+                     precision=M.FP32_IR)
+    solver.close()
 
 
 def test_explicit_block_with_duplicate_columns_deflates():
