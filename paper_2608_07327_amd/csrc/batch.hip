@@ -24,6 +24,7 @@ constexpr int BT = 128;        // rows per item
 constexpr int PSTRIDE = 48;    // doubles of partial sums per item
 constexpr int BATCH_TERM_BARRIERS = 9;  // grid barriers of the termination
 constexpr int BSM = 4096;    // LDS doubles of the persistent kernel (32 KB)
+static_assert(SxsWs<8>::DOUBLES <= BSM, "s x s workspace of the widest batched system");
 
 struct BSys {
     int64_t n, rp_off, nz_off, vec_off, blk_off;

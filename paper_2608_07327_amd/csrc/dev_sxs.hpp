@@ -140,9 +140,14 @@ __device__ int cholqr_factor(const double* G, double tau, double* U, int* keep, 
     return *cnt;
 }
 
+// threads of the one-workgroup tail kernels: enough that each entry of an
+// s = 32 Gram (528 entries) is summed by one thread in one pass
+constexpr int TAIL_THREADS = 1024;
+
+// reduction workspace: max(E, threads of any caller)
 template <int E>
 struct RedWs {
-    static constexpr int N = E > MB_BLOCK ? E : MB_BLOCK;
+    static constexpr int N = E > TAIL_THREADS ? E : TAIL_THREADS;
 };
 
 // doubles / ints of LDS workspace each body needs
@@ -180,27 +185,77 @@ __device__ void tail_xi_body(const double* __restrict__ part, int nwg, int strid
         C[e] = v;
     }
     __syncthreads();
-    if (chol_lower<S>(C, L, smi)) {
-        if (t == 0) st->done = DONE_NOTSPD;
+    if (S >= 16 && (int)blockDim.x >= S * S) {   // uniform across the workgroup
+        // Wide blocks: Gauss-Jordan elimination without pivoting, one thread
+        // per entry, in place.  On an SPD matrix its pivots are those of the
+        // Cholesky factorisation (squared diagonal of L), so a pivot that is
+        // not positive and finite means C is not SPD, as there.  S steps of
+        // two barriers replace the sequential Cholesky, triangular inverse
+        // and L^-T L^-1 of the narrow path; the result is symmetrised.
+        const int i = t / S, j = t % S;
+        const bool mine = t < S * S;
+        bool bad = false;
+        for (int k = 0; k < S; ++k) {
+            double p = C[k * S + k];
+            const double aik = mine ? C[i * S + k] : 0.0;
+            const double akj = mine ? C[k * S + j] : 0.0;
+            __syncthreads();
+            if (!(p > 0.0) || !finite_d(p)) {
+                bad = true;
+                p = 1.0;
+            }
+            const double rp = 1.0 / p;
+            if (mine) {
+                double v;
+                if (i == k && j == k) v = rp;
+                else if (i == k) v = akj * rp;
+                else if (j == k) v = -aik * rp;
+                else v = C[t] - aik * (akj * rp);
+                C[t] = v;
+            }
+            __syncthreads();
+        }
+        if (bad) {
+            if (t == 0) st->done = DONE_NOTSPD;
+            return;
+        }
+        if (mine) {
+            Xi[t] = 0.5 * (C[i * S + j] + C[j * S + i]);
+            L[t] = st->Sigma[i * MB_SM + j];   // Sigma staged in LDS
+        }
+        __syncthreads();
+        if (mine) {
+            double v = 0.0;
+#pragma unroll 8
+            for (int l = 0; l < S; ++l) v += Xi[i * S + l] * L[l * S + j];
+            st->alpha[i * MB_SM + j] = v;
+            st->Xi[i * MB_SM + j] = Xi[t];
+        }
+        (void)Li;
         return;
-    }
-    // L^-1, one column per lane
-    lower_inverse<S>(L, Li);
-    // Xi = L^-T L^-1
-    for (int e = t; e < S * S; e += blockDim.x) {
-        const int i = e / S, j = e % S;
-        const int k0 = i > j ? i : j;
-        double v = 0.0;
-        for (int k = k0; k < S; ++k) v += Li[k * S + i] * Li[k * S + j];
-        Xi[e] = v;
-    }
-    __syncthreads();
-    for (int e = t; e < S * S; e += blockDim.x) {
-        const int i = e / S, j = e % S;
-        double v = 0.0;
-        for (int l = 0; l < S; ++l) v += Xi[i * S + l] * st->Sigma[l * MB_SM + j];
-        st->alpha[i * MB_SM + j] = v;
-        st->Xi[i * MB_SM + j] = Xi[e];
+    } else {
+        if (chol_lower<S>(C, L, smi)) {
+            if (t == 0) st->done = DONE_NOTSPD;
+            return;
+        }
+        // L^-1, one column per lane
+        lower_inverse<S>(L, Li);
+        // Xi = L^-T L^-1
+        for (int e = t; e < S * S; e += blockDim.x) {
+            const int i = e / S, j = e % S;
+            const int k0 = i > j ? i : j;
+            double v = 0.0;
+            for (int k = k0; k < S; ++k) v += Li[k * S + i] * Li[k * S + j];
+            Xi[e] = v;
+        }
+        __syncthreads();
+        for (int e = t; e < S * S; e += blockDim.x) {
+            const int i = e / S, j = e % S;
+            double v = 0.0;
+            for (int l = 0; l < S; ++l) v += Xi[i * S + l] * st->Sigma[l * MB_SM + j];
+            st->alpha[i * MB_SM + j] = v;
+            st->Xi[i * MB_SM + j] = Xi[e];
+        }
     }
 }
 
@@ -229,14 +284,14 @@ __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride
     int* stop = smi + S + 1;
     const int t = threadIdx.x;
     reduce_partials(part, nwg, ET, stride, red, tmp);
+    if (t < st->s) st->nu[t] = sqrt(red[E + t]) / st->bnorm;
     if (t == 0) {
         // best column in the original residual norm (Sec. 1: R = D R~)
         const int s = st->s;
         int h = 0;
         double best = red[E];
-        for (int j = 0; j < s; ++j) {
-            st->nu[j] = sqrt(red[E + j]) / st->bnorm;
-            if (j > 0 && red[E + j] < best) {
+        for (int j = 1; j < s; ++j) {
+            if (red[E + j] < best) {
                 best = red[E + j];
                 h = j;
             }
@@ -268,6 +323,10 @@ __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride
     }
     __syncthreads();
     const int k = cholqr_factor<S>(G, st->tau, U, keep, Z, M, cnt);
+    // Sigma staged in LDS (G is free once the factor is done)
+    if (!setup)
+        for (int e = t; e < S * S; e += blockDim.x) G[e] = st->Sigma[(e / S) * MB_SM + e % S];
+    __syncthreads();
     for (int e = t; e < S * S; e += blockDim.x) {
         const int i = e / S, j = e % S;
         double v;
@@ -275,7 +334,7 @@ __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride
             v = Z[e];
         } else {
             v = 0.0;
-            for (int l = 0; l < S; ++l) v += Z[i * S + l] * st->Sigma[l * MB_SM + j];
+            for (int l = 0; l < S; ++l) v += Z[i * S + l] * G[l * S + j];
         }
         Sg[e] = v;
     }

@@ -255,7 +255,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit
                                                            double* __restrict__ part,
                                                            const DevState* __restrict__ st) {
     if (st && st->done) return;
-    constexpr int T = 64 > S ? 64 : S;
+    constexpr int T = dense_reduce_rows(S);
     constexpr int E = tri_count(S);
     constexpr bool MF = S >= 8;
     __shared__ double sP[T * S], sQ[T * S], red[MB_BLOCK];
@@ -283,7 +283,15 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit
             double q = 0.0, p = 0.0;
             if (e < rows * S) {
                 const int64_t g = r0 * S + e;
-                for (int k = 0; k < ksplit; ++k) q += qpart[k * nS + g];
+                // four loads in flight, combined in a fixed order
+                double q4[4] = {0.0, 0.0, 0.0, 0.0};
+                int k = 0;
+                for (; k + 4 <= ksplit; k += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) q4[u] += qpart[(k + u) * nS + g];
+                }
+                for (int u = 0; k < ksplit; ++k, ++u) q4[u] += qpart[k * nS + g];
+                q = (q4[0] + q4[1]) + (q4[2] + q4[3]);
                 p = P[g];
                 Q[g] = q;
             }

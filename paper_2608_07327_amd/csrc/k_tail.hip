@@ -7,8 +7,6 @@
 
 namespace mb {
 
-#define TAIL_THREADS 256
-
 // First stage of a two-stage fixed-order sum of per-workgroup partials:
 // workgroup g adds partials [g c, (g + 1) c) of every entry (c = ceil(nwg / G))
 // and writes out[g * E + e].  The one-workgroup tails then add G partials

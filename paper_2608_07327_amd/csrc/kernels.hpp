@@ -28,6 +28,8 @@ inline int part_entries_ls(int S) { return tri_count(S + 1); }
 
 // tile rows of the streaming n x S kernels: 4 rows per thread
 __host__ __device__ constexpr int stream_tile(int S) { return 1024 / S; }
+// rows per tile of the dense reduce/Gram kernel (more workgroups for wide blocks)
+__host__ __device__ constexpr int dense_reduce_rows(int S) { return S >= 16 ? 32 : 64; }
 
 // ---- block product Q = A P (+ lower triangle of P^T Q per workgroup).
 // Shape: T rows per tile, SL slots per row, V adjacent columns per lane, U

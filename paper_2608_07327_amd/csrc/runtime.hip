@@ -179,7 +179,8 @@ static Plan make_plan(Ctx& c, int s, DenseKind kind) {
     pl.nwg_e = round_grid((c.n + MB_BLOCK - 1) / MB_BLOCK, 1024);
     if (c.dense) {
         pl.ksplit = dense_ksplit(c.n);
-        pl.nwg_dred = round_grid((c.n + 63) / 64, cap);
+        const int Tr = dense_reduce_rows(S);
+        pl.nwg_dred = round_grid((c.n + Tr - 1) / Tr, cap);
         pl.nwg_prod = pl.nwg_dred;
     } else {
         pl.nwg_prod = pl.nwg_spmm;
