@@ -260,8 +260,10 @@ __device__ __forceinline__ double sum_strided(const double* __restrict__ part, i
 }
 
 // Sum part[w * stride + e] over w = 0..nwg-1 in a fixed order into out[e]
-// (LDS), using all threads of the block.  tmp must hold max(blockDim, E)
-// doubles.  Ends with a barrier.
+// (LDS), using all threads of the block: tpe = floor_pow2(blockDim / E)
+// threads per entry each add a contiguous range of partials, then a pairwise
+// tree over those tpe sums.  tmp must hold max(blockDim, E) doubles.  Ends
+// with a barrier.
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nwg, int E,
                                                 int stride, double* out, double* tmp) {
     const int B = blockDim.x, t = threadIdx.x;
@@ -270,7 +272,8 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
         __syncthreads();
         return;
     }
-    const int tpe = B / E;
+    int tpe = 1;
+    while (tpe * 2 * E <= B) tpe *= 2;
     const int e = t % E, q = t / E;
     if (q < tpe) {
         const int chunk = (nwg + tpe - 1) / tpe;
@@ -278,11 +281,11 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
         tmp[q * E + e] = sum_strided(part, w0, w1, stride, e);
     }
     __syncthreads();
-    if (t < E) {
-        double s = 0.0;
-        for (int q2 = 0; q2 < tpe; ++q2) s += tmp[q2 * E + t];
-        out[t] = s;
+    for (int h = tpe / 2; h >= 1; h /= 2) {
+        if (q < h) tmp[q * E + e] += tmp[(q + h) * E + e];
+        __syncthreads();
     }
+    if (t < E) out[t] = tmp[t];
     __syncthreads();
 }
 

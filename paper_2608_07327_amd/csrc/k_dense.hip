@@ -3,8 +3,9 @@
 //
 // A workgroup of four wavefronts owns 256 rows and one of KSPLIT column
 // ranges; wavefront w owns rows [64w, 64w + 64) as four 16-row MFMA tiles, and
-// every S/16 output column tile reuses each loaded A operand.  P is staged
-// through LDS in chunks of KB rows and shared by the four wavefronts.  The
+// every S/16 output column tile reuses each loaded A operand.  The FP64
+// kernel reads P directly (the block is a few MB and stays in the L2) and
+// issues the loads of the next k-steps ahead of the MFMAs.  The
 // KSPLIT partial products are written to a scratch block and added in a fixed
 // order by k_dense_reduce, which also forms the Gram P^T Q of the tail.
 //
@@ -43,48 +44,63 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double*
                                                         const DevState* __restrict__ st) {
     if (st && st->done) return;
     constexpr int CT = S >= 16 ? S / 16 : 1;  // output column tiles
-    constexpr int KB = 32;                    // k rows of P per LDS chunk
-    __shared__ double sB[KB * 16 * CT];
+    constexpr int QS = 4;                     // MFMA k-steps (of 4) per trip
     const int rb = blockIdx.x / ksplit, ks = blockIdx.x % ksplit;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t kchunk = (n + ksplit - 1) / ksplit;
     const int64_t kbeg = ks * kchunk, kend = min(n, kbeg + kchunk);
     const int64_t rbase = (int64_t)rb * DENSE_ROWS + wave * 64;
     const int li = l & 15, lk = l >> 4;
+    int64_t row[4];
+    bool rok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        row[t] = rbase + 16 * t + li;
+        rok[t] = row[t] < n;
+    }
     d4 acc[4][CT];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
-
-    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
-        // A operands of this chunk: tile t, step q -> A[rbase + 16t + li][k0 + 4q + lk]
-        double a[KB / 4][4];
+    // operands of QS k-steps from k0: lane (li, lk) holds A[row t][k0 + 4q + lk]
+    // and P[k0 + 4q + lk][16c + li] (P is a few MB and stays in the L2)
+    auto load = [&](int64_t k0, double (&a)[QS][4], double (&b)[QS][CT]) {
 #pragma unroll
-        for (int q = 0; q < KB / 4; ++q) {
+        for (int q = 0; q < QS; ++q) {
             const int64_t k = k0 + 4 * q + lk;
+            const bool kin = k < kend;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t r = rbase + 16 * t + li;
-                a[q][t] = (k < kend && r < n) ? A[k * lda + r] : 0.0;
-            }
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < KB * 16 * CT; e += MB_BLOCK) {
-            const int kk = e / (16 * CT), j = e % (16 * CT);
-            const int64_t k = k0 + kk;
-            sB[e] = (k < kend && j < S) ? P[k * S + j] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < KB / 4; ++q) {
+            for (int t = 0; t < 4; ++t) a[q][t] = (kin && rok[t]) ? A[k * lda + row[t]] : 0.0;
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
-                const double bv = sB[(4 * q + lk) * (16 * CT) + 16 * c + li];
+                const int j = 16 * c + li;
+                b[q][c] = (kin && j < S) ? P[k * S + j] : 0.0;
+            }
+        }
+    };
+    auto mma = [&](const double (&a)[QS][4], const double (&b)[QS][CT]) {
+#pragma unroll
+        for (int q = 0; q < QS; ++q)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][t], bv, acc[t][c], 0, 0, 0);
-            }
+                    acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][t], b[q][c], acc[t][c], 0,
+                                                                    0, 0);
+    };
+    // no LDS and no barriers: the loads of the next trip are issued before
+    // the MFMAs of this one, and the other wavefronts of the CU overlap theirs
+    double a0[QS][4], b0[QS][CT], a1[QS][4], b1[QS][CT];
+    int64_t k0 = kbeg;
+    if (k0 < kend) load(k0, a0, b0);
+    for (; k0 < kend; k0 += 8 * QS) {
+        const int64_t k1 = k0 + 4 * QS;
+        if (k1 < kend) load(k1, a1, b1);
+        mma(a0, b0);
+        if (k1 < kend) {
+            if (k1 + 4 * QS < kend) load(k1 + 4 * QS, a0, b0);
+            mma(a1, b1);
         }
     }
     // D layout of v_mfma_f64_16x16x4f64: lane l, element v -> row l/16 + 4v, column l % 16
