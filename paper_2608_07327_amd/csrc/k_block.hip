@@ -19,6 +19,14 @@ struct Tiles {
     static constexpr int T = stream_tile(S);   // 4 passes per tile
 };
 
+// For S <= 16 the direction kernel stores only P, and the update kernel forms
+// W = V_prev M_prev from the previous V (kept in the W buffer) and the
+// previous M: one n x S block less written per iteration.  At S = 32 the
+// extra column of M does not fit the update kernel's registers, and the
+// direction kernel stores W as before.
+template <int S>
+constexpr bool lazy_w() { return S <= 16; }
+
 // Row rl of a tile of M^-1 X for the block-Jacobi preconditioner with blocks
 // of BS rows: the tile starts at a multiple of BS (T is one), so the block of
 // row r0 + rl is the tile rows (rl / BS) * BS ..; sX holds the tile of X
@@ -40,6 +48,8 @@ __device__ __forceinline__ double bj_row(const double* __restrict__ inv, int64_t
 // V = W - Q Xi with the Gram V^T V (first half of the Cholesky QR).
 //   X~ += P alpha,  R -= Q alpha,  V = W - Q Xi  (V overwrites W),
 //   partial lower triangle of V^T V and nu_j = sum_r (d_r R_rj)^2.
+// With lazy_w, W = V_prev M_prev is formed here from the W buffer (which
+// holds the previous V) and the previous Cholesky-QR M.
 // ---------------------------------------------------------------------------
 // BS > 0 (preconditioned form): also Y = M^-1 V into Yp, and the Gram is V^T Y.
 template <int S, int BS>
@@ -56,17 +66,20 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
     if (st->done) return;
     constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
     constexpr int E = tri_count(S);
+    constexpr bool LW = lazy_w<S>();
     __shared__ double sP[T * S];
     __shared__ double sQ[T * S];
     __shared__ double sV[T * S];
     __shared__ double sY[BS > 0 ? T * S : 1];
+    __shared__ double sW[LW ? T * S : 1];
     __shared__ double red[MB_BLOCK];
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
-    double al[S], xi[S];
+    double al[S], xi[S], mp[LW ? S : 1];
 #pragma unroll
     for (int l = 0; l < S; ++l) {
         al[l] = st->alpha[l * MB_SM + j];
         xi[l] = st->Xi[l * MB_SM + j];
+        if constexpr (LW) mp[l] = st->M[l * MB_SM + j];   // M of the previous Cholesky QR
     }
     constexpr bool MF = S >= 8;   // V^T V on the matrix cores
     TileSums<E> gs;
@@ -94,6 +107,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
             const bool in = e < rows * S;
             sP[e] = in ? Pt[e] : 0.0;
             sQ[e] = in ? Qt[e] : 0.0;
+            if constexpr (LW) sW[e] = in ? W[r0 * S + e] : 0.0;   // the previous V
         }
         __syncthreads();
         for (int rl = rl0; rl < T; rl += RPP) {
@@ -110,7 +124,15 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
                 }
                 const double xn = stream_load(Xt + g) + tx;
                 const double rn = stream_load(R + g) - trr;
-                v = W[g] - tv;
+                double w;
+                if constexpr (LW) {
+                    w = 0.0;
+#pragma unroll
+                    for (int l = 0; l < S; ++l) w += sW[rl * S + l] * mp[l];
+                } else {
+                    w = W[g];
+                }
+                v = w - tv;
                 stream_store(Xt + g, xn);
                 stream_store(R + g, rn);
                 W[g] = v;
@@ -155,11 +177,12 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
 // ---------------------------------------------------------------------------
 // K_C: W = V M (second half of the Cholesky QR) and P = W + P Z^T.
 //   W = V M  (M = inverse of the kept Cholesky factor),  P = W + P Z^T.
+// W is stored only where the update kernel does not form it itself (S = 32,
+// lazy_w); otherwise the W buffer keeps V for the next update.
 // FIRST: the first direction block P0 = W0.  Optionally also writes P rounded to FP32 or BF16
 // for the low-precision dense product.
+// PREC (preconditioned form): P = Yp M + P Z^T with Yp = M^-1 V.
 // ---------------------------------------------------------------------------
-// PREC (preconditioned form): P = Yp M + P Z^T with Yp = M^-1 V (W = V M as
-// before).
 template <int S, int FIRST, int LO, int PREC>
 __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __restrict__ W,
                                                         double* __restrict__ P,
@@ -208,7 +231,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
                 p = p + acc;
             }
             const int64_t g = (r0 + rl) * S + j;
-            W[g] = w;
+            if (!lazy_w<S>()) W[g] = w;
             P[g] = p;
             if (LO == DENSE_F32) static_cast<float*>(Plo)[lo_pindex(LO, r0 + rl, j, S)] = (float)p;
             if (LO == DENSE_BF16)
