@@ -14,6 +14,10 @@
 #define MB_SM 32
 #define MB_BLOCK 256
 
+// threads of the one-workgroup tail kernels: enough that each entry of an
+// s = 32 Gram (528 entries) is summed by one thread in one pass
+constexpr int TAIL_THREADS = 1024;
+
 namespace mb {
 
 enum DoneCode : int32_t {

@@ -140,10 +140,6 @@ __device__ int cholqr_factor(const double* G, double tau, double* U, int* keep, 
     return *cnt;
 }
 
-// threads of the one-workgroup tail kernels: enough that each entry of an
-// s = 32 Gram (528 entries) is summed by one thread in one pass
-constexpr int TAIL_THREADS = 1024;
-
 // reduction workspace: max(E, threads of any caller)
 template <int E>
 struct RedWs {

@@ -220,7 +220,11 @@ static hipError_t launch_product(Ctx& c, const Plan& pl, const double* P, double
 // workgroups (fixed order) into c.part_r.
 static hipError_t staged_partials(Ctx& c, int nwg, int E, const double* part,
                                   const double** use, int* use_nwg) {
-    if (nwg <= 2 * PART_REDUCE_G) {
+    // the tail's own threads per entry (a power of two, as in reduce_partials)
+    int tpe = 1;
+    while (tpe * 2 * E <= TAIL_THREADS) tpe *= 2;
+    // one stage when each tail thread adds at most 32 partials
+    if (nwg <= 2 * PART_REDUCE_G || nwg <= 32 * tpe) {
         *use = part;
         *use_nwg = nwg;
         return hipSuccess;
