@@ -93,13 +93,18 @@ __device__ bool grid_sync(BCtl* ctl, long long spin_limit, int* flag) {
     return ab == 0;
 }
 
-// block-wide fixed-order sum of one value per thread (result valid in thread 0)
+// block-wide fixed-order sum of one value per thread, by a pairwise tree
+// (result valid in thread 0)
 __device__ double block_sum(double v, double* red) {
-    red[threadIdx.x] = v;
+    const int t = threadIdx.x;
+    red[t] = v;
     __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int k = 0; k < MB_BLOCK; ++k) s += red[k];
+#pragma unroll
+    for (int h = MB_BLOCK / 2; h >= 1; h /= 2) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double s = red[0];
     __syncthreads();
     return s;
 }
@@ -373,12 +378,8 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
     double* out = a.part + it * PSTRIDE;
     gs.finish(red, out);
     red[t] = nu;
-    __syncthreads();
-    if (t < S) {
-        double s = 0.0;
-        for (int q = 0; q < RPP; ++q) s += red[t + q * S];
-        out[E + t] = s;
-    }
+    column_sums<S>(red);
+    if (t < S) out[E + t] = red[t];
     __syncthreads();
 }
 

@@ -151,18 +151,21 @@ struct TileSums {
     }
 
     // Writes the workgroup's ETOT sums to out[0..ETOT).  lds must hold
-    // MB_BLOCK doubles.  Ends with a barrier.
+    // MB_BLOCK doubles.  Ends with a barrier.  The TPE partial sums of an
+    // entry are added by a pairwise tree (fixed order).
     __device__ __forceinline__ void finish(double* lds, double* out) {
         if (TPE > 1) {
             __syncthreads();
             lds[threadIdx.x] = acc[0];
             __syncthreads();
-            const int e = threadIdx.x;
-            if (e < ETOT) {
-                double s = 0.0;
-                for (int q = 0; q < TPE; ++q) s += lds[e * TPE + q];
-                out[e] = s;
+            const int q = threadIdx.x % TPE;
+#pragma unroll
+            for (int h = TPE / 2; h >= 1; h /= 2) {
+                if (q < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+                __syncthreads();
             }
+            const int e = threadIdx.x;
+            if (e < ETOT) out[e] = lds[e * TPE];
             __syncthreads();
         } else {
 #pragma unroll
@@ -171,6 +174,21 @@ struct TileSums {
         }
     }
 };
+
+// Column sums of red[q * S + j] over q < MB_BLOCK / S (one value per thread,
+// thread t = q * S + j already stored), by a pairwise tree over q; the sum
+// of column j ends in red[j].  Starts and ends with a barrier.
+template <int S>
+__device__ __forceinline__ void column_sums(double* red) {
+    constexpr int RPP = MB_BLOCK / S;
+    const int t = threadIdx.x, q = t / S;
+    __syncthreads();
+#pragma unroll
+    for (int h = RPP / 2; h >= 1; h /= 2) {
+        if (q < h) red[t] += red[t + h * S];
+        __syncthreads();
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Lower triangle of X^T Y over the rows of tiles, on the matrix cores

@@ -166,12 +166,8 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
     else gs.finish(red, out);
     __syncthreads();
     red[t] = nu;
-    __syncthreads();
-    if (t < S) {
-        double s = 0.0;
-        for (int q = 0; q < RPP; ++q) s += red[t + q * S];
-        out[E + t] = s;
-    }
+    column_sums<S>(red);
+    if (t < S) out[E + t] = red[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -408,12 +404,8 @@ __global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* _
     else gs.finish(red, out);
     __syncthreads();
     red[t] = nu;
-    __syncthreads();
-    if (t < S) {
-        double s = 0.0;
-        for (int q = 0; q < RPP; ++q) s += red[t + q * S];
-        out[E + t] = s;
-    }
+    column_sums<S>(red);
+    if (t < S) out[E + t] = red[t];
 }
 
 // ---------------------------------------------------------------------------
