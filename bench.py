@@ -462,6 +462,12 @@ def bench_dense(args, mixed):
             "mfma_TFLOPs": round(flops_prod / (prod_ms * 1e-3) / 1e12, 2),
             "mfma_peak_TFLOPs": peak_tf,
             "mfma_frac": round(flops_prod / (prod_ms * 1e-3) / 1e12 / peak_tf, 4),
+            # fraction of the attainable roofline min(MFMA peak, HBM peak x intensity)
+            "attainable_TFLOPs": round(min(peak_tf, HBM_PEAK_GBS * 1e9 * flops_prod / bytes_prod
+                                           / 1e12), 2),
+            "attainable_frac": round(flops_prod / (prod_ms * 1e-3) / 1e12
+                                     / min(peak_tf, HBM_PEAK_GBS * 1e9 * flops_prod / bytes_prod
+                                           / 1e12), 4),
         },
         "cpu_baseline": None,
         "sweep": sweep,
@@ -518,6 +524,33 @@ def bench_batch(args):
     nnz = sum(y.A.nnz for y in systems)
     n_tot = sum(y.A.n for y in systems)
     worst = max(i["rel_res_true"] for i in infos)
+    # algorithmic bytes of the whole job: per system and iteration the block
+    # product (CSR once, P read, Q written) and the streaming updates (update
+    # 8 n S + n words, direction 4 n S words); the profiled run's stamped
+    # phases give the time they took
+    def pad(s_):
+        S_ = 1
+        while S_ < s_:
+            S_ *= 2
+        return S_
+    prod_b = upd_b = 0
+    for y, inf in zip(systems, infos):
+        S_ = pad(y.s)
+        k = inf["iterations"]
+        prod_b += k * (12 * y.A.nnz + 4 * (y.A.n + 1) + 16 * y.A.n * S_)
+        upd_b += k * (8 * 8 * y.A.n * S_ + 8 * y.A.n + 4 * 8 * y.A.n * S_)
+    prod_s = phases["product"] * 1e-3
+    upd_s = (phases["update"] + phases["dir"]) * 1e-3
+    roof = {"bound": "hbm",
+            "achieved": round(prod_b / prod_s / 1e9, 1) if prod_s > 0 else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(prod_b / prod_s / 1e9 / HBM_PEAK_GBS, 4) if prod_s > 0 else None,
+            "traffic": None,
+            "kernel": "k_batch product phase (all systems' block products, summed over the "
+                      "profiled run's stamped phases)",
+            "bytes_total": prod_b,
+            "update_phases_GBps": round(upd_b / upd_s / 1e9, 1) if upd_s > 0 else None,
+            "job_GBps": round((prod_b + upd_b) / sec / 1e9, 1)}
     out = {
         "metric": "time-to-solution of the whole batch at rel.res 1e-8 (one persistent launch; "
                   "the same systems solved one after another beside it)",
@@ -534,7 +567,7 @@ def bench_batch(args):
         "sequential_seconds": round(seq, 4), "sequential_iterations_sum": sum(seq_its),
         "speedup_vs_sequential": round(seq / sec, 3),
         "ms_phases_profiled_run": phases,
-        "roofline": None, "cpu_baseline": None,
+        "roofline": roof, "cpu_baseline": None,
     }
     print(json.dumps(out))
     if out["converged"] != len(systems):

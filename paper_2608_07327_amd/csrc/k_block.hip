@@ -622,6 +622,16 @@ __global__ __launch_bounds__(MB_BLOCK) void k_cg_prec(int64_t n, const double* _
     }
 }
 
+__global__ void k_export_x(int64_t n, int S, int s, const double* __restrict__ Xt,
+                           const double* __restrict__ X0, double* __restrict__ out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * s;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / s;
+        const int j = (int)(e % s);
+        out[e] = Xt[r * S + j] + X0[r * S + j];
+    }
+}
+
 __global__ void k_unscale(int64_t n, const double* __restrict__ xs, const double* __restrict__ d,
                           double* __restrict__ x) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -857,6 +867,13 @@ hipError_t launch_cg_prec(int nwg, int64_t n, const double* r, const double* d, 
                            part, bj.inv, bj.Y);
         return hipGetLastError();
     })
+}
+
+hipError_t launch_export_x(int S, int64_t n, int s, const double* Xt, const double* X0, double* out,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_export_x, dim3(grid_for(n * s, 4096)), dim3(MB_BLOCK), 0, st, n, S, s, Xt,
+                       X0, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* x, hipStream_t s) {

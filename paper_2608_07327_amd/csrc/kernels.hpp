@@ -148,6 +148,9 @@ hipError_t launch_cg_update(int nwg, int64_t n, double* p, double* sv, double* x
 hipError_t launch_cg_prec(int nwg, int64_t n, const double* r, const double* d, double* part,
                           const BjArgs& bj, hipStream_t s);
 hipError_t launch_unscale(int64_t n, const double* xs, const double* d, double* x, hipStream_t s);
+// out (n x s row-major) = X~ + X0 (n x S blocks), the block iterate at exit
+hipError_t launch_export_x(int S, int64_t n, int s, const double* Xt, const double* X0, double* out,
+                           hipStream_t st);
 
 // ---- tails (one workgroup): reductions of partials + s x s FP64 work
 hipError_t launch_tail_gamma(int nwg_b, const double* part_b, int nwg_y, const double* part_y,

@@ -801,6 +801,17 @@ mbpcg_status solve_entry(Ctx& c, const double* b, double* x, mbpcg_mem mem,
     else if (p.precision == MBPCG_FP64) st = run_mbpcg(c, bd, xd, Ud, p, DENSE_F64, true, info);
     else st = run_ir(c, bd, mem == MBPCG_MEM_HOST ? nullptr : xd, Ud, p, info);
     if (st == MBPCG_ERR_HIP || st == MBPCG_ERR_OOM) return st;
+    if (!cg && p.precision == MBPCG_FP64 && p.X_out) {
+        // block iterate at exit (zero when the setup did not finish, e.g. b = 0)
+        const size_t bytes = sizeof(double) * (size_t)c.n * p.s;
+        double* dst = mem == MBPCG_MEM_HOST ? c.W : p.X_out;
+        if (c.st_host->ready)
+            CK(launch_export_x(padded_width(p.s), c.n, p.s, c.Xt, c.X0, dst, c.stream));
+        else
+            CK(hipMemsetAsync(dst, 0, bytes, c.stream));
+        if (mem == MBPCG_MEM_HOST)
+            CK(hipMemcpyAsync(p.X_out, c.W, bytes, hipMemcpyDeviceToHost, c.stream));
+    }
     if (mem == MBPCG_MEM_HOST) {
         const double* src = (!cg && p.precision != MBPCG_FP64) ? c.xacc : c.xdev;
         CK(hipMemcpyAsync(x, src, sizeof(double) * c.n, hipMemcpyDeviceToHost, c.stream));

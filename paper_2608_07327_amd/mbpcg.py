@@ -35,7 +35,7 @@ class Params(C.Structure):
                 ("U", C.c_void_p), ("tau", C.c_double), ("precision", C.c_int),
                 ("ir_tol", C.c_double), ("inner_tol", C.c_double), ("max_outer", C.c_int32),
                 ("history", C.c_void_p), ("poll_every", C.c_int32), ("profile", C.c_int32),
-                ("block_size", C.c_int32)]
+                ("block_size", C.c_int32), ("X_out", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -267,11 +267,16 @@ class Solver:
         return x, d
 
     def solve(self, b, x=None, history=False, **kw):
-        """MBPCG (Algorithm 1).  kw: fields of Params (s, tol, seed, precond, U, ...)."""
+        """MBPCG (Algorithm 1).  kw: fields of Params (s, tol, seed, precond, U, ...);
+        X_out: an optional n x s array (same memory kind as b) that receives the
+        block iterate X~ + X0 at exit (scaled space)."""
         U = kw.pop("U", None)
+        X_out = kw.pop("X_out", None)
         p = default_params(**kw)
         if U is not None:
             p.U, _ = _ptr_mem(U)
+        if X_out is not None:
+            p.X_out, _ = _ptr_mem(X_out)
         return self._solve("mbpcg_solve", b, x, p, history)
 
     def cg_solve(self, b, x=None, history=False, **kw):

@@ -354,6 +354,32 @@ def test_block_jacobi_reports_an_indefinite_block_and_rejects_bad_sizes():
     solver.close()
 
 
+@pytest.mark.parametrize("s", [3, 4, 8])
+def test_block_iterate_against_oracle(s):
+    # the block iterate X = X~ + X0 at exit (scaled space), exported on request
+    A = W.diffusion3d(20)
+    b = W.rhs(A.n, 75)
+    seed = W.uniform_block_seed(75, s)
+    _, io, exo = O.mbpcg_solve(A, b, s, seed=seed, want_X=True)
+    O.set_summation(1)
+    try:
+        _, ip, exp_ = O.mbpcg_solve(A, b, s, seed=seed, want_X=True)
+    finally:
+        O.set_summation(0)
+    say("block iterate", A.n, s)
+    solver = M.Solver.from_matrix(A)
+    Xg = torch.zeros((A.n, s), dtype=torch.float64, device=DEV)
+    _, info = solver.solve(dev(b), s=s, seed=seed, X_out=Xg)
+    Xh = np.zeros((A.n, s))
+    _, info_h = solver.solve(b, s=s, seed=seed, X_out=Xh)    # host memory
+    solver.close()
+    assert info["iterations"] == info_h["iterations"]
+    assert np.array_equal(Xg.cpu().numpy(), Xh)
+    if info["iterations"] == io["iterations"] == ip["iterations"]:
+        f = rel(exp_["X"], exo["X"])
+        assert rel(Xg.cpu().numpy(), exo["X"]) <= max(1e-10, 10 * f), (rel(Xg.cpu().numpy(), exo["X"]), f)
+
+
 def test_explicit_block_with_duplicate_columns_deflates():
     A = W.poisson2d(16)
     b = W.rhs(A.n, 6)
