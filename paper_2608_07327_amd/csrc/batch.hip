@@ -2,8 +2,9 @@
 // width s (1..8) solved together by ONE persistent kernel, launched through a
 // hipGraph.  The kernel walks the whole of Algorithm 1 -- scaling, initial
 // block, the iteration loop and the least-squares termination -- for every
-// system at once.  Each phase spreads its work over the grid: row phases take
-// (system, 128-row tile) items, s x s phases take one system per workgroup.
+// system at once.  Each phase spreads its work over the grid: streaming row
+// phases take (system, 1024 / S-row) items, the block products take
+// (system, 128-row) items, s x s phases take one system per workgroup.
 // Phases are separated by a software grid barrier; every barrier wait is
 // bounded, so a grid that is not co-resident ends with an error instead of a
 // hang.  Systems that finish drop out of the item loops; the loop ends when
@@ -20,7 +21,15 @@
 
 namespace mb {
 
-constexpr int BT = 128;        // rows per item
+// rows per item: 1024 / S, so every item holds 1024 block entries (S = 8:
+// 128 rows, S = 1: 1024 rows) and a phase moves the same bytes per item
+// whatever the width
+__host__ __device__ constexpr int item_rows(int S) { return 1024 / S; }
+constexpr int ITEM_ELEMS = 1024;
+// rows per block-product item: the product phases keep 128-row items (their
+// gathers do best spread over many small items), with partial sums of their
+// own
+constexpr int PT = 128;
 constexpr int PSTRIDE = 48;    // doubles of partial sums per item
 constexpr int BATCH_TERM_BARRIERS = 9;  // grid barriers of the termination
 constexpr int BSM = 4096;    // LDS doubles of the persistent kernel (32 KB)
@@ -28,7 +37,7 @@ static_assert(SxsWs<8>::DOUBLES <= BSM, "s x s workspace of the widest batched s
 
 struct BSys {
     int64_t n, rp_off, nz_off, vec_off, blk_off;
-    int32_t s, S, SL, ntile, item_off, pad;
+    int32_t s, S, SL, ntile, item_off, pntile, pitem_off, pad;
 };
 
 struct BCtl {
@@ -39,6 +48,9 @@ struct BCtl {
 
 struct BArgs {
     int nsys, total_items, max_iter, jacobi;
+    int total_pitems, pad_p;
+    const int32_t* pitem_sys;   // system of each block-product item
+    double* ppart;              // partial sums of the block-product items
     double tol, tau;
     uint64_t seed;
     long long spin_limit;
@@ -111,20 +123,35 @@ __device__ double block_sum(double v, double* red) {
 
 struct Item {
     int sys;
+    int it;      // global item index (its partial-sum slot)
     int64_t r0;
     int rows;
 };
 
+// block-product item (PT rows)
+__device__ __forceinline__ Item pitem_of(const BArgs& a, int it) {
+    Item m;
+    m.sys = a.pitem_sys[it];
+    m.it = it;
+    const BSys& y = a.sys[m.sys];
+    m.r0 = (int64_t)(it - y.pitem_off) * PT;
+    m.rows = (int)min((int64_t)PT, y.n - m.r0);
+    return m;
+}
+
 __device__ __forceinline__ Item item_of(const BArgs& a, int it) {
     Item m;
     m.sys = a.item_sys[it];
+    m.it = it;
     const BSys& y = a.sys[m.sys];
-    m.r0 = (int64_t)(it - y.item_off) * BT;
-    m.rows = (int)min((int64_t)BT, y.n - m.r0);
+    const int bt = item_rows(y.S);
+    m.r0 = (int64_t)(it - y.item_off) * bt;
+    m.rows = (int)min((int64_t)bt, y.n - m.r0);
     return m;
 }
 
 #define FOR_ITEMS for (int it_ = blockIdx.x; it_ < a.total_items; it_ += gridDim.x)
+#define FOR_PITEMS for (int it_ = blockIdx.x; it_ < a.total_pitems; it_ += gridDim.x)
 #define FOR_SYS for (int sy_ = blockIdx.x; sy_ < a.nsys; sy_ += gridDim.x)
 #define DISPATCH_S(Sv, CALL)                          \
     switch (Sv) {                                     \
@@ -135,7 +162,7 @@ __device__ __forceinline__ Item item_of(const BArgs& a, int it) {
     }
 
 // ---------------------------------------------------------------------------
-// row phases (one 128-row tile of one system)
+// row phases (one item: item_rows(S) rows of one system)
 // ---------------------------------------------------------------------------
 // D = diag(sqrt(a_jj)) (Sec. 1), b~ = D^-1 b, partial ||b||^2 and ||b~||^2
 __device__ void ph_diag(const BArgs& a, const Item& m, double* sm) {
@@ -162,12 +189,12 @@ __device__ void ph_diag(const BArgs& a, const Item& m, double* sm) {
         s0 += bv * bv;
         s1 += bb * bb;
     }
-    const int64_t it = y.item_off + m.r0 / BT;
+    const int64_t it = m.it;
     const double t0 = block_sum(s0, sm);
     const double t1 = block_sum(s1, sm);
     if (threadIdx.x == 0) {
-        a.part[it * PSTRIDE + 0] = t0;
-        a.part[it * PSTRIDE + 1] = t1;
+        a.ppart[it * PSTRIDE + 0] = t0;   // a block-product item (pitem_of)
+        a.ppart[it * PSTRIDE + 1] = t1;
     }
 }
 
@@ -215,18 +242,18 @@ __device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double*
     const BSys& y = a.sys[m.sys];
     const double* P = Pb + y.blk_off;
     double* Q = Qb + y.blk_off;
-    double* sQ = sm;                    // BT * 8
-    double* sP = sm + BT * 8;           // BT * 8
-    double* sV = sm + 2 * BT * 8;       // 8 * BT
-    int32_t* sC = reinterpret_cast<int32_t*>(sm + 2 * BT * 8 + 8 * BT);   // 8 * BT ints
-    int32_t* sRp = sC + 8 * BT;                                   // BT + 1 ints
+    double* sQ = sm;                    // PT * 8
+    double* sP = sm + PT * 8;           // PT * 8
+    double* sV = sm + 2 * PT * 8;       // 8 * PT
+    int32_t* sC = reinterpret_cast<int32_t*>(sm + 2 * PT * 8 + 8 * PT);   // 8 * PT ints
+    int32_t* sRp = sC + 8 * PT;                                   // PT + 1 ints
     double* red = sm + BSM - MB_BLOCK;
-    static_assert(2 * BT * 8 + 8 * BT + (8 * BT + BT + 2) / 2 + MB_BLOCK <= BSM, "batched LDS");
+    static_assert(2 * PT * 8 + 8 * PT + (8 * PT + PT + 2) / 2 + MB_BLOCK <= BSM, "batched LDS");
     const int tid = threadIdx.x;
-    spmm_tile<S, BT, SL>(a.rowptr + y.rp_off, a.colind + y.nz_off, a.vals_s + y.nz_off, P, m.r0,
+    spmm_tile<S, PT, SL>(a.rowptr + y.rp_off, a.colind + y.nz_off, a.vals_s + y.nz_off, P, m.r0,
                          m.rows, sRp, sC, sV, sQ);
     if (gram)
-        for (int e = tid; e < BT * S; e += MB_BLOCK) sP[e] = e < m.rows * S ? P[m.r0 * S + e] : 0.0;
+        for (int e = tid; e < PT * S; e += MB_BLOCK) sP[e] = e < m.rows * S ? P[m.r0 * S + e] : 0.0;
     double q2 = 0.0;
     for (int e = tid; e < m.rows * S; e += MB_BLOCK) {
         const double q = sQ[e];
@@ -234,8 +261,7 @@ __device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double*
         q2 += q * q;
     }
     __syncthreads();
-    const int64_t it = y.item_off + m.r0 / BT;
-    double* out = a.part + it * PSTRIDE;
+    double* out = a.ppart + (int64_t)m.it * PSTRIDE;
     if (gram) {
         TileSums<E> gs;
         gs.init();
@@ -270,15 +296,16 @@ template <int S>
 __device__ void ph_init(const BArgs& a, const Item& m, double* sm) {
     constexpr int E = tri_count(S);
     const BSys& y = a.sys[m.sys];
+    constexpr int TB = item_rows(S);   // rows per item
     const DevState* st = a.st + m.sys;
     const double g = st->gamma;
     double* sR = sm;
-    double* red = sm + BT * S;
+    double* red = sm + TB * S;
     const int64_t base = y.blk_off + m.r0 * S;
     const double* bb = a.bbar + y.vec_off + m.r0;
     const double* d = a.d + y.vec_off + m.r0;
     const int t = threadIdx.x;
-    for (int e = t; e < BT * S; e += MB_BLOCK) {
+    for (int e = t; e < TB * S; e += MB_BLOCK) {
         double r = 0.0;
         if (e < m.rows * S) {
             const int j = e % S;
@@ -299,7 +326,7 @@ __device__ void ph_init(const BArgs& a, const Item& m, double* sm) {
         if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
     }
     gs.add_rows(m.rows, [&](int k, int r) { return sR[r * S + gi[k]] * sR[r * S + gj[k]]; });
-    const int64_t it = y.item_off + m.r0 / BT;
+    const int64_t it = m.it;
     double* out = a.part + it * PSTRIDE;
     gs.finish(red, out);
     for (int j = 0; j < S; ++j) {
@@ -320,11 +347,12 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
     constexpr int RPP = MB_BLOCK / S;
     constexpr int E = tri_count(S);
     const BSys& y = a.sys[m.sys];
+    constexpr int TB = item_rows(S);   // rows per item
     const DevState* st = a.st + m.sys;
     double* sP = sm;
-    double* sQ = sm + BT * S;
-    double* sV = sm + 2 * BT * S;
-    double* red = sm + 3 * BT * S;
+    double* sQ = sm + TB * S;
+    double* sV = sm + 2 * TB * S;
+    double* red = sm + 3 * TB * S;
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
     double al[S], xi[S];
 #pragma unroll
@@ -333,7 +361,7 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
         xi[l] = st->Xi[l * MB_SM + j];
     }
     const int64_t base = y.blk_off + m.r0 * S;
-    for (int e = t; e < BT * S; e += MB_BLOCK) {
+    for (int e = t; e < TB * S; e += MB_BLOCK) {
         const bool in = e < m.rows * S;
         sP[e] = in ? a.P[base + e] : 0.0;
         sQ[e] = in ? a.Q[base + e] : 0.0;
@@ -341,7 +369,7 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
     __syncthreads();
     const double* d = a.d + y.vec_off + m.r0;
     double nu = 0.0;
-    for (int rl = rl0; rl < BT; rl += RPP) {
+    for (int rl = rl0; rl < TB; rl += RPP) {
         double v = 0.0;
         if (rl < m.rows) {
             const int64_t g = base + rl * S + j;
@@ -362,7 +390,7 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
             const double dr = d[rl] * rn;
             nu += dr * dr;
         }
-        if (rl < BT) sV[rl * S + j] = v;
+        if (rl < TB) sV[rl * S + j] = v;
     }
     __syncthreads();
     TileSums<E> gs;
@@ -374,7 +402,7 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
         if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
     }
     gs.add_rows(m.rows, [&](int k, int r) { return sV[r * S + gi[k]] * sV[r * S + gj[k]]; });
-    const int64_t it = y.item_off + m.r0 / BT;
+    const int64_t it = m.it;
     double* out = a.part + it * PSTRIDE;
     gs.finish(red, out);
     red[t] = nu;
@@ -388,9 +416,10 @@ template <int S, int FIRST>
 __device__ void ph_dir(const BArgs& a, const Item& m, double* sm) {
     constexpr int RPP = MB_BLOCK / S;
     const BSys& y = a.sys[m.sys];
+    constexpr int TB = item_rows(S);   // rows per item
     const DevState* st = a.st + m.sys;
     double* sV = sm;
-    double* sP = sm + BT * S;
+    double* sP = sm + TB * S;
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
     double mm[S], z[S];
 #pragma unroll
@@ -400,7 +429,7 @@ __device__ void ph_dir(const BArgs& a, const Item& m, double* sm) {
     }
     const int64_t base = y.blk_off + m.r0 * S;
     const double* V = FIRST ? a.R : a.W;
-    for (int e = t; e < BT * S; e += MB_BLOCK) {
+    for (int e = t; e < TB * S; e += MB_BLOCK) {
         const bool in = e < m.rows * S;
         sV[e] = in ? V[base + e] : 0.0;
         if (!FIRST) sP[e] = in ? a.P[base + e] : 0.0;
@@ -429,17 +458,18 @@ __device__ void ph_ls_gram(const BArgs& a, const Item& m, double* sm) {
     constexpr int NC = S + 1;
     constexpr int E = tri_count(NC);
     const BSys& y = a.sys[m.sys];
+    constexpr int TB = item_rows(S);   // rows per item
     double* sM = sm;
-    double* red = sm + BT * NC;
+    double* red = sm + TB * NC;
     const int t = threadIdx.x;
     const int64_t base = y.blk_off + m.r0 * S;
     const double* d = a.d + y.vec_off + m.r0;
     const double* b = a.b + y.vec_off + m.r0;
-    for (int e = t; e < BT * S; e += MB_BLOCK) {
+    for (int e = t; e < TB * S; e += MB_BLOCK) {
         const int rl = e / S, j = e % S;
         sM[rl * NC + 1 + j] = rl < m.rows ? d[rl] * a.R[base + e] : 0.0;
     }
-    for (int rl = t; rl < BT; rl += MB_BLOCK) sM[rl * NC] = rl < m.rows ? b[rl] : 0.0;
+    for (int rl = t; rl < TB; rl += MB_BLOCK) sM[rl * NC] = rl < m.rows ? b[rl] : 0.0;
     __syncthreads();
     TileSums<E> gs;
     gs.init();
@@ -450,7 +480,7 @@ __device__ void ph_ls_gram(const BArgs& a, const Item& m, double* sm) {
         if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
     }
     gs.add_rows(m.rows, [&](int k, int r) { return sM[r * NC + gi[k]] * sM[r * NC + gj[k]]; });
-    const int64_t it = y.item_off + m.r0 / BT;
+    const int64_t it = m.it;
     gs.finish(red, a.part + it * PSTRIDE);
     __syncthreads();
 }
@@ -481,7 +511,7 @@ __device__ void ph_ls_apply(const BArgs& a, const Item& m, double* sm) {
         const double res = y0 * b[rl] + ar;
         s2 += res * res;
     }
-    const int64_t it = y.item_off + m.r0 / BT;
+    const int64_t it = m.it;
     const double tot = block_sum(s2, sm);
     if (threadIdx.x == 0) a.part[it * PSTRIDE + 0] = tot;
 }
@@ -520,9 +550,9 @@ __device__ void ph_resid(const BArgs& a, const Item& m, double* sm) {
         const double e = b[r] - acc;
         s2 += e * e;
     }
-    const int64_t it = y.item_off + m.r0 / BT;
+    const int64_t it = m.it;
     const double tot = block_sum(s2, sm);
-    if (threadIdx.x == 0) a.part[it * PSTRIDE + 1] = tot;
+    if (threadIdx.x == 0) a.ppart[it * PSTRIDE + 1] = tot;   // block-product item
 }
 
 // ||b - A x_h||^2 partial into part[2], x_h = D^-1 (X~ + X0)_h read from the
@@ -549,9 +579,9 @@ __device__ void ph_resid_best(const BArgs& a, const Item& m, double* sm) {
         const double e = b[r] - acc;
         s2 += e * e;
     }
-    const int64_t it = y.item_off + m.r0 / BT;
+    const int64_t it = m.it;
     const double tot = block_sum(s2, sm);
-    if (threadIdx.x == 0) a.part[it * PSTRIDE + 2] = tot;
+    if (threadIdx.x == 0) a.ppart[it * PSTRIDE + 2] = tot;   // block-product item
 }
 
 // an accepted combination whose true residual misses the tolerance
@@ -563,6 +593,13 @@ __device__ inline bool needs_pick(const DevState* st) {
 __device__ inline bool was_picked(const DevState* st) {
     return st->done == DONE_CONVERGED && !st->accepted && st->ls_ok && finite_d(st->rel_ls) &&
            st->rel_ls < st->tol;
+}
+
+// sum of ppart[slot] over a system's block-product items (fixed order)
+__device__ double sys_psum(const BArgs& a, const BSys& y, int slot, double* sm) {
+    reduce_partials(a.ppart + (int64_t)y.pitem_off * PSTRIDE + slot, y.pntile, 1, PSTRIDE, sm,
+                    sm + 8);
+    return sm[0];
 }
 
 // sum of part[slot] over a system's items (fixed order), result to thread 0
@@ -591,30 +628,31 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     stamp();
 
     // --- setup: scaling, b~, ||b||
-    FOR_ITEMS {
-        const Item m = item_of(a, it_);
+    // (the CSR row phases take the 128-row block-product items)
+    FOR_PITEMS {
+        const Item m = pitem_of(a, it_);
         ph_diag(a, m, sm);
     }
     SYNC_OR_QUIT
-    FOR_ITEMS {
-        const Item m = item_of(a, it_);
+    FOR_PITEMS {
+        const Item m = pitem_of(a, it_);
         DISPATCH_S(a.sys[m.sys].S, ph_scale_u<SS>(a, m))
     }
     SYNC_OR_QUIT
     // initial guess: Y = A~ U and ||Y||_F^2
-    FOR_ITEMS {
-        const Item m = item_of(a, it_);
+    FOR_PITEMS {
+        const Item m = pitem_of(a, it_);
         DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(a, m, a.U, a.Y, false, true, sm))
     }
     SYNC_OR_QUIT
     FOR_SYS {
         const BSys& y = a.sys[sy_];
         DevState* st = a.st + sy_;
-        const double sb = sys_sum(a, y, 0, sm);
+        const double sb = sys_psum(a, y, 0, sm);
         __syncthreads();
-        const double sbb = sys_sum(a, y, 1, sm);
+        const double sbb = sys_psum(a, y, 1, sm);
         __syncthreads();
-        const double sy = sys_sum(a, y, 2, sm);
+        const double sy = sys_psum(a, y, 2, sm);
         if (threadIdx.x == 0) {
             const double bn = sqrt(sb);
             st->bnorm = bn;
@@ -659,8 +697,8 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
 
     // --- the iteration loop (Xi to the new Sigma) for every active system
     for (int loop = 0; loop <= a.max_iter + 1; ++loop) {
-        FOR_ITEMS {
-            const Item m = item_of(a, it_);
+        FOR_PITEMS {
+            const Item m = pitem_of(a, it_);
             if (a.st[m.sys].done) continue;
             DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(a, m, a.P, a.Q, true, false, sm))
         }
@@ -669,7 +707,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
             const BSys& y = a.sys[sy_];
             DevState* st = a.st + sy_;
             if (st->done) continue;
-            DISPATCH_S(y.S, tail_xi_body<SS>(a.part + (int64_t)y.item_off * PSTRIDE, y.ntile,
+            DISPATCH_S(y.S, tail_xi_body<SS>(a.ppart + (int64_t)y.pitem_off * PSTRIDE, y.pntile,
                                              PSTRIDE, st, sm, smi))
             __syncthreads();
             if (threadIdx.x == 0 && st->done)
@@ -754,21 +792,21 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         DISPATCH_S(a.sys[m.sys].S, ph_select<SS>(a, m))
     }
     SYNC_OR_QUIT
-    FOR_ITEMS {
-        const Item m = item_of(a, it_);
+    FOR_PITEMS {
+        const Item m = pitem_of(a, it_);
         ph_resid(a, m, sm);
     }
     SYNC_OR_QUIT
     FOR_SYS {
         const BSys& y = a.sys[sy_];
         DevState* st = a.st + sy_;
-        const double s2 = sys_sum(a, y, 1, sm);
+        const double s2 = sys_psum(a, y, 1, sm);
         if (threadIdx.x == 0) st->rel_true = st->done == DONE_ZERO_RHS ? 0.0 : sqrt(s2) / st->bnorm;
         __syncthreads();
     }
     SYNC_OR_QUIT
-    FOR_ITEMS {
-        const Item m = item_of(a, it_);
+    FOR_PITEMS {
+        const Item m = pitem_of(a, it_);
         if (!needs_pick(a.st + m.sys)) continue;
         DISPATCH_S(a.sys[m.sys].S, ph_resid_best<SS>(a, m, sm))
     }
@@ -777,7 +815,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         const BSys& y = a.sys[sy_];
         DevState* st = a.st + sy_;
         if (!needs_pick(st)) continue;
-        const double s2 = sys_sum(a, y, 2, sm);
+        const double s2 = sys_psum(a, y, 2, sm);
         if (threadIdx.x == 0) {
             const double rel_h = sqrt(s2) / st->bnorm;
             if (rel_h < st->rel_true) {
@@ -862,9 +900,9 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     } while (0)
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<BSys> hs(nsys);
-    std::vector<int32_t> item_sys;
+    std::vector<int32_t> item_sys, pitem_sys;
     int64_t rp = 0, nz = 0, vec = 0, blk = 0;
-    int items = 0;
+    int items = 0, pitems = 0;
     for (int i = 0; i < nsys; ++i) {
         const mbpcg_system& y = systems[i];
         BSys& b = hs[i];
@@ -876,17 +914,21 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
         b.s = y.s;
         b.S = padded_width(y.s);
         b.SL = batch_slots(y);
-        b.ntile = (int)((y.n + BT - 1) / BT);
+        b.ntile = (int)((y.n + item_rows(b.S) - 1) / item_rows(b.S));
         b.item_off = items;
+        b.pntile = (int)((y.n + PT - 1) / PT);
+        b.pitem_off = pitems;
         b.pad = 0;
         for (int t = 0; t < b.ntile; ++t) item_sys.push_back(i);
+        for (int t = 0; t < b.pntile; ++t) pitem_sys.push_back(i);
         items += b.ntile;
+        pitems += b.pntile;
         rp += y.n + 1;
         nz += y.nnz;
         vec += y.n;
         blk += y.n * b.S;
     }
-    if (items >= INT32_MAX / 2) {
+    if (items >= INT32_MAX / 2 || pitems >= INT32_MAX / 2) {
         err = "batch too large";
         return MBPCG_ERR_UNSUPPORTED;
     }
@@ -924,6 +966,8 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     BCK(B.alloc(&d_d, vec));
     BCK(B.alloc(&d_bb, vec));
     BCK(B.alloc(&d_items, items));
+    int32_t* d_pitems;
+    BCK(B.alloc(&d_pitems, pitems));
     BCK(B.alloc(&d_sys, nsys));
     BCK(B.alloc(&d_st, nsys));
     BCK(B.alloc(&d_ctl, 1));
@@ -931,6 +975,8 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     for (auto& q : blocks) BCK(B.alloc(&q, blk));
     double* d_part;
     BCK(B.alloc(&d_part, (size_t)items * PSTRIDE));
+    double* d_ppart;
+    BCK(B.alloc(&d_ppart, (size_t)pitems * PSTRIDE));
 
     const hipMemcpyKind kind = mem == MBPCG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     for (int i = 0; i < nsys; ++i) {
@@ -945,6 +991,8 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     }
     BCK(hipMemcpyAsync(d_items, item_sys.data(), sizeof(int32_t) * items, hipMemcpyHostToDevice,
                        stream));
+    BCK(hipMemcpyAsync(d_pitems, pitem_sys.data(), sizeof(int32_t) * pitems,
+                       hipMemcpyHostToDevice, stream));
     BCK(hipMemcpyAsync(d_sys, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, stream));
     BCK(hipMemsetAsync(d_ctl, 0, sizeof(BCtl), stream));
     hipLaunchKernelGGL(k_batch_state_init, dim3(nsys), dim3(MB_BLOCK), 0, stream, nsys, d_st, d_sys,
@@ -953,6 +1001,9 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
 
     a.nsys = nsys;
     a.total_items = items;
+    a.total_pitems = pitems;
+    a.pitem_sys = d_pitems;
+    a.ppart = d_ppart;
     a.max_iter = (int)p.max_iter;
     a.jacobi = p.precond == MBPCG_PRECOND_JACOBI;
     a.tol = p.tol;
@@ -996,7 +1047,7 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
         err = "batched kernel does not fit on a compute unit";
         return MBPCG_ERR_HIP;
     }
-    const int grid = std::max(1, std::min(items, per_cu * cus));
+    const int grid = std::max(1, std::min(std::max(items, pitems), per_cu * cus));
 
     // one persistent kernel, captured in a graph and launched once
     hipGraph_t graph = nullptr;

@@ -52,7 +52,7 @@ def oracle_pair(y, seed):
     return xs, i_s, xp, i_p
 
 
-def check_batch(systems, seed=100):
+def check_batch(systems, seed=100, x_floor=1e-10):
     items = to_items(systems)
     say("batch", len(items), [(y.A.n, y.s) for y in systems])
     st, infos = M.solve_batch(items, seed=seed)
@@ -78,7 +78,7 @@ def check_batch(systems, seed=100):
                 and not differ:
             f = np.linalg.norm(xp - xo) / np.linalg.norm(xo)
             err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
-            assert err <= max(1e-10, 10 * f), (i, err, f)
+            assert err <= max(x_floor, 10 * f), (i, err, f)
         if io["status"] == 0:
             assert info["rel_res_true"] < 2e-8, (i, info["rel_res_true"])
     return st, infos
@@ -112,7 +112,10 @@ def test_batch_falls_back_on_the_true_residual():
     for k, (n, s) in enumerate([(2000, 2), (2000, 8), (5000, 4), (1200, 1)]):
         A = W.graph_laplacian(n, 8, 1e-6, W.rng_for((W.CFG_BATCH, 98, n, k)))
         sys_list.append(W.BatchSystem(A, W.rng_for((99, k)).standard_normal(n), s))
-    st, infos = check_batch(sys_list, seed=21)
+    # kappa ~ 1.6e7 (lambda_min = 1e-6): a change of summation order moves x
+    # by up to ~kappa eps ~ 2e-9 relative, more than the two oracle orders
+    # happen to differ by, so the x floor is 1e-8 here
+    st, infos = check_batch(sys_list, seed=21, x_floor=1e-8)
     assert st == 0
     for y, info in zip(sys_list, infos):
         assert info["rel_res_true"] < 1e-8, info
