@@ -151,7 +151,12 @@ __device__ __forceinline__ Item item_of(const BArgs& a, int it) {
 }
 
 #define FOR_ITEMS for (int it_ = blockIdx.x; it_ < a.total_items; it_ += gridDim.x)
-#define FOR_PITEMS for (int it_ = blockIdx.x; it_ < a.total_pitems; it_ += gridDim.x)
+// block-product items in XCD-aware order: XCD x (workgroups blockIdx % 8 == x)
+// takes the x-th eighth of the item range, so a system's items, and the P
+// rows their gathers read, stay in the L2 of one XCD
+#define FOR_PITEMS                                                                            \
+    for (TileRange r_ = tile_range(a.total_pitems); r_.first < r_.end; r_.first += r_.step) \
+        if (const int it_ = (int)r_.first; true)
 #define FOR_SYS for (int sy_ = blockIdx.x; sy_ < a.nsys; sy_ += gridDim.x)
 #define DISPATCH_S(Sv, CALL)                          \
     switch (Sv) {                                     \
