@@ -1,7 +1,9 @@
-// One-workgroup tail kernels: add up the per-workgroup partial sums of a
-// reduction in a fixed order, then do the s x s FP64 work of the iteration.
-// The s x s factorisations run on one wavefront: step j is a barrier-separated
-// stage and lane i owns row (or column) i.
+// One-workgroup tail kernels (TAIL_THREADS threads): add up the per-workgroup
+// partial sums of a reduction in a fixed order, then do the s x s FP64 work of
+// the iteration.  The s x s factorisations run on one wavefront with lane i
+// owning row (or column) i and readlane broadcasts between the steps; for
+// s >= 16 the inverse of P^T A P is a Gauss-Jordan elimination with one
+// thread per entry.
 #include "dev_sxs.hpp"
 #include "kernels.hpp"
 
