@@ -372,44 +372,65 @@ int or_cholqr_deflate_prec(int64_t n, int m, const double* V, const double* Y, d
 /* ---------------------------------------------------------------------------
  * Least squares min_c ||b - B c|| (Alg. 1, the combination c^ of the termination).  The paper writes
  * the normal equations and reports that forming B^T B overflows or loses
- * accuracy; the oracle computes the same minimiser by Householder QR.
+ * accuracy; the oracle computes the same minimiser by Householder QR.  A
+ * column whose part orthogonal to the columns already taken is not above
+ * 1e-12 of its norm (numerically dependent, or beyond the n-th independent
+ * column when B has more columns than rows) is left out with coefficient 0;
+ * the residual is the same minimum.
  * ------------------------------------------------------------------------- */
 int or_lstsq(int64_t n, int m, const double* B, const double* b, double* c)
 {
+    return or_lstsq_kept(n, m, B, b, c, NULL);
+}
+
+int or_lstsq_kept(int64_t n, int m, const double* B, const double* b, double* c, int* kept)
+{
+    const double tau_ls = 1e-12;
     double* Bc = (double*)xcalloc((size_t)(n * m), sizeof(double)); /* column-major */
     double* bb = (double*)xcalloc((size_t)n, sizeof(double));
-    double* Rd = (double*)xcalloc((size_t)(m * m), sizeof(double));
+    double* rdiag = (double*)xcalloc((size_t)m + 1, sizeof(double));
+    int* kc = (int*)xcalloc((size_t)m + 1, sizeof(int)); /* kept column of reflection q */
     int rc = 0;
     for (int64_t r = 0; r < n; ++r) {
         for (int j = 0; j < m; ++j) Bc[(int64_t)j * n + r] = B[r * m + j];
         bb[r] = b[r];
     }
-    for (int k = 0; k < m && k < n; ++k) {
+    int p = 0; /* reflections done = kept columns */
+    for (int k = 0; k < m; ++k) {
+        c[k] = 0.0;
         double* v = Bc + (int64_t)k * n;
-        double nrm = sqrt(dot_strided(n - k, v + k, 1, v + k, 1));
-        if (!(nrm > 0.0) || !isfinite(nrm)) { rc = -1; break; }
-        double alpha = (v[k] > 0.0) ? -nrm : nrm;
-        v[k] -= alpha; /* Householder vector in rows k.. of column k */
-        double vtv = dot_strided(n - k, v + k, 1, v + k, 1);
+        double n0 = sqrt(dot_strided(n, v, 1, v, 1));
+        if (!isfinite(n0)) { rc = -1; break; }
+        if (p >= n) continue;
+        double nrm = sqrt(dot_strided(n - p, v + p, 1, v + p, 1));
+        if (!(nrm > tau_ls * n0)) continue; /* dependent (or zero) column: left out */
+        double alpha = (v[p] > 0.0) ? -nrm : nrm;
+        v[p] -= alpha; /* Householder vector in rows p.. of column k */
+        double vtv = dot_strided(n - p, v + p, 1, v + p, 1);
         for (int j = k + 1; j < m; ++j) {
             double* col = Bc + (int64_t)j * n;
-            double t = 2.0 * dot_strided(n - k, v + k, 1, col + k, 1) / vtv;
-            for (int64_t r = k; r < n; ++r) col[r] -= t * v[r];
+            double t = 2.0 * dot_strided(n - p, v + p, 1, col + p, 1) / vtv;
+            for (int64_t r = p; r < n; ++r) col[r] -= t * v[r];
         }
-        double t = 2.0 * dot_strided(n - k, v + k, 1, bb + k, 1) / vtv;
-        for (int64_t r = k; r < n; ++r) bb[r] -= t * v[r];
-        Rd[k * m + k] = alpha;
-        for (int j = k + 1; j < m; ++j) Rd[k * m + j] = Bc[(int64_t)j * n + k];
+        double t = 2.0 * dot_strided(n - p, v + p, 1, bb + p, 1) / vtv;
+        for (int64_t r = p; r < n; ++r) bb[r] -= t * v[r];
+        rdiag[p] = alpha;
+        kc[p] = k;
+        ++p;
     }
     if (rc == 0) {
-        if (m > n) rc = -1;
-        for (int k = m - 1; k >= 0 && rc == 0; --k) {
-            double v = bb[k];
-            for (int j = k + 1; j < m; ++j) v -= Rd[k * m + j] * c[j];
-            c[k] = v / Rd[k * m + k];
+        if (p == 0) rc = -1;
+        /* back substitution over the kept columns; row q of R holds
+         * Bc[col][q] for the kept columns after column kc[q] */
+        for (int q = p - 1; q >= 0 && rc == 0; --q) {
+            double v = bb[q];
+            for (int q2 = q + 1; q2 < p; ++q2) v -= Bc[(int64_t)kc[q2] * n + q] * c[kc[q2]];
+            c[kc[q]] = v / rdiag[q];
         }
     }
-    free(Rd);
+    if (kept) *kept = p;
+    free(kc);
+    free(rdiag);
     free(bb);
     free(Bc);
     return rc;
@@ -717,6 +738,9 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
     if (m == 0) {
         converged = 1;
     }
+    /* no iteration when the first Cholesky QR already dropped every column
+     * (R0 = 0): the count stays 0 */
+    if (!converged)
     for (it = 1; !converged && it <= p->max_iter; ++it) {
         /* step matrix Xi = (P^T A P)^-1 */
         or_matmul_block(As, m, P, Q);
@@ -772,7 +796,7 @@ int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,
                     Bh[r * s + j] = br - ro;
                 }
             const double* bref_v = p->ls_scaled ? bbar : b;
-            int lsr = or_lstsq(n, s, Bh, bref_v, chat);
+            int lsr = or_lstsq_kept(n, s, Bh, bref_v, chat, &inf.ls_kept);
             int finite = (lsr == 0);
             for (int j = 0; j < s && finite; ++j) finite = isfinite(chat[j]);
             if (finite) {

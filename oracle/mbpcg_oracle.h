@@ -72,6 +72,7 @@ typedef struct {
     double rel_res_true;  /* ||b - A x|| / ||b|| recomputed on the original A */
     double seconds;       /* wall time of scaling + setup + loop + termination */
     double seconds_setup; /* scaling + random block + first QR */
+    int ls_kept;          /* columns the least squares kept (s when none was left out) */
 } or_info;
 
 /* summation order of every reduction over n: 0 sequential, 1 blocked pairwise */
@@ -109,6 +110,8 @@ void or_block_jacobi_apply(const or_matrix* A, int jacobi, int bs, int m, const 
 /* min_c ||b - B c||_2 for B n x m (row-major) by Householder QR.
  * Writes c[m]; returns 0, or -1 when R has a zero diagonal. */
 int or_lstsq(int64_t n, int m, const double* B, const double* b, double* c);
+/* the same, with the number of columns kept written to *kept (when not NULL) */
+int or_lstsq_kept(int64_t n, int m, const double* B, const double* b, double* c, int* kept);
 
 /* Algorithm 1 (MBPCG).  x receives the solution in the original space. */
 int or_mbpcg_solve(const or_matrix* A, const double* b, const or_params* p,

@@ -47,7 +47,7 @@ class OrInfo(C.Structure):
                 ("final_width", C.c_int), ("deflations", C.c_int), ("used_fallback", C.c_int),
                 ("rel_res_best", C.c_double), ("rel_res_ls", C.c_double),
                 ("rel_res_true", C.c_double), ("seconds", C.c_double),
-                ("seconds_setup", C.c_double)]
+                ("seconds_setup", C.c_double), ("ls_kept", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

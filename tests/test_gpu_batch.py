@@ -69,13 +69,16 @@ def check_batch(systems, seed=100, x_floor=1e-10):
             assert not np.any(x), i
             continue
         # the combination-or-best-column choice on true residuals may differ
-        # (see test_gpu_parity.check_against_oracle); the GPU's pick meets tol
+        # where it is rounding-sensitive, and x is compared only for a unique
+        # least-squares minimiser (see test_gpu_parity.check_against_oracle)
         picked = io["status"] == 0 and io["used_fallback"] == 1 and io["rel_res_ls"] < 1e-8
-        differ = picked and info["used_fallback"] != io["used_fallback"]
+        unique = io["used_fallback"] == 1 or io["ls_kept"] == y.s
+        differ = io["status"] == 0 and info["used_fallback"] != io["used_fallback"]
         if differ:
-            assert info["used_fallback"] == 0 and info["rel_res_true"] < 1e-8, (i, info)
+            assert picked or not unique, (i, info, io)
+            assert info["rel_res_true"] < 1e-8, (i, info)
         if info["iterations"] == io["iterations"] and ip["iterations"] == io["iterations"] \
-                and not differ:
+                and not differ and unique:
             f = np.linalg.norm(xp - xo) / np.linalg.norm(xo)
             err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
             assert err <= max(x_floor, 10 * f), (i, err, f)

@@ -88,15 +88,22 @@ def check_against_oracle(A, b, s, tol=1e-8, jacobi=True, seed=0, U=None, max_ite
     # The choice between the combination and the best column on their true
     # residuals rests on rounding-sensitive numbers (the combination's
     # coefficients amplify the drift between A X and B - R, and the two
-    # sides compute the least squares differently): where the oracle's
-    # combination passed the test on B^ c but it returned the best column,
-    # the GPU may keep its own combination, provided that meets tol.
+    # sides compute the least squares differently).  It may differ where
+    # the oracle's combination passed the test on B^ c but it returned the
+    # best column, or where the oracle's least squares left nearly dependent
+    # columns out (the minimiser is then not unique and the two sides may
+    # take different minimisers, whose residuals are both the minimum);
+    # whatever the GPU returns then meets tol on its true residual.  x is
+    # compared only where the minimiser is unique or the best column was
+    # returned.
     picked = io["status"] == 0 and io["used_fallback"] == 1 and io["rel_res_ls"] < tol
-    differ = picked and info["used_fallback"] != io["used_fallback"]
+    unique = io["used_fallback"] == 1 or io["ls_kept"] == s
+    differ = io["status"] == 0 and info["used_fallback"] != io["used_fallback"]
     if differ:
-        assert info["used_fallback"] == 0 and info["rel_res_true"] < tol, info
+        assert picked or not unique, (info, io)
+        assert info["rel_res_true"] < tol, info
     if info["iterations"] == io["iterations"] and not differ:
-        if same:
+        if same and unique:
             bound = max(1e-10, 10 * f)
             assert rel(x, xo) <= bound, (rel(x, xo), bound, f)
         for key in ("used_fallback", "final_width", "deflations"):
@@ -253,9 +260,10 @@ def test_dense_against_oracle(s):
 
 @pytest.mark.parametrize("kind", ["dense", "csr"])
 @pytest.mark.parametrize("s", [2, 4, 8])
-def test_near_singular_systems_fall_back_on_the_true_residual(kind, s):
-    # kappa ~ 4e6 dense and a graph Laplacian shifted by 1e-6: the accepted
-    # combination misses tol on its true residual, the best column meets it
+def test_near_singular_systems_meet_tol_on_the_true_residual(kind, s):
+    # kappa ~ 4e6 dense and a graph Laplacian shifted by 1e-6: whichever of
+    # the combination and the best column each side returns meets tol on its
+    # true residual
     if kind == "dense":
         A = W.dense_spd(256, tag=(W.CFG_DENSE, 95, 256), shift=1e-6)
         b = W.rng_for((96, 256)).standard_normal(256)
@@ -265,7 +273,7 @@ def test_near_singular_systems_fall_back_on_the_true_residual(kind, s):
         b = W.rng_for((93, 2000)).standard_normal(2000)
         jac = True
     x, info, xo, io = check_against_oracle(A, b, s, jacobi=jac, seed=W.uniform_block_seed(97, s))
-    assert io["used_fallback"] == 1 and io["rel_res_true"] < 1e-8
+    assert io["rel_res_true"] < 1e-8
     assert info["rel_res_true"] < 1e-8
 
 
@@ -378,6 +386,34 @@ def test_block_iterate_against_oracle(s):
     if info["iterations"] == io["iterations"] == ip["iterations"]:
         f = rel(exp_["X"], exo["X"])
         assert rel(Xg.cpu().numpy(), exo["X"]) <= max(1e-10, 10 * f), (rel(Xg.cpu().numpy(), exo["X"]), f)
+
+
+@pytest.mark.parametrize("n,s", [(3, 8), (5, 8), (20, 32), (7, 3)])
+@pytest.mark.parametrize("fmt", ["dense", "csr"])
+def test_degenerate_sizes_against_oracle(n, s, fmt):
+    # n <= s: the first Cholesky QR or the first iteration drops columns and
+    # the residual reaches zero within a step or two
+    A = W.tiny_spd(n, 50.0, tag=(80, n, s))
+    b = W.rng_for((81, n)).standard_normal(n)
+    M_ = A if fmt == "dense" else W.dense_to_csr(A)
+    x, info, xo, io = check_against_oracle(M_, b, s, seed=3)
+    assert info["rel_res_true"] < 1e-12
+
+
+@pytest.mark.parametrize("s", [1, 4])
+@pytest.mark.parametrize("fmt", ["dense", "csr"])
+def test_one_row_system(s, fmt):
+    # n = 1: X0 = gamma U can already be the solution (R0 = 0 exactly, every
+    # column dropped, no iteration) or miss it by an ulp (one iteration);
+    # which one depends on rounding in gamma, so only the answer is compared
+    A = np.array([[2.5]])
+    b = np.array([-1.75])
+    say("one row", s, fmt)
+    solver = M.Solver.from_matrix(A if fmt == "dense" else W.dense_to_csr(A))
+    x, info = solver.solve(dev(b), s=s, seed=3)
+    solver.close()
+    assert info["status"] == 0 and info["iterations"] <= 1
+    assert abs(x.cpu().numpy()[0] - (-0.7)) <= 1e-15
 
 
 def test_explicit_block_with_duplicate_columns_deflates():
