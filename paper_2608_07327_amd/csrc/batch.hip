@@ -257,8 +257,23 @@ __device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double*
     const int tid = threadIdx.x;
     spmm_tile<S, PT, SL>(a.rowptr + y.rp_off, a.colind + y.nz_off, a.vals_s + y.nz_off, P, m.r0,
                          m.rows, sRp, sC, sV, sQ);
-    if (gram)
-        for (int e = tid; e < PT * S; e += MB_BLOCK) sP[e] = e < m.rows * S ? P[m.r0 * S + e] : 0.0;
+    if (gram) {
+        // all loads first, then the LDS stores: one memory round trip
+        constexpr int PPT = (PT * S + MB_BLOCK - 1) / MB_BLOCK;
+        double pv[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            const bool in = e < m.rows * S;
+            const double v = P[m.r0 * S + (in ? e : 0)];
+            pv[q] = in ? v : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            if (e < PT * S) sP[e] = pv[q];
+        }
+    }
     double q2 = 0.0;
     for (int e = tid; e < m.rows * S; e += MB_BLOCK) {
         const double q = sQ[e];

@@ -78,6 +78,35 @@ template <class T>
 __device__ __forceinline__ void stream_store(T* p, T v) { __builtin_nontemporal_store(v, p); }
 
 // ---------------------------------------------------------------------------
+// A copy of N consecutive doubles into LDS, split into a load step and a
+// store step so that a kernel can issue every load of a tile (several
+// blocks, its own rows) before the first LDS store: the copy then costs one
+// memory round trip instead of one per element a thread moves.  Elements at
+// or beyond `valid` are zero; their addresses are clamped to src[0].
+// ---------------------------------------------------------------------------
+template <int N>
+struct Stage {
+    static constexpr int EPT = (N + MB_BLOCK - 1) / MB_BLOCK;
+    double v[EPT];
+    __device__ __forceinline__ void load(const double* __restrict__ src, int valid) {
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = threadIdx.x + q * MB_BLOCK;
+            const bool in = e < valid;
+            const double x = src[in ? e : 0];
+            v[q] = in ? x : 0.0;
+        }
+    }
+    __device__ __forceinline__ void store(double* dst) const {
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = threadIdx.x + q * MB_BLOCK;
+            if (N % MB_BLOCK == 0 || e < N) dst[e] = v[q];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Work split of n rows, in tiles of T rows, over the grid.  On MI355X
 // consecutive workgroup ids land on different XCDs (8 of them, each with its
 // own L2), so when the grid is a multiple of 8 each XCD is given one

@@ -40,7 +40,21 @@ __device__ __forceinline__ void spmm_tile(const int32_t* __restrict__ rowptr,
     const int tid = threadIdx.x;
     const int grp = tid / TL::LPR, lane = tid % TL::LPR;
     const int slot = lane / S, j = lane % S;
-    for (int e = tid; e <= rows; e += MB_BLOCK) sRp[e] = rowptr[r0 + e];
+    // each staging copy issues all of a thread's loads before its LDS stores
+    // (one memory round trip; addresses clamped inside the arrays)
+    constexpr int RPT = (T + 1 + MB_BLOCK - 1) / MB_BLOCK;
+    constexpr int CPT = (NZC + MB_BLOCK - 1) / MB_BLOCK;
+    int rpv[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int e = tid + q * MB_BLOCK;
+        rpv[q] = rowptr[r0 + (e <= rows ? e : 0)];
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int e = tid + q * MB_BLOCK;
+        if (e <= rows) sRp[e] = rpv[q];
+    }
     __syncthreads();
     const int nz0 = sRp[0];
     const int nzt = sRp[rows] - nz0;
@@ -49,9 +63,22 @@ __device__ __forceinline__ void spmm_tile(const int32_t* __restrict__ rowptr,
     for (int i = 0; i < NR; ++i) acc[i] = 0.0;
     for (int cb = 0; cb < nzt; cb += NZC) {
         const int cn = min(NZC, nzt - cb);
-        for (int e = tid; e < cn; e += MB_BLOCK) {
-            sC[e] = colind[nz0 + cb + e];
-            sV[e] = vals[nz0 + cb + e];
+        int cc[CPT];
+        double cv[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            const int64_t g = (int64_t)nz0 + cb + (e < cn ? e : 0);
+            cc[q] = colind[g];
+            cv[q] = vals[g];
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            if (e < cn) {
+                sC[e] = cc[q];
+                sV[e] = cv[q];
+            }
         }
         __syncthreads();
 #pragma unroll

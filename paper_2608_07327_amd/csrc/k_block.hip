@@ -101,16 +101,30 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
     for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
         const int64_t r0 = tile * T;
         const int rows = (int)min((int64_t)T, n - r0);
-        const double* Pt = P + r0 * S;
-        const double* Qt = Q + r0 * S;
-        for (int e = t; e < T * S; e += MB_BLOCK) {
-            const bool in = e < rows * S;
-            sP[e] = in ? Pt[e] : 0.0;
-            sQ[e] = in ? Qt[e] : 0.0;
-            if constexpr (LW) sW[e] = in ? W[r0 * S + e] : 0.0;   // the previous V
+        // every load of the tile (the P, Q and previous-V tiles and this
+        // thread's X~, R and d entries) is issued before the first LDS store
+        constexpr int RT = T / RPP;   // rows per thread
+        Stage<T * S> stp, stq, stw;
+        stp.load(P + r0 * S, rows * S);
+        stq.load(Q + r0 * S, rows * S);
+        if constexpr (LW) stw.load(W + r0 * S, rows * S);   // the previous V
+        double xo[RT], ro[RT], wo[LW ? 1 : RT], dv[RT];
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int rl = rl0 + k * RPP;
+            const int64_t g = (r0 + (rl < rows ? rl : 0)) * S + j;
+            xo[k] = stream_load(Xt + g);
+            ro[k] = stream_load(R + g);
+            if constexpr (!LW) wo[k] = W[g];
+            dv[k] = d[r0 + (rl < rows ? rl : 0)];
         }
+        stp.store(sP);
+        stq.store(sQ);
+        if constexpr (LW) stw.store(sW);
         __syncthreads();
-        for (int rl = rl0; rl < T; rl += RPP) {
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int rl = rl0 + k * RPP;
             double v = 0.0;
             if (rl < rows) {
                 const int64_t g = (r0 + rl) * S + j;
@@ -122,21 +136,21 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
                     trr += q * al[l];
                     tv += q * xi[l];
                 }
-                const double xn = stream_load(Xt + g) + tx;
-                const double rn = stream_load(R + g) - trr;
+                const double xn = xo[k] + tx;
+                const double rn = ro[k] - trr;
                 double w;
                 if constexpr (LW) {
                     w = 0.0;
 #pragma unroll
                     for (int l = 0; l < S; ++l) w += sW[rl * S + l] * mp[l];
                 } else {
-                    w = W[g];
+                    w = wo[k];
                 }
                 v = w - tv;
                 stream_store(Xt + g, xn);
                 stream_store(R + g, rn);
                 W[g] = v;
-                const double dr = d[r0 + rl] * rn;
+                const double dr = dv[k] * rn;
                 nu += dr * dr;
             }
             sV[rl * S + j] = v;
@@ -202,12 +216,14 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
     for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
         const int64_t r0 = tile * T;
         const int rows = (int)min((int64_t)T, n - r0);
-        for (int e = t; e < T * S; e += MB_BLOCK) {
-            const bool in = e < rows * S;
-            sV[e] = in ? W[r0 * S + e] : 0.0;
-            if (!FIRST) sP[e] = in ? P[r0 * S + e] : 0.0;
-            if (PREC) sY[e] = in ? Yp[r0 * S + e] : 0.0;
-        }
+        // all loads of the tile before the first LDS store
+        Stage<T * S> stv, stp, sty;
+        stv.load(W + r0 * S, rows * S);
+        if (!FIRST) stp.load(P + r0 * S, rows * S);
+        if (PREC) sty.load(Yp + r0 * S, rows * S);
+        stv.store(sV);
+        if (!FIRST) stp.store(sP);
+        if (PREC) sty.store(sY);
         __syncthreads();
         for (int rl = rl0; rl < rows; rl += RPP) {
             double w = 0.0;

@@ -78,6 +78,9 @@ void k_spmm(const int32_t* __restrict__ rowptr,
     constexpr int S = B::S, T = B::T, SL = B::SL, V = B::V, U = B::U;
     constexpr int RPP = B::RPP, NR = B::NR, NZC = B::NZC;
     constexpr bool REG = B::REG, MF = B::MF;
+    constexpr int RPT = (T + 1 + MB_BLOCK - 1) / MB_BLOCK;   // row pointers per thread
+    constexpr int PPT = (T * S + MB_BLOCK - 1) / MB_BLOCK;   // staged P entries per thread
+    constexpr int CPT = (NZC + MB_BLOCK - 1) / MB_BLOCK;     // CSR entries per thread and chunk
     constexpr int E = tri_count(S);
     if (st && st->done) return;
     __shared__ int32_t sRp[T + 1];
@@ -117,7 +120,17 @@ void k_spmm(const int32_t* __restrict__ rowptr,
         const int rows = (int)min((int64_t)T, n - r0);
         const double* Pt = P + r0 * S;
 
+        // Every staging copy below issues all of a thread's loads before its
+        // first LDS store (fixed per-thread counts, addresses clamped inside
+        // the arrays), so each stage costs one memory round trip per tile.
         double pr[REG ? NR : 1][S];    // register Gram: this lane's P rows
+        int rpv[RPT];
+        double ppv[REG ? 1 : PPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            rpv[q] = rowptr[r0 + (e <= rows ? e : 0)];
+        }
         if (gram) {
             if constexpr (REG) {
 #pragma unroll
@@ -131,10 +144,29 @@ void k_spmm(const int32_t* __restrict__ rowptr,
                     }
                 }
             } else {
-                for (int e = tid; e < T * S; e += MB_BLOCK) sP[e] = e < rows * S ? Pt[e] : 0.0;
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    const int e = tid + q * MB_BLOCK;
+                    const bool in = e < rows * S;
+                    const double v = Pt[in ? e : 0];
+                    ppv[q] = in ? v : 0.0;
+                }
             }
         }
-        for (int e = tid; e <= rows; e += MB_BLOCK) sRp[e] = rowptr[r0 + e];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            if (e <= rows) sRp[e] = rpv[q];
+        }
+        if constexpr (!REG) {
+            if (gram) {
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    const int e = tid + q * MB_BLOCK;
+                    if (e < T * S) sP[e] = ppv[q];
+                }
+            }
+        }
         __syncthreads();
         const int nz0 = sRp[0];
         const int nzt = sRp[rows] - nz0;
@@ -145,17 +177,30 @@ void k_spmm(const int32_t* __restrict__ rowptr,
             for (int q = 0; q < V; ++q) acc[i][q] = 0.0;
         for (int cb = 0; cb < nzt; cb += NZC) {
             const int cn = min(NZC, nzt - cb);
-            for (int e = tid; e < cn; e += MB_BLOCK) {
-                // S >= 2: the CSR slice is not read again before a whole
-                // block-CG iteration has evicted it; non-temporal loads keep
-                // P in the last-level cache instead.  S = 1 (CG) moves so
-                // little per iteration that A itself may stay cached.
+            // S >= 2: the CSR slice is not read again before a whole
+            // block-CG iteration has evicted it; non-temporal loads keep P in
+            // the last-level cache instead.  S = 1 (CG) moves so little per
+            // iteration that A itself may stay cached.
+            int cc[CPT];
+            double cv[CPT];
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const int e = tid + q * MB_BLOCK;
+                const int64_t g = (int64_t)nz0 + cb + (e < cn ? e : 0);
                 if constexpr (S >= 2) {
-                    sC[e] = stream_load(colind + nz0 + cb + e);
-                    sV[e] = stream_load(vals + nz0 + cb + e);
+                    cc[q] = stream_load(colind + g);
+                    cv[q] = stream_load(vals + g);
                 } else {
-                    sC[e] = colind[nz0 + cb + e];
-                    sV[e] = vals[nz0 + cb + e];
+                    cc[q] = colind[g];
+                    cv[q] = vals[g];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const int e = tid + q * MB_BLOCK;
+                if (e < cn) {
+                    sC[e] = cc[q];
+                    sV[e] = cv[q];
                 }
             }
             __syncthreads();
