@@ -49,6 +49,10 @@ struct DevState {
     double nu[MB_SM];
     double chat[MB_SM + 1];
     int32_t active[MB_SM];
+    // 1 from the Xi tail of an iteration whose update runs until the next
+    // Xi tail: tells the direction update to apply that iteration's
+    // X~ += P alpha even when the QR tail has just stopped the loop
+    int32_t xt_pending, pad3;
 };
 
 __host__ __device__ constexpr int tri_count(int S) { return S * (S + 1) / 2; }

@@ -27,6 +27,13 @@ struct Tiles {
 template <int S>
 constexpr bool lazy_w() { return S <= 16; }
 
+// For S <= 16 the direction update also applies X~ += P alpha (the same sum
+// in the same order): it reads the P block anyway, so the update kernel need
+// not read it (one n x S block less per iteration).  At S = 32 the alpha
+// column would not fit the direction kernel's registers.
+template <int S>
+constexpr bool xt_in_dir() { return S <= 16; }
+
 // Row rl of a tile of M^-1 X for the block-Jacobi preconditioner with blocks
 // of BS rows: the tile starts at a multiple of BS (T is one), so the block of
 // row r0 + rl is the tile rows (rl / BS) * BS ..; sX holds the tile of X
@@ -43,13 +50,46 @@ __device__ __forceinline__ double bj_row(const double* __restrict__ inv, int64_t
     return y;
 }
 
+// The same for the RT rows rl0 + k*RPP of a thread (k < RT), into y[k]: the
+// inverse rows are loaded 4 entries at a time for every row before they are
+// used, so the rows' loads overlap (entries added in the same order as
+// bj_row; rows at or beyond `rows` read row r0 and are not used).
+template <int S, int BS, int RT, int RPP>
+__device__ __forceinline__ void bj_rows(const double* __restrict__ inv, int64_t r0, int rows,
+                                        const double* sX, int rl0, int j, double* y) {
+    static_assert(BS > 0 && Tiles<S>::T % BS == 0, "tiles must hold whole blocks");
+    constexpr int G = BS < 4 ? BS : 4;
+#pragma unroll
+    for (int k = 0; k < RT; ++k) y[k] = 0.0;
+    // a rolled loop over the groups, so that only one group's loads are in
+    // registers at a time
+#pragma unroll 1
+    for (int c0 = 0; c0 < BS; c0 += G) {
+        double iv[RT][G];
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int rl = rl0 + k * RPP;
+            const double* row = inv + (r0 + (rl < rows ? rl : 0)) * BS + c0;
+#pragma unroll
+            for (int c = 0; c < G; ++c) iv[k][c] = row[c];
+        }
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int b0 = ((rl0 + k * RPP) / BS) * BS;
+#pragma unroll
+            for (int c = 0; c < G; ++c) y[k] += iv[k][c] * sX[(b0 + c0 + c) * S + j];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K_B: X~ += P alpha, R -= Q alpha, the column norms behind h, and
 // V = W - Q Xi with the Gram V^T V (first half of the Cholesky QR).
 //   X~ += P alpha,  R -= Q alpha,  V = W - Q Xi  (V overwrites W),
 //   partial lower triangle of V^T V and nu_j = sum_r (d_r R_rj)^2.
 // With lazy_w, W = V_prev M_prev is formed here from the W buffer (which
-// holds the previous V) and the previous Cholesky-QR M.
+// holds the previous V) and the previous Cholesky-QR M.  With xt_in_dir the
+// X~ update is left to the direction kernel of the same iteration.
 // ---------------------------------------------------------------------------
 // BS > 0 (preconditioned form): also Y = M^-1 V into Yp, and the Gram is V^T Y.
 template <int S, int BS>
@@ -67,7 +107,8 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
     constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
     constexpr int E = tri_count(S);
     constexpr bool LW = lazy_w<S>();
-    __shared__ double sP[T * S];
+    constexpr bool XD = xt_in_dir<S>();   // X~ is updated by the direction kernel
+    __shared__ double sP[XD ? 1 : T * S];
     __shared__ double sQ[T * S];
     __shared__ double sV[T * S];
     __shared__ double sY[BS > 0 ? T * S : 1];
@@ -105,20 +146,26 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
         // thread's X~, R and d entries) is issued before the first LDS store
         constexpr int RT = T / RPP;   // rows per thread
         Stage<T * S> stp, stq, stw;
-        stp.load(P + r0 * S, rows * S);
+        if constexpr (!XD) stp.load(P + r0 * S, rows * S);
         stq.load(Q + r0 * S, rows * S);
         if constexpr (LW) stw.load(W + r0 * S, rows * S);   // the previous V
-        double xo[RT], ro[RT], wo[LW ? 1 : RT], dv[RT];
-#pragma unroll
-        for (int k = 0; k < RT; ++k) {
+        // (S = 32: the row entries are loaded where they are used, for the
+        // registers)
+        constexpr bool PF = S <= 16;
+        double xo[XD ? 1 : RT], ro[RT], wo[LW ? 1 : RT], dv[RT];
+        auto row_loads = [&](int k) {
             const int rl = rl0 + k * RPP;
             const int64_t g = (r0 + (rl < rows ? rl : 0)) * S + j;
-            xo[k] = stream_load(Xt + g);
+            if constexpr (!XD) xo[k] = stream_load(Xt + g);
             ro[k] = stream_load(R + g);
             if constexpr (!LW) wo[k] = W[g];
             dv[k] = d[r0 + (rl < rows ? rl : 0)];
+        };
+        if constexpr (PF) {
+#pragma unroll
+            for (int k = 0; k < RT; ++k) row_loads(k);
         }
-        stp.store(sP);
+        if constexpr (!XD) stp.store(sP);
         stq.store(sQ);
         if constexpr (LW) stw.store(sW);
         __syncthreads();
@@ -126,17 +173,17 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
         for (int k = 0; k < RT; ++k) {
             const int rl = rl0 + k * RPP;
             double v = 0.0;
+            if constexpr (!PF) row_loads(k);
             if (rl < rows) {
                 const int64_t g = (r0 + rl) * S + j;
                 double tx = 0.0, trr = 0.0, tv = 0.0;
 #pragma unroll
                 for (int l = 0; l < S; ++l) {
-                    const double p = sP[rl * S + l], q = sQ[rl * S + l];
-                    tx += p * al[l];
+                    const double q = sQ[rl * S + l];
+                    if constexpr (!XD) tx += sP[rl * S + l] * al[l];
                     trr += q * al[l];
                     tv += q * xi[l];
                 }
-                const double xn = xo[k] + tx;
                 const double rn = ro[k] - trr;
                 double w;
                 if constexpr (LW) {
@@ -147,7 +194,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
                     w = wo[k];
                 }
                 v = w - tv;
-                stream_store(Xt + g, xn);
+                if constexpr (!XD) stream_store(Xt + g, xo[k] + tx);
                 stream_store(R + g, rn);
                 W[g] = v;
                 const double dr = dv[k] * rn;
@@ -157,13 +204,13 @@ __global__ __launch_bounds__(MB_BLOCK) void k_update(int64_t n, const double* __
         }
         __syncthreads();
         if constexpr (BS > 0) {
-            for (int rl = rl0; rl < T; rl += RPP) {
-                double y = 0.0;
-                if (rl < rows) {
-                    y = bj_row<S, BS>(inv, r0 + rl, sV, rl, j);
-                    Yp[(r0 + rl) * S + j] = y;
-                }
-                sY[rl * S + j] = y;
+            double y[RT];
+            bj_rows<S, BS, RT, RPP>(inv, r0, rows, sV, rl0, j, y);
+#pragma unroll
+            for (int k = 0; k < RT; ++k) {
+                const int rl = rl0 + k * RPP;
+                if (rl < rows) Yp[(r0 + rl) * S + j] = y[k];
+                sY[rl * S + j] = rl < rows ? y[k] : 0.0;
             }
             __syncthreads();
         }
@@ -198,18 +245,26 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
                                                         double* __restrict__ P,
                                                         void* __restrict__ Plo,
                                                         const DevState* __restrict__ st,
-                                                        const double* __restrict__ Yp) {
-    if (st->done) return;
+                                                        const double* __restrict__ Yp,
+                                                        double* __restrict__ Xt) {
+    // XD: also X~ += P alpha of this iteration, from the P read here (P is
+    // still the block the update kernel's iteration used).  When the QR tail
+    // has just stopped the loop, only that X~ update is left to do.
+    constexpr bool XD = !FIRST && xt_in_dir<S>();
+    const int stop = st->done;
+    if (stop && !(XD && st->xt_pending)) return;
     constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
+    constexpr int RT = T / RPP;   // rows per thread
     __shared__ double sV[T * S];
     __shared__ double sP[T * S];
     __shared__ double sY[PREC ? T * S : 1];
     const int t = threadIdx.x, j = t % S, rl0 = t / S;
-    double m[S], z[S];
+    double m[S], z[S], al[XD ? S : 1];
 #pragma unroll
     for (int l = 0; l < S; ++l) {
         m[l] = st->M[l * MB_SM + j];
         z[l] = st->Z[j * MB_SM + l];
+        if constexpr (XD) al[l] = st->alpha[l * MB_SM + j];
     }
     const int64_t ntiles = (n + T - 1) / T;
     const TileRange tr = tile_range(ntiles);
@@ -218,14 +273,33 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
         const int rows = (int)min((int64_t)T, n - r0);
         // all loads of the tile before the first LDS store
         Stage<T * S> stv, stp, sty;
-        stv.load(W + r0 * S, rows * S);
+        if (!stop) stv.load(W + r0 * S, rows * S);
         if (!FIRST) stp.load(P + r0 * S, rows * S);
-        if (PREC) sty.load(Yp + r0 * S, rows * S);
-        stv.store(sV);
+        if (PREC && !stop) sty.load(Yp + r0 * S, rows * S);
+        double xo[XD ? RT : 1];
+        if constexpr (XD) {
+#pragma unroll
+            for (int k = 0; k < RT; ++k) {
+                const int rl = rl0 + k * RPP;
+                xo[k] = stream_load(Xt + (r0 + (rl < rows ? rl : 0)) * S + j);
+            }
+        }
+        if (!stop) stv.store(sV);
         if (!FIRST) stp.store(sP);
-        if (PREC) sty.store(sY);
+        if (PREC && !stop) sty.store(sY);
         __syncthreads();
-        for (int rl = rl0; rl < rows; rl += RPP) {
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int rl = rl0 + k * RPP;
+            if (rl >= rows) continue;
+            const int64_t g = (r0 + rl) * S + j;
+            if constexpr (XD) {
+                double tx = 0.0;
+#pragma unroll
+                for (int l = 0; l < S; ++l) tx += sP[rl * S + l] * al[l];
+                stream_store(Xt + g, xo[k] + tx);
+            }
+            if (stop) continue;
             double w = 0.0;
 #pragma unroll
             for (int l = 0; l < S; ++l) w += sV[rl * S + l] * m[l];
@@ -242,7 +316,6 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
                 for (int l = 0; l < S; ++l) acc += sP[rl * S + l] * z[l];
                 p = p + acc;
             }
-            const int64_t g = (r0 + rl) * S + j;
             if (!lazy_w<S>()) W[g] = w;
             P[g] = p;
             if (LO == DENSE_F32) static_cast<float*>(Plo)[lo_pindex(LO, r0 + rl, j, S)] = (float)p;
@@ -744,35 +817,37 @@ hipError_t launch_update(int S, int nwg, int64_t n, const double* P, const doubl
 
 template <int S, int FIRST>
 static hipError_t dirupdate_sf(int nwg, int64_t n, double* W, double* P, void* Plo, DenseKind lo,
-                               const DevState* st, hipStream_t stream, const double* Yp) {
+                               const DevState* st, hipStream_t stream, const double* Yp,
+                               double* Xt) {
     if (Yp) {
         if (lo != DENSE_F64) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_F64, 1>), dim3(nwg), dim3(MB_BLOCK), 0,
-                           stream, n, W, P, Plo, st, Yp);
+                           stream, n, W, P, Plo, st, Yp, Xt);
     } else if (lo == DENSE_F32) {
         hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_F32, 0>), dim3(nwg), dim3(MB_BLOCK), 0,
-                           stream, n, W, P, Plo, st, Yp);
+                           stream, n, W, P, Plo, st, Yp, Xt);
     } else if (lo == DENSE_BF16) {
         hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_BF16, 0>), dim3(nwg), dim3(MB_BLOCK), 0,
-                           stream, n, W, P, Plo, st, Yp);
+                           stream, n, W, P, Plo, st, Yp, Xt);
     } else {
         hipLaunchKernelGGL((k_dirupdate<S, FIRST, DENSE_F64, 0>), dim3(nwg), dim3(MB_BLOCK), 0,
-                           stream, n, W, P, Plo, st, Yp);
+                           stream, n, W, P, Plo, st, Yp, Xt);
     }
     return hipGetLastError();
 }
 
 template <int S>
 static hipError_t dirupdate_s(int nwg, int64_t n, double* W, double* P, void* Plo, DenseKind lo,
-                              int first, const DevState* st, hipStream_t stream, const double* Yp) {
-    return first ? dirupdate_sf<S, 1>(nwg, n, W, P, Plo, lo, st, stream, Yp)
-                 : dirupdate_sf<S, 0>(nwg, n, W, P, Plo, lo, st, stream, Yp);
+                              int first, const DevState* st, hipStream_t stream, const double* Yp,
+                              double* Xt) {
+    return first ? dirupdate_sf<S, 1>(nwg, n, W, P, Plo, lo, st, stream, Yp, Xt)
+                 : dirupdate_sf<S, 0>(nwg, n, W, P, Plo, lo, st, stream, Yp, Xt);
 }
 
 hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, void* Plo,
                             DenseKind lo_kind, int first, const DevState* st, hipStream_t stream,
-                            const double* Yp) {
-    MB_DISPATCH_S(S, return dirupdate_s<SS>(nwg, n, W, P, Plo, lo_kind, first, st, stream, Yp))
+                            const double* Yp, double* Xt) {
+    MB_DISPATCH_S(S, return dirupdate_s<SS>(nwg, n, W, P, Plo, lo_kind, first, st, stream, Yp, Xt))
 }
 
 hipError_t launch_rhs(int nwg, int64_t n, const double* b, const double* d, double* bbar,

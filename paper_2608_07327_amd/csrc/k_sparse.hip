@@ -113,46 +113,80 @@ void k_spmm(const int32_t* __restrict__ rowptr,
         }
     }
 
+    // Software pipeline over this workgroup's tiles: while a tile's gathers
+    // are in flight, the next tile's row pointers, P tile and CSR-slice
+    // bounds are loaded, and its first CSR chunk is loaded while the tile's
+    // Q rows are stored and its Gram is formed; every copy issues all of a
+    // thread's loads before its first LDS store (fixed per-thread counts,
+    // addresses clamped inside the arrays).
     const int64_t ntiles = (n + T - 1) / T;
     const TileRange tr = tile_range(ntiles);
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
-        const int64_t r0 = tile * T;
-        const int rows = (int)min((int64_t)T, n - r0);
-        const double* Pt = P + r0 * S;
-
-        // Every staging copy below issues all of a thread's loads before its
-        // first LDS store (fixed per-thread counts, addresses clamped inside
-        // the arrays), so each stage costs one memory round trip per tile.
-        double pr[REG ? NR : 1][S];    // register Gram: this lane's P rows
-        int rpv[RPT];
-        double ppv[REG ? 1 : PPT];
+    int rpv[RPT];                      // row pointers of the tile in flight
+    double ppv[REG ? 1 : PPT];         // its P tile (Gram operand)
+    int cc[CPT];                       // its first CSR chunk
+    double cv[CPT];
+    int h_nzb = 0, h_nze = 0;          // its CSR range
+    auto fetch_head = [&](int64_t tl) {
+        const int64_t q0 = tl * T;
+        const int qrows = (int)min((int64_t)T, n - q0);
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int e = tid + q * MB_BLOCK;
-            rpv[q] = rowptr[r0 + (e <= rows ? e : 0)];
+            rpv[q] = rowptr[q0 + (e <= qrows ? e : 0)];
         }
-        if (gram) {
-            if constexpr (REG) {
-#pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    const int rl = i * RPP + grp;
-                    if (rl < rows && slot == 0) {
-                        load_cols<S>(Pt + (int64_t)rl * S, pr[i]);
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < S; ++c) pr[i][c] = 0.0;
-                    }
-                }
-            } else {
+        if constexpr (!REG) {
+            if (gram) {
 #pragma unroll
                 for (int q = 0; q < PPT; ++q) {
                     const int e = tid + q * MB_BLOCK;
-                    const bool in = e < rows * S;
-                    const double v = Pt[in ? e : 0];
+                    const bool in = e < qrows * S;
+                    const double v = P[q0 * S + (in ? e : 0)];
                     ppv[q] = in ? v : 0.0;
                 }
             }
         }
+        h_nzb = rowptr[q0];
+        h_nze = rowptr[q0 + qrows];
+    };
+    // CSR entries [g0, g0 + cnt) into cc/cv; S >= 2: the CSR slice is not
+    // read again before a whole block-CG iteration has evicted it, and
+    // non-temporal loads keep P in the last-level cache instead (S = 1, CG,
+    // moves so little per iteration that A itself may stay cached)
+    auto fetch_csr = [&](int64_t g0, int cnt) {
+        if (cnt <= 0) return;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            const int64_t g = g0 + (e < cnt ? e : 0);
+            if constexpr (S >= 2) {
+                cc[q] = stream_load(colind + g);
+                cv[q] = stream_load(vals + g);
+            } else {
+                cc[q] = colind[g];
+                cv[q] = vals[g];
+            }
+        }
+    };
+    auto put_csr = [&](int cnt) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int e = tid + q * MB_BLOCK;
+            if (e < cnt) {
+                sC[e] = cc[q];
+                sV[e] = cv[q];
+            }
+        }
+    };
+    if (tr.first < tr.end) {
+        fetch_head(tr.first);
+        fetch_csr(h_nzb, min(NZC, h_nze - h_nzb));
+    }
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * T;
+        const int rows = (int)min((int64_t)T, n - r0);
+        const double* Pt = P + r0 * S;
+        const int nz0 = h_nzb;
+        const int nzt = h_nze - h_nzb;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int e = tid + q * MB_BLOCK;
@@ -167,9 +201,25 @@ void k_spmm(const int32_t* __restrict__ rowptr,
                 }
             }
         }
+        put_csr(min(NZC, nzt));
+        double pr[REG ? NR : 1][S];    // register Gram: this lane's P rows
         __syncthreads();
-        const int nz0 = sRp[0];
-        const int nzt = sRp[rows] - nz0;
+        const int64_t nxt = tile + tr.step;
+        if (nxt < tr.end) fetch_head(nxt);
+        if (gram) {
+            if constexpr (REG) {
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    const int rl = i * RPP + grp;
+                    if (rl < rows && slot == 0) {
+                        load_cols<S>(Pt + (int64_t)rl * S, pr[i]);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < S; ++c) pr[i][c] = 0.0;
+                    }
+                }
+            }
+        }
         double acc[NR][V];
 #pragma unroll
         for (int i = 0; i < NR; ++i)
@@ -177,33 +227,12 @@ void k_spmm(const int32_t* __restrict__ rowptr,
             for (int q = 0; q < V; ++q) acc[i][q] = 0.0;
         for (int cb = 0; cb < nzt; cb += NZC) {
             const int cn = min(NZC, nzt - cb);
-            // S >= 2: the CSR slice is not read again before a whole
-            // block-CG iteration has evicted it; non-temporal loads keep P in
-            // the last-level cache instead.  S = 1 (CG) moves so little per
-            // iteration that A itself may stay cached.
-            int cc[CPT];
-            double cv[CPT];
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                const int e = tid + q * MB_BLOCK;
-                const int64_t g = (int64_t)nz0 + cb + (e < cn ? e : 0);
-                if constexpr (S >= 2) {
-                    cc[q] = stream_load(colind + g);
-                    cv[q] = stream_load(vals + g);
-                } else {
-                    cc[q] = colind[g];
-                    cv[q] = vals[g];
-                }
+            if (cb > 0) {
+                // rows longer than the chunk: later chunks are loaded here
+                fetch_csr((int64_t)nz0 + cb, cn);
+                put_csr(cn);
+                __syncthreads();
             }
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                const int e = tid + q * MB_BLOCK;
-                if (e < cn) {
-                    sC[e] = cc[q];
-                    sV[e] = cv[q];
-                }
-            }
-            __syncthreads();
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 const int rl = i * RPP + grp;
@@ -233,6 +262,8 @@ void k_spmm(const int32_t* __restrict__ rowptr,
             }
             __syncthreads();
         }
+        // the next tile's first CSR chunk (its bounds came with its head)
+        if (nxt < tr.end) fetch_csr(h_nzb, min(NZC, h_nze - h_nzb));
 
 #pragma unroll
         for (int i = 0; i < NR; ++i) {

@@ -31,10 +31,16 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_part_reduce(const double* __re
 template <int S>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail_xi(const double* __restrict__ part, int nwg,
                                                           DevState* __restrict__ st) {
-    if (st->done) return;
+    if (st->done) {
+        if (threadIdx.x == 0) st->xt_pending = 0;
+        return;
+    }
     __shared__ double sm[SxsWs<S>::DOUBLES];
     __shared__ int smi[SxsWs<S>::INTS];
     tail_xi_body<S>(part, nwg, tri_count(S), st, sm, smi);
+    __syncthreads();
+    // the update runs unless this tail stopped the loop (P^T A P not SPD)
+    if (threadIdx.x == 0) st->xt_pending = st->done == 0;
 }
 
 template <int S>

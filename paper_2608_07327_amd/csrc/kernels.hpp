@@ -103,9 +103,11 @@ hipError_t launch_update(int S, int nwg, int64_t n, const double* P, const doubl
                          double* R, double* W, const double* d, double* part, const DevState* st,
                          hipStream_t stream, const BjArgs& bj = BjArgs());
 // With Yp (the preconditioned path, FP64 only): W = V M and P = Yp M + P Z^T.
+// Xt: X~, which the non-first direction update advances by P alpha for
+// S <= 16 (the update kernel does it at S = 32).
 hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, void* Plo,
                             DenseKind lo_kind, int first, const DevState* st, hipStream_t stream,
-                            const double* Yp = nullptr);
+                            const double* Yp, double* Xt);
 
 // ---- setup
 hipError_t launch_diag_csr(const CsrDev& A, int jacobi, double* d, DevState* st, hipStream_t s);

@@ -288,7 +288,7 @@ static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist,
     if ((e = launch_tail_qr(pl.S, pn, pr, c.st, hist, 0, c.stream)) != hipSuccess) return e;
     if ((e = mark(4)) != hipSuccess) return e;
     if ((e = launch_dirupdate(pl.S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, pl.kind, 0, c.st,
-                              c.stream, pl.bs ? c.Y : nullptr)) != hipSuccess)
+                              c.stream, pl.bs ? c.Y : nullptr, c.Xt)) != hipSuccess)
         return e;
     return mark(5);
 }
@@ -527,7 +527,7 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     CK(hipMemcpyAsync(c.W, c.R, sizeof(double) * (size_t)c.n * S, hipMemcpyDeviceToDevice,
                       c.stream));
     CK(launch_dirupdate(S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, kind, 1, c.st, c.stream,
-                        pl.bs ? c.Y : nullptr));
+                        pl.bs ? c.Y : nullptr, c.Xt));
     const double t_setup = now_ms();
 
     double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
@@ -898,7 +898,7 @@ mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out) {
     for (int k = 0; k < nsh; ++k) {
         const SpmmShape sh = shapes[k];
         const int64_t tiles = (c.n + sh.T - 1) / sh.T;
-        for (int w : {1024, 2048, 4096}) {
+        for (int w : {512, 1024, 2048, 4096}) {
             const int nwg = round_grid(std::min<int64_t>(tiles, w), NWG_MAX);
             if (w > 1024 && nwg < w) continue;  // already capped by the tile count
             CK(launch_spmm(S, sh, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
