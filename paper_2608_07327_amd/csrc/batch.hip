@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -71,6 +72,13 @@ struct BArgs {
     long long* tstamp;   // profile: steady-clock stamp after every grid barrier (or null)
 };
 
+// The batch's arguments, written by the host before each launch.  Device
+// code reads them from here (scalar loads at a fixed address) rather than
+// through a reference to the kernel argument, which the compiler kept in
+// per-lane scratch memory for the phase functions it does not inline.
+// One batched solve at a time per process (the host serialises them).
+__constant__ BArgs g_bargs;
+
 // ---------------------------------------------------------------------------
 // software grid barrier (sense by generation counter), bounded wait
 // ---------------------------------------------------------------------------
@@ -129,7 +137,8 @@ struct Item {
 };
 
 // block-product item (PT rows)
-__device__ __forceinline__ Item pitem_of(const BArgs& a, int it) {
+__device__ __forceinline__ Item pitem_of(int it) {
+    const BArgs& a = g_bargs;
     Item m;
     m.sys = a.pitem_sys[it];
     m.it = it;
@@ -139,7 +148,8 @@ __device__ __forceinline__ Item pitem_of(const BArgs& a, int it) {
     return m;
 }
 
-__device__ __forceinline__ Item item_of(const BArgs& a, int it) {
+__device__ __forceinline__ Item item_of(int it) {
+    const BArgs& a = g_bargs;
     Item m;
     m.sys = a.item_sys[it];
     m.it = it;
@@ -170,7 +180,8 @@ __device__ __forceinline__ Item item_of(const BArgs& a, int it) {
 // row phases (one item: item_rows(S) rows of one system)
 // ---------------------------------------------------------------------------
 // D = diag(sqrt(a_jj)) (Sec. 1), b~ = D^-1 b, partial ||b||^2 and ||b~||^2
-__device__ void ph_diag(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_diag(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     const BSys& y = a.sys[m.sys];
     DevState* st = a.st + m.sys;
     const int32_t* rp = a.rowptr + y.rp_off;
@@ -212,7 +223,8 @@ __device__ __forceinline__ uint64_t splitmix64_at_b(uint64_t seed, uint64_t k) {
 
 // scaled values a_rc / (d_r d_c) and the Uniform(-1,1) block U (Alg. 1, the random block U)
 template <int S>
-__device__ void ph_scale_u(const BArgs& a, const Item& m) {
+__device__ void ph_scale_u(const Item& m) {
+    const BArgs& a = g_bargs;
     const BSys& y = a.sys[m.sys];
     const int32_t* rp = a.rowptr + y.rp_off;
     const int32_t* ci = a.colind + y.nz_off;
@@ -241,8 +253,9 @@ __device__ void ph_scale_u(const BArgs& a, const Item& m) {
 // Q = A~ P for the tile (spmm_tile, CSR slice staged in LDS); optional
 // lower-triangle Gram P^T Q into part[0..E) and/or sum of Q^2 into part[2]
 template <int S, int SL>
-__device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double* Qb, bool gram,
+__device__ void ph_spmm(const Item& m, const double* Pb, double* Qb, bool gram,
                         bool qsq, double* sm) {
+    const BArgs& a = g_bargs;
     constexpr int E = tri_count(S);
     const BSys& y = a.sys[m.sys];
     const double* P = Pb + y.blk_off;
@@ -302,18 +315,20 @@ __device__ void ph_spmm(const BArgs& a, const Item& m, const double* Pb, double*
 }
 
 template <int S>
-__device__ void ph_spmm_dispatch(const BArgs& a, const Item& m, const double* P, double* Q,
+__device__ void ph_spmm_dispatch(const Item& m, const double* P, double* Q,
                                  bool gram, bool qsq, double* sm) {
+    const BArgs& a = g_bargs;
     if (a.sys[m.sys].SL == 2) {
-        if constexpr (S * 2 <= 64) ph_spmm<S, 2>(a, m, P, Q, gram, qsq, sm);
+        if constexpr (S * 2 <= 64) ph_spmm<S, 2>(m, P, Q, gram, qsq, sm);
     } else {
-        ph_spmm<S, 1>(a, m, P, Q, gram, qsq, sm);
+        ph_spmm<S, 1>(m, P, Q, gram, qsq, sm);
     }
 }
 
 // X0 = gamma U, X~ = 0, R = B~ - gamma Y; Gram of R and nu (setup QR partials)
 template <int S>
-__device__ void ph_init(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_init(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     constexpr int E = tri_count(S);
     const BSys& y = a.sys[m.sys];
     constexpr int TB = item_rows(S);   // rows per item
@@ -363,7 +378,8 @@ __device__ void ph_init(const BArgs& a, const Item& m, double* sm) {
 
 // X~ += P alpha, R -= Q alpha and V = W - Q Xi, with Gram of V and nu partials
 template <int S>
-__device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_update(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     constexpr int RPP = MB_BLOCK / S;
     constexpr int E = tri_count(S);
     const BSys& y = a.sys[m.sys];
@@ -381,15 +397,31 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
         xi[l] = st->Xi[l * MB_SM + j];
     }
     const int64_t base = y.blk_off + m.r0 * S;
-    for (int e = t; e < TB * S; e += MB_BLOCK) {
-        const bool in = e < m.rows * S;
-        sP[e] = in ? a.P[base + e] : 0.0;
-        sQ[e] = in ? a.Q[base + e] : 0.0;
-    }
-    __syncthreads();
     const double* d = a.d + y.vec_off + m.r0;
+    // every load of the item (P and Q tiles, this thread's X~, R, W and d
+    // entries) before the first LDS store: one memory round trip
+    constexpr int RT = TB / RPP;
+    Stage<TB * S> stp, stq;
+    stp.load(a.P + base, m.rows * S);
+    stq.load(a.Q + base, m.rows * S);
+    double xo[RT], ro[RT], wo[RT], dv[RT];
+#pragma unroll
+    for (int k = 0; k < RT; ++k) {
+        const int rl = rl0 + k * RPP;
+        const int rr = rl < m.rows ? rl : 0;
+        const int64_t g = base + rr * S + j;
+        xo[k] = a.Xt[g];
+        ro[k] = a.R[g];
+        wo[k] = a.W[g];
+        dv[k] = d[rr];
+    }
+    stp.store(sP);
+    stq.store(sQ);
+    __syncthreads();
     double nu = 0.0;
-    for (int rl = rl0; rl < TB; rl += RPP) {
+#pragma unroll
+    for (int k = 0; k < RT; ++k) {
+        const int rl = rl0 + k * RPP;
         double v = 0.0;
         if (rl < m.rows) {
             const int64_t g = base + rl * S + j;
@@ -401,16 +433,16 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
                 tr += q * al[l];
                 tv += q * xi[l];
             }
-            const double xn = a.Xt[g] + tx;
-            const double rn = a.R[g] - tr;
-            v = a.W[g] - tv;
+            const double xn = xo[k] + tx;
+            const double rn = ro[k] - tr;
+            v = wo[k] - tv;
             a.Xt[g] = xn;
             a.R[g] = rn;
             a.W[g] = v;
-            const double dr = d[rl] * rn;
+            const double dr = dv[k] * rn;
             nu += dr * dr;
         }
-        if (rl < TB) sV[rl * S + j] = v;
+        sV[rl * S + j] = v;
     }
     __syncthreads();
     TileSums<E> gs;
@@ -433,7 +465,8 @@ __device__ void ph_update(const BArgs& a, const Item& m, double* sm) {
 
 // W = V M, P = W + P Z^T (FIRST: P = W, V read from R)
 template <int S, int FIRST>
-__device__ void ph_dir(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_dir(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     constexpr int RPP = MB_BLOCK / S;
     const BSys& y = a.sys[m.sys];
     constexpr int TB = item_rows(S);   // rows per item
@@ -449,11 +482,11 @@ __device__ void ph_dir(const BArgs& a, const Item& m, double* sm) {
     }
     const int64_t base = y.blk_off + m.r0 * S;
     const double* V = FIRST ? a.R : a.W;
-    for (int e = t; e < TB * S; e += MB_BLOCK) {
-        const bool in = e < m.rows * S;
-        sV[e] = in ? V[base + e] : 0.0;
-        if (!FIRST) sP[e] = in ? a.P[base + e] : 0.0;
-    }
+    Stage<TB * S> stv, stp;   // all loads before the LDS stores
+    stv.load(V + base, m.rows * S);
+    if (!FIRST) stp.load(a.P + base, m.rows * S);
+    stv.store(sV);
+    if (!FIRST) stp.store(sP);
     __syncthreads();
     for (int rl = rl0; rl < m.rows; rl += RPP) {
         double w = 0.0;
@@ -474,7 +507,8 @@ __device__ void ph_dir(const BArgs& a, const Item& m, double* sm) {
 
 // Gram of [b, D R] for the least-squares termination
 template <int S>
-__device__ void ph_ls_gram(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_ls_gram(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     constexpr int NC = S + 1;
     constexpr int E = tri_count(NC);
     const BSys& y = a.sys[m.sys];
@@ -507,7 +541,8 @@ __device__ void ph_ls_gram(const BArgs& a, const Item& m, double* sm) {
 
 // x = D^-1 (X~ + X0) c, r = y0 b + (D R) c, partial ||r||^2 into part[0]
 template <int S>
-__device__ void ph_ls_apply(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_ls_apply(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     const BSys& y = a.sys[m.sys];
     const DevState* st = a.st + m.sys;
     const int64_t base = y.blk_off + m.r0 * S;
@@ -538,7 +573,8 @@ __device__ void ph_ls_apply(const BArgs& a, const Item& m, double* sm) {
 
 // best column when the combination was not accepted; x = 0 for b = 0
 template <int S>
-__device__ void ph_select(const BArgs& a, const Item& m) {
+__device__ void ph_select(const Item& m) {
+    const BArgs& a = g_bargs;
     const BSys& y = a.sys[m.sys];
     const DevState* st = a.st + m.sys;
     double* x = a.x + y.vec_off + m.r0;
@@ -555,7 +591,8 @@ __device__ void ph_select(const BArgs& a, const Item& m) {
 }
 
 // ||b - A x||^2 partial on the original values into part[1]
-__device__ void ph_resid(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_resid(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     const BSys& y = a.sys[m.sys];
     const int32_t* rp = a.rowptr + y.rp_off;
     const int32_t* ci = a.colind + y.nz_off;
@@ -578,7 +615,8 @@ __device__ void ph_resid(const BArgs& a, const Item& m, double* sm) {
 // ||b - A x_h||^2 partial into part[2], x_h = D^-1 (X~ + X0)_h read from the
 // blocks (the best column, when the accepted combination misses the tolerance)
 template <int S>
-__device__ void ph_resid_best(const BArgs& a, const Item& m, double* sm) {
+__device__ void ph_resid_best(const Item& m, double* sm) {
+    const BArgs& a = g_bargs;
     const BSys& y = a.sys[m.sys];
     const int32_t* rp = a.rowptr + y.rp_off;
     const int32_t* ci = a.colind + y.nz_off;
@@ -616,14 +654,16 @@ __device__ inline bool was_picked(const DevState* st) {
 }
 
 // sum of ppart[slot] over a system's block-product items (fixed order)
-__device__ double sys_psum(const BArgs& a, const BSys& y, int slot, double* sm) {
+__device__ double sys_psum(const BSys& y, int slot, double* sm) {
+    const BArgs& a = g_bargs;
     reduce_partials(a.ppart + (int64_t)y.pitem_off * PSTRIDE + slot, y.pntile, 1, PSTRIDE, sm,
                     sm + 8);
     return sm[0];
 }
 
 // sum of part[slot] over a system's items (fixed order), result to thread 0
-__device__ double sys_sum(const BArgs& a, const BSys& y, int slot, double* sm) {
+__device__ double sys_sum(const BSys& y, int slot, double* sm) {
+    const BArgs& a = g_bargs;
     reduce_partials(a.part + (int64_t)y.item_off * PSTRIDE + slot, y.ntile, 1, PSTRIDE, sm,
                     sm + 8);
     return sm[0];
@@ -632,7 +672,9 @@ __device__ double sys_sum(const BArgs& a, const BSys& y, int slot, double* sm) {
 // ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
+// one body for every phase: the register cap (168) keeps three waves per SIMD
+__global__ __launch_bounds__(MB_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_batch() {
+    const BArgs& a = g_bargs;
     __shared__ double sm[BSM];
     __shared__ int smi[48];
     int* flag = smi + 40;
@@ -650,29 +692,29 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     // --- setup: scaling, b~, ||b||
     // (the CSR row phases take the 128-row block-product items)
     FOR_PITEMS {
-        const Item m = pitem_of(a, it_);
-        ph_diag(a, m, sm);
+        const Item m = pitem_of(it_);
+        ph_diag(m, sm);
     }
     SYNC_OR_QUIT
     FOR_PITEMS {
-        const Item m = pitem_of(a, it_);
-        DISPATCH_S(a.sys[m.sys].S, ph_scale_u<SS>(a, m))
+        const Item m = pitem_of(it_);
+        DISPATCH_S(a.sys[m.sys].S, ph_scale_u<SS>(m))
     }
     SYNC_OR_QUIT
     // initial guess: Y = A~ U and ||Y||_F^2
     FOR_PITEMS {
-        const Item m = pitem_of(a, it_);
-        DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(a, m, a.U, a.Y, false, true, sm))
+        const Item m = pitem_of(it_);
+        DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(m, a.U, a.Y, false, true, sm))
     }
     SYNC_OR_QUIT
     FOR_SYS {
         const BSys& y = a.sys[sy_];
         DevState* st = a.st + sy_;
-        const double sb = sys_psum(a, y, 0, sm);
+        const double sb = sys_psum(y, 0, sm);
         __syncthreads();
-        const double sbb = sys_psum(a, y, 1, sm);
+        const double sbb = sys_psum(y, 1, sm);
         __syncthreads();
-        const double sy = sys_psum(a, y, 2, sm);
+        const double sy = sys_psum(y, 2, sm);
         if (threadIdx.x == 0) {
             const double bn = sqrt(sb);
             st->bnorm = bn;
@@ -690,9 +732,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     SYNC_OR_QUIT
     // scaled right-hand sides, R0 and the partials of the first QR
     FOR_ITEMS {
-        const Item m = item_of(a, it_);
+        const Item m = item_of(it_);
         if (a.st[m.sys].done) continue;
-        DISPATCH_S(a.sys[m.sys].S, ph_init<SS>(a, m, sm))
+        DISPATCH_S(a.sys[m.sys].S, ph_init<SS>(m, sm))
     }
     SYNC_OR_QUIT
     FOR_SYS {
@@ -705,9 +747,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     }
     SYNC_OR_QUIT
     FOR_ITEMS {
-        const Item m = item_of(a, it_);
+        const Item m = item_of(it_);
         if (a.st[m.sys].done) continue;
-        DISPATCH_S(a.sys[m.sys].S, (ph_dir<SS, 1>(a, m, sm)))
+        DISPATCH_S(a.sys[m.sys].S, (ph_dir<SS, 1>(m, sm)))
     }
     FOR_SYS {
         if (threadIdx.x == 0 && !a.st[sy_].done)
@@ -718,9 +760,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     // --- the iteration loop (Xi to the new Sigma) for every active system
     for (int loop = 0; loop <= a.max_iter + 1; ++loop) {
         FOR_PITEMS {
-            const Item m = pitem_of(a, it_);
+            const Item m = pitem_of(it_);
             if (a.st[m.sys].done) continue;
-            DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(a, m, a.P, a.Q, true, false, sm))
+            DISPATCH_S(a.sys[m.sys].S, ph_spmm_dispatch<SS>(m, a.P, a.Q, true, false, sm))
         }
         SYNC_OR_QUIT
         FOR_SYS {
@@ -736,9 +778,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         }
         SYNC_OR_QUIT
         FOR_ITEMS {
-            const Item m = item_of(a, it_);
+            const Item m = item_of(it_);
             if (a.st[m.sys].done) continue;
-            DISPATCH_S(a.sys[m.sys].S, ph_update<SS>(a, m, sm))
+            DISPATCH_S(a.sys[m.sys].S, ph_update<SS>(m, sm))
         }
         SYNC_OR_QUIT
         FOR_SYS {
@@ -761,9 +803,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
         __syncthreads();
         if (still <= 0) break;
         FOR_ITEMS {
-            const Item m = item_of(a, it_);
+            const Item m = item_of(it_);
             if (a.st[m.sys].done) continue;
-            DISPATCH_S(a.sys[m.sys].S, (ph_dir<SS, 0>(a, m, sm)))
+            DISPATCH_S(a.sys[m.sys].S, (ph_dir<SS, 0>(m, sm)))
         }
         SYNC_OR_QUIT
         if (blockIdx.x == 0 && threadIdx.x == 0) ctl->loops = loop + 1;
@@ -771,9 +813,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
 
     // --- termination (least-squares combination)
     FOR_ITEMS {
-        const Item m = item_of(a, it_);
+        const Item m = item_of(it_);
         if (a.st[m.sys].done != DONE_CONVERGED) continue;
-        DISPATCH_S(a.sys[m.sys].S, ph_ls_gram<SS>(a, m, sm))
+        DISPATCH_S(a.sys[m.sys].S, ph_ls_gram<SS>(m, sm))
     }
     SYNC_OR_QUIT
     FOR_SYS {
@@ -786,9 +828,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     }
     SYNC_OR_QUIT
     FOR_ITEMS {
-        const Item m = item_of(a, it_);
+        const Item m = item_of(it_);
         if (a.st[m.sys].done != DONE_CONVERGED) continue;
-        DISPATCH_S(a.sys[m.sys].S, ph_ls_apply<SS>(a, m, sm))
+        DISPATCH_S(a.sys[m.sys].S, ph_ls_apply<SS>(m, sm))
     }
     SYNC_OR_QUIT
     FOR_SYS {
@@ -798,7 +840,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
             if (threadIdx.x == 0) st->accepted = 0;
             continue;
         }
-        const double s2 = sys_sum(a, y, 0, sm);
+        const double s2 = sys_sum(y, 0, sm);
         if (threadIdx.x == 0) {
             const double rel = sqrt(s2) / st->bnorm;
             st->rel_ls = rel;
@@ -808,34 +850,34 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     }
     SYNC_OR_QUIT
     FOR_ITEMS {
-        const Item m = item_of(a, it_);
-        DISPATCH_S(a.sys[m.sys].S, ph_select<SS>(a, m))
+        const Item m = item_of(it_);
+        DISPATCH_S(a.sys[m.sys].S, ph_select<SS>(m))
     }
     SYNC_OR_QUIT
     FOR_PITEMS {
-        const Item m = pitem_of(a, it_);
-        ph_resid(a, m, sm);
+        const Item m = pitem_of(it_);
+        ph_resid(m, sm);
     }
     SYNC_OR_QUIT
     FOR_SYS {
         const BSys& y = a.sys[sy_];
         DevState* st = a.st + sy_;
-        const double s2 = sys_psum(a, y, 1, sm);
+        const double s2 = sys_psum(y, 1, sm);
         if (threadIdx.x == 0) st->rel_true = st->done == DONE_ZERO_RHS ? 0.0 : sqrt(s2) / st->bnorm;
         __syncthreads();
     }
     SYNC_OR_QUIT
     FOR_PITEMS {
-        const Item m = pitem_of(a, it_);
+        const Item m = pitem_of(it_);
         if (!needs_pick(a.st + m.sys)) continue;
-        DISPATCH_S(a.sys[m.sys].S, ph_resid_best<SS>(a, m, sm))
+        DISPATCH_S(a.sys[m.sys].S, ph_resid_best<SS>(m, sm))
     }
     SYNC_OR_QUIT
     FOR_SYS {
         const BSys& y = a.sys[sy_];
         DevState* st = a.st + sy_;
         if (!needs_pick(st)) continue;
-        const double s2 = sys_psum(a, y, 2, sm);
+        const double s2 = sys_psum(y, 2, sm);
         if (threadIdx.x == 0) {
             const double rel_h = sqrt(s2) / st->bnorm;
             if (rel_h < st->rel_true) {
@@ -847,9 +889,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_batch(BArgs a) {
     }
     SYNC_OR_QUIT
     FOR_ITEMS {
-        const Item m = item_of(a, it_);
+        const Item m = item_of(it_);
         if (!was_picked(a.st + m.sys)) continue;
-        DISPATCH_S(a.sys[m.sys].S, ph_select<SS>(a, m))
+        DISPATCH_S(a.sys[m.sys].S, ph_select<SS>(m))
     }
     stamp();
 #undef SYNC_OR_QUIT
@@ -918,6 +960,10 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
             return _e == hipErrorOutOfMemory ? MBPCG_ERR_OOM : MBPCG_ERR_HIP;  \
         }                                                                      \
     } while (0)
+    // the kernel reads its arguments from one device symbol (g_bargs): one
+    // batched solve at a time in this process
+    static std::mutex batch_mu;
+    std::lock_guard<std::mutex> batch_lock(batch_mu);
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<BSys> hs(nsys);
     std::vector<int32_t> item_sys, pitem_sys;
@@ -1072,9 +1118,11 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     // one persistent kernel, captured in a graph and launched once
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    BCK(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_bargs), &a, sizeof(BArgs), 0, hipMemcpyHostToDevice,
+                               stream));
     BCK(hipStreamSynchronize(stream));
     BCK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(MB_BLOCK), 0, stream, a);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(MB_BLOCK), 0, stream);
     hipError_t le = hipGetLastError();
     hipError_t ce = hipStreamEndCapture(stream, &graph);
     if (le != hipSuccess || ce != hipSuccess) {
