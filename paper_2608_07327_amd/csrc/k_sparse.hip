@@ -398,6 +398,23 @@ SpmmShape spmm_default_shape(int S) {
 
 int spmm_lanes_per_row(int S, const SpmmShape& sh) { return S / sh.V * sh.SL; }
 
+int spmm_blocks_per_cu(int S, const SpmmShape& sh) {
+    int per_cu = 0;
+    any_shape(
+        [&](auto b) {
+            using B = decltype(b);
+            if (!shape_is(b, S, sh)) return false;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm<B>, MB_BLOCK, 0) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                per_cu = 0;
+            }
+            return true;
+        },
+        (BpShapes*)nullptr);
+    return per_cu;
+}
+
 hipError_t launch_spmm(int S, const SpmmShape& sh, int nwg, const CsrDev& A, const double* P,
                        double* Q, double* part, const DevState* st, hipStream_t stream) {
     hipError_t err = hipErrorInvalidValue;

@@ -44,6 +44,8 @@ bool spmm_valid_shape(int S, const SpmmShape& sh);
 int spmm_shape_list(int S, SpmmShape* out, int cap);
 SpmmShape spmm_default_shape(int S);
 int spmm_lanes_per_row(int S, const SpmmShape& sh);
+// workgroups of the shape's block-product kernel that fit on one CU (0 on error)
+int spmm_blocks_per_cu(int S, const SpmmShape& sh);
 
 // ---- dense product: Q partials over KSPLIT column ranges, then reduce + Gram
 enum DenseKind { DENSE_F64 = 0, DENSE_F32 = 1, DENSE_BF16 = 2 };

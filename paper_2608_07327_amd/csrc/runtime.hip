@@ -895,10 +895,16 @@ mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out) {
     CK(hipMemsetAsync(flush, 0, flush_bytes, c.stream));
     SpmmShape shapes[64];
     const int nsh = spmm_shape_list(S, shapes, 64);
+    int dev = 0, cus = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     for (int k = 0; k < nsh; ++k) {
         const SpmmShape sh = shapes[k];
         const int64_t tiles = (c.n + sh.T - 1) / sh.T;
-        for (int w : {512, 1024, 2048, 4096}) {
+        // fixed grids, and the one that fills every CU to the shape's occupancy
+        const int resident = spmm_blocks_per_cu(S, sh) * cus;
+        for (int w : {512, 1024, 2048, 4096, resident}) {
+            if (w <= 0) continue;
             const int nwg = round_grid(std::min<int64_t>(tiles, w), NWG_MAX);
             if (w > 1024 && nwg < w) continue;  // already capped by the tile count
             CK(launch_spmm(S, sh, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
