@@ -137,6 +137,11 @@ def main():
     ap.add_argument("--shift", type=float, default=1e-3,
                     help="dense workloads: the shift of G G^T / n + shift I (1e-3 as configured; "
                          "smaller is harder for CG)")
+    ap.add_argument("--inclusions", type=int, default=0,
+                    help="diffusion3d: that many highly conducting cubic inclusions (a few "
+                         "isolated small eigenvalues: harder for CG), 0 as configured")
+    ap.add_argument("--contrast", type=float, default=1e4,
+                    help="diffusion3d with --inclusions: coefficient factor inside them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sweep", action="store_true")
@@ -169,7 +174,8 @@ def bench_sparse(args):
 
     pois = args.workload == "poisson2d"
     cfg = W.CFG_POISSON2D if pois else W.CFG_DIFFUSION3D
-    A = W.poisson2d(64) if pois else W.diffusion3d(args.grid)
+    A = W.poisson2d(64) if pois else W.diffusion3d(args.grid, inclusions=args.inclusions,
+                                                   contrast=args.contrast)
     b = W.rhs(A.n, cfg)
     s = args.s
     S = 1
@@ -294,7 +300,8 @@ def bench_sparse(args):
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A, b, s, seed, it, args.cpu_seconds, "64^2 Poisson" if pois else
-                           f"{args.grid}^3 diffusion")
+                           f"{args.grid}^3 diffusion"
+                           + (f" with {args.inclusions} inclusions" if args.inclusions else ""))
 
     out = {
         "metric": "time-to-solution at rel.res 1e-8 (MBPCG; plain CG on the same GPU beside it)",
@@ -312,8 +319,10 @@ def bench_sparse(args):
         "config": {
             "workload": (f"poisson2d 64^2 5-point, b~N(0,1), Jacobi scaling, tol 1e-8, MBPCG s={s} "
                          "(L2-resident: latency-bound, no meaningful HBM roofline)") if pois else
-                        f"diffusion3d {args.grid}^3 7-point, lognormal(sigma=1) coefficients, "
-                        f"b~N(0,1), Jacobi scaling, tol 1e-8, MBPCG s={s}",
+                        f"diffusion3d {args.grid}^3 7-point, lognormal(sigma=1) coefficients"
+                        + (f" with {args.inclusions} 4^3 inclusions x{args.contrast:g}"
+                           if args.inclusions else "")
+                        + f", b~N(0,1), Jacobi scaling, tol 1e-8, MBPCG s={s}",
             "n": A.n, "nnz": A.nnz, "s": s,
         },
         "iterations": it,

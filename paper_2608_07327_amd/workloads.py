@@ -16,7 +16,9 @@ headline configurations):
 * ``poisson2d(64)``            2-D 5-point Dirichlet Poisson, n = 4096.
 * ``diffusion3d(128)``         3-D 7-point variable-coefficient diffusion,
                                 log-normal(sigma=1) cell coefficients,
-                                harmonic-mean face weights, n = 2,097,152.
+                                harmonic-mean face weights, n = 2,097,152;
+                                optionally with highly conducting cubic
+                                inclusions (a few isolated small eigenvalues).
 * ``dense_spd(8192)``          A = G G^T / n + 1e-3 I, G iid N(0,1).
 * ``graph_laplacian_batch``    random-graph Laplacians (average degree 8)
                                 plus 1e-2 I, n log-uniform in [1e3, 2e5].
@@ -100,7 +102,8 @@ def poisson2d(m: int = 64) -> CSR:
     return _stencil_csr(n, cols, vals, valid)
 
 
-def diffusion3d(m: int = 128, sigma: float = 1.0, tag=CFG_DIFFUSION3D) -> CSR:
+def diffusion3d(m: int = 128, sigma: float = 1.0, tag=CFG_DIFFUSION3D, inclusions: int = 0,
+                contrast: float = 1e4, size: int = 4) -> CSR:
     """Cell-centred 7-point finite-volume diffusion on an m^3 grid with iid
     log-normal cell coefficients kappa_c = exp(sigma * g_c), g_c ~ N(0,1).
 
@@ -108,7 +111,15 @@ def diffusion3d(m: int = 128, sigma: float = 1.0, tag=CFG_DIFFUSION3D) -> CSR:
     Dirichlet boundary face (half-cell distance): 2 kappa_c.
     A_cc = sum of the cell's face weights, A_cc' = -w(c, c').
     Lexicographic order with x fastest, so every row's columns ascend as
-    (-z, -y, -x, self, +x, +y, +z)."""
+    (-z, -y, -x, self, +x, +y, +z).
+
+    inclusions > 0: that many size^3 cubes of cells (corners drawn uniformly
+    in [1, m - size - 1] per axis from a stream of their own, so the other
+    coefficients do not change) have kappa multiplied by `contrast`.  Highly
+    conducting inclusions give the scaled operator one small eigenvalue per
+    inclusion, well separated from the rest of the spectrum: the case where
+    CG needs many iterations and a block of s >= inclusions columns does
+    not."""
     rng = rng_for(tag)
     n = m ** 3
     g = rng.standard_normal(n)
@@ -117,6 +128,15 @@ def diffusion3d(m: int = 128, sigma: float = 1.0, tag=CFG_DIFFUSION3D) -> CSR:
     x = idx % m
     y = (idx // m) % m
     z = idx // (m * m)
+    if inclusions > 0:
+        if not 1 <= size <= m - 2:
+            raise ValueError("inclusion size must lie in [1, m - 2]")
+        ri = rng_for((CFG_DIFFUSION3D, 77, m, inclusions, size))
+        for _ in range(inclusions):
+            c = ri.integers(1, m - size, 3)        # corner, in [1, m - size - 1]
+            inside = ((x >= c[0]) & (x < c[0] + size) & (y >= c[1]) & (y < c[1] + size)
+                      & (z >= c[2]) & (z < c[2] + size))
+            kap[inside] *= contrast
     strides = [m * m, m, 1]
     coords = [z, y, x]
     cols = np.empty((n, 7), dtype=np.int64)

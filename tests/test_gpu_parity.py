@@ -258,6 +258,15 @@ def test_dense_against_oracle(s):
     check_against_oracle(A, b, s, jacobi=False, seed=W.uniform_block_seed(3, s))
 
 
+@pytest.mark.parametrize("s", [1, 4, 8])
+def test_diffusion_with_inclusions_against_oracle(s):
+    # highly conducting inclusions: a few isolated small eigenvalues of the
+    # scaled operator (CG 158 iterations at n = 4096, s = 8 about 70)
+    A = W.diffusion3d(16, inclusions=6, contrast=1e4, size=3)
+    b = W.rhs(A.n, 81)
+    check_against_oracle(A, b, s, seed=W.uniform_block_seed(81, s))
+
+
 @pytest.mark.parametrize("kind", ["dense", "csr"])
 @pytest.mark.parametrize("s", [2, 4, 8])
 def test_near_singular_systems_meet_tol_on_the_true_residual(kind, s):

@@ -110,3 +110,36 @@ def test_tiny_spd_has_the_requested_spectrum(cond):
     ev = np.linalg.eigvalsh(A)
     assert np.array_equal(A, A.T)
     assert np.allclose(ev, np.geomspace(1.0, cond, 12), rtol=1e-10)
+
+
+def test_diffusion3d_inclusions_scale_the_cube_coefficients():
+    m, k, size, contrast = 10, 3, 3, 1e4
+    A0 = W.diffusion3d(m)
+    A1 = W.diffusion3d(m, inclusions=k, contrast=contrast, size=size)
+    # same sparsity, same coefficients outside the inclusions' neighbourhoods
+    assert np.array_equal(A0.rowptr, A1.rowptr) and np.array_equal(A0.colind, A1.colind)
+    D0, D1 = _dense(A0), _dense(A1)
+    assert np.array_equal(D1, D1.T)
+    assert np.linalg.eigvalsh(D1).min() > 0.0
+    # rebuild the cells' coefficients the generator draws and check every
+    # changed entry touches an inclusion cell
+    n = m ** 3
+    idx = np.arange(n)
+    x, y, z = idx % m, (idx // m) % m, idx // (m * m)
+    inside = np.zeros(n, dtype=bool)
+    ri = W.rng_for((W.CFG_DIFFUSION3D, 77, m, k, size))
+    for _ in range(k):
+        c = ri.integers(1, m - size, 3)
+        assert np.all(c >= 1) and np.all(c + size <= m - 1)
+        inside |= ((x >= c[0]) & (x < c[0] + size) & (y >= c[1]) & (y < c[1] + size)
+                   & (z >= c[2]) & (z < c[2] + size))
+    assert size ** 3 <= inside.sum() <= k * size ** 3
+    changed = np.argwhere(D0 != D1)
+    assert len(changed) > 0
+    # only rows of inclusion cells and of their neighbours change
+    near = inside | ((D0 != 0).astype(int) @ inside.astype(int) > 0)
+    assert np.all(near[changed[:, 0]]) and np.all(near[changed[:, 1]])
+    # an interior inclusion cell's diagonal grows by about the contrast
+    cell = np.flatnonzero(inside & (x > 0) & (x < m - 1) & (y > 0) & (y < m - 1)
+                          & (z > 0) & (z < m - 1))
+    assert D1[cell, cell].max() > 10.0 * D0[cell, cell].max()
