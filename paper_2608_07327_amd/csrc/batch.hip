@@ -41,10 +41,13 @@ struct BSys {
     int32_t s, S, SL, ntile, item_off, pntile, pitem_off, pad;
 };
 
+constexpr int BAR_GROUPS = 8;   // first-level arrival counters of the grid barrier
+
 struct BCtl {
     unsigned bar_count, bar_gen;
     int abort, active;
     int loops, pad0, pad1, pad2;
+    unsigned sub[BAR_GROUPS * 32];   // group g's arrival counter at sub[32 g] (own 128-byte line)
 };
 
 struct BArgs {
@@ -86,14 +89,30 @@ __device__ bool grid_sync(BCtl* ctl, long long spin_limit, int* flag) {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
+        // two levels of arrival: workgroup b counts on its group's counter
+        // (g = b mod groups), the group's last arriver on the top counter,
+        // and the last group releases everyone by bumping the generation;
+        // the atomics on one address are serialised, so the chain is about
+        // nb / 8 + 8 long instead of nb
         const unsigned nb = gridDim.x;
+        const unsigned groups = nb < (unsigned)BAR_GROUPS ? nb : (unsigned)BAR_GROUPS;
+        const unsigned g = blockIdx.x % groups;
+        const unsigned ng = (nb - g + groups - 1) / groups;   // workgroups of group g
         const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nb - 1) {
-            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        bool last = false;
+        const unsigned a1 =
+            __hip_atomic_fetch_add(&ctl->sub[32 * g], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (a1 == ng - 1) {
+            __hip_atomic_store(&ctl->sub[32 * g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned a2 =
+                __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (a2 == groups - 1) {
+                __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (!last) {
             long long spins = 0;
             while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(8);
