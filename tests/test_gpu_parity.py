@@ -515,6 +515,31 @@ def test_nonpositive_diagonal():
     solver.close()
 
 
+@pytest.mark.parametrize("kind", ["tridiagonal", "shifted_poisson"])
+@pytest.mark.parametrize("s", [1, 2, 4])
+def test_indefinite_matrix_stops_not_spd_with_the_best_column(kind, s):
+    # positive diagonals, indefinite matrices: tridiagonal (1, -0.9) with 156
+    # of 500 eigenvalues negative, where P^T A P fails at the first step; the
+    # 16 x 16 Poisson matrix minus 0.1 I with one negative eigenvalue, where
+    # it fails after a dozen steps.  The failing step's update never runs;
+    # the best column of the iterate so far is returned.
+    import scipy.sparse as sp
+    if kind == "tridiagonal":
+        n = 500
+        T = sp.diags([-0.9 * np.ones(n - 1), np.ones(n), -0.9 * np.ones(n - 1)], [-1, 0, 1])
+    else:
+        P = W.poisson2d(16)
+        n = P.n
+        T = sp.csr_matrix((P.vals, P.colind, P.rowptr), shape=(n, n)) - 0.1 * sp.identity(n)
+    T = T.tocsr()
+    T.sort_indices()
+    A = W.CSR(n, T.indptr.astype(np.int32), T.indices.astype(np.int32), T.data.astype(np.float64))
+    b = W.rhs(n, 5)
+    x, info, xo, io = check_against_oracle(A, b, s, seed=3)
+    assert io["status"] == M.ERR_NOT_SPD and info["status"] == M.ERR_NOT_SPD
+    assert info["used_fallback"] == 1 and info["iterations"] == io["iterations"]
+
+
 def test_max_iter_returns_best_column():
     A = W.diffusion3d(12)
     b = W.rhs(A.n, 5)
