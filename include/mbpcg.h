@@ -200,7 +200,10 @@ typedef struct {
 
 /* Solve nsys independent sparse systems (uneven n and s) together in one
  * persistent launch per graph replay.  common->s is ignored; each system uses
- * its own s.  per_system[nsys] receives each system's info. */
+ * its own s.  per_system[nsys] receives each system's info.  The call returns
+ * when the batch has finished; concurrent calls from several threads of one
+ * process run one after the other (the kernel's arguments live in one
+ * device symbol). */
 mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
                                const mbpcg_params* common, mbpcg_info* per_system,
                                mbpcg_mem mem, void* hip_stream);
