@@ -850,6 +850,41 @@ hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, voi
     MB_DISPATCH_S(S, return dirupdate_s<SS>(nwg, n, W, P, Plo, lo_kind, first, st, stream, Yp, Xt))
 }
 
+// workgroups of the FP64 update / direction kernels (no preconditioner) that
+// fit on one CU; 0 on error or an unknown width
+static int occ_of(const void* fn) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, MB_BLOCK, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu;
+}
+
+int update_blocks_per_cu(int S) {
+    switch (S) {
+        case 1: return occ_of((const void*)k_update<1, 0>);
+        case 2: return occ_of((const void*)k_update<2, 0>);
+        case 4: return occ_of((const void*)k_update<4, 0>);
+        case 8: return occ_of((const void*)k_update<8, 0>);
+        case 16: return occ_of((const void*)k_update<16, 0>);
+        case 32: return occ_of((const void*)k_update<32, 0>);
+    }
+    return 0;
+}
+
+int dirupdate_blocks_per_cu(int S) {
+    switch (S) {
+        case 1: return occ_of((const void*)k_dirupdate<1, 0, DENSE_F64, 0>);
+        case 2: return occ_of((const void*)k_dirupdate<2, 0, DENSE_F64, 0>);
+        case 4: return occ_of((const void*)k_dirupdate<4, 0, DENSE_F64, 0>);
+        case 8: return occ_of((const void*)k_dirupdate<8, 0, DENSE_F64, 0>);
+        case 16: return occ_of((const void*)k_dirupdate<16, 0, DENSE_F64, 0>);
+        case 32: return occ_of((const void*)k_dirupdate<32, 0, DENSE_F64, 0>);
+    }
+    return 0;
+}
+
 hipError_t launch_rhs(int nwg, int64_t n, const double* b, const double* d, double* bbar,
                       double* part, hipStream_t s) {
     hipLaunchKernelGGL(k_rhs, dim3(nwg), dim3(MB_BLOCK), 0, s, n, b, d, bbar, part);

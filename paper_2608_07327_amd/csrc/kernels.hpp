@@ -111,6 +111,10 @@ hipError_t launch_dirupdate(int S, int nwg, int64_t n, double* W, double* P, voi
                             DenseKind lo_kind, int first, const DevState* st, hipStream_t stream,
                             const double* Yp, double* Xt);
 
+// workgroups of k_update<S, 0> / k_dirupdate<S, 0, DENSE_F64, 0> per CU (0 on error)
+int update_blocks_per_cu(int S);
+int dirupdate_blocks_per_cu(int S);
+
 // ---- setup
 hipError_t launch_diag_csr(const CsrDev& A, int jacobi, double* d, DevState* st, hipStream_t s);
 hipError_t launch_diag_dense(int64_t n, const double* A, int64_t lda, int jacobi, double* d,

@@ -82,6 +82,7 @@ static void drop_graphs(Ctx& c) {
 
 mbpcg_status ctx_init_common(Ctx& c, hipStream_t user_stream) {
     CK(hipGetDevice(&c.device));
+    CK(hipDeviceGetAttribute(&c.cus, hipDeviceAttributeMultiprocessorCount, c.device));
     c.user_stream = user_stream;
     CK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     CK(hipEventCreateWithFlags(&c.ev_poll[0], hipEventDisableTiming));
@@ -175,6 +176,13 @@ static Plan make_plan(Ctx& c, int s, DenseKind kind) {
     const int64_t upd_tiles = (c.n + Tu - 1) / Tu;
     pl.nwg_upd = round_grid(upd_tiles, cap);
     pl.nwg_dir = round_grid(upd_tiles, 1024);
+    if (S <= 8 && c.cus > 0) {
+        // widths whose partials stay small: fill every CU to the kernels'
+        // occupancy (one wave of resident workgroups)
+        const int ou = update_blocks_per_cu(S), od = dirupdate_blocks_per_cu(S);
+        if (ou > 0) pl.nwg_upd = round_grid(upd_tiles, std::min(ou * c.cus, NWG_MAX));
+        if (od > 0) pl.nwg_dir = round_grid(upd_tiles, std::min(od * c.cus, NWG_MAX));
+    }
     pl.nwg_ls = round_grid((c.n + 63) / 64, cap);
     pl.nwg_e = round_grid((c.n + MB_BLOCK - 1) / MB_BLOCK, 1024);
     if (c.dense) {

@@ -29,6 +29,7 @@ struct Ctx {
     int dense = 0;
     int64_t n = 0, nnz = 0;
     int device = 0;
+    int cus = 0;                   // compute units of the device
     hipStream_t user_stream = nullptr;
     hipStream_t stream = nullptr;  // private, non-blocking
     std::string err;
