@@ -301,16 +301,42 @@ struct GramMfma {
 };
 
 // Sum of part[w * stride + e] for w in [w0, w1): eight interleaved
-// accumulators (eight loads in flight), combined in a fixed tree.
+// accumulators (partial w0 + i goes to accumulator i mod 8, the last
+// (w1 - w0) mod 8 to accumulators 0, 1, ...), combined in a fixed tree;
+// up to 32 loads in flight.
 __device__ __forceinline__ double sum_strided(const double* __restrict__ part, int w0, int w1,
                                               int stride, int e) {
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int w = w0;
+    // runs of 32 and then 16 partials issue all their loads before adding
+    // them (same additions in the same order as the runs of 8)
+    for (; w + 32 <= w1; w += 32) {
+        double v[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) v[u] = part[(int64_t)(w + u) * stride + e];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) a[u % 8] += v[u];
+    }
+    if (w + 16 <= w1) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(w + u) * stride + e];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u % 8] += v[u];
+        w += 16;
+    }
     for (; w + 8 <= w1; w += 8) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] += part[(int64_t)(w + u) * stride + e];
     }
-    for (int u = 0; w < w1; ++w, ++u) a[u] += part[(int64_t)w * stride + e];
+    // the last w1 - w < 8 partials go to a[0], a[1], ... (loads first)
+    const int r = w1 - w;
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = u < r ? part[(int64_t)(w + u) * stride + e] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (u < r) a[u] += v[u];
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 

@@ -295,24 +295,44 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit
     for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
         const int64_t r0 = tile * T;
         const int rows = (int)min((int64_t)T, n - r0);
-        for (int e = t; e < T * S; e += MB_BLOCK) {
-            double q = 0.0, p = 0.0;
-            if (e < rows * S) {
-                const int64_t g = r0 * S + e;
-                // four loads in flight, combined in a fixed order
-                double q4[4] = {0.0, 0.0, 0.0, 0.0};
-                int k = 0;
-                for (; k + 4 <= ksplit; k += 4) {
+        // each thread's EPT entries: four running sums per entry (partial k
+        // goes to sum k mod 4), combined in a fixed order; the loads of all
+        // entries and of four partials are issued together
+        constexpr int EPT = (T * S + MB_BLOCK - 1) / MB_BLOCK;
+        double q4[EPT][4], pv[EPT];
+        int64_t gq[EPT];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) q4[u] += qpart[(k + u) * nS + g];
-                }
-                for (int u = 0; k < ksplit; ++k, ++u) q4[u] += qpart[k * nS + g];
-                q = (q4[0] + q4[1]) + (q4[2] + q4[3]);
-                p = P[g];
-                Q[g] = q;
-            }
-            sQ[e] = q;
-            sP[e] = p;
+        for (int q = 0; q < EPT; ++q) {
+            const int e = t + q * MB_BLOCK;
+            gq[q] = r0 * S + (e < rows * S ? e : 0);
+            pv[q] = P[gq[q]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q4[q][u] = 0.0;
+        }
+        int k = 0;
+        for (; k + 4 <= ksplit; k += 4) {
+            double v[EPT][4];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[q][u] = qpart[(k + u) * nS + gq[q]];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q4[q][u] += v[q][u];
+        }
+        for (int u = 0; k < ksplit; ++k, ++u)
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) q4[q][u] += qpart[k * nS + gq[q]];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = t + q * MB_BLOCK;
+            if (e >= T * S) continue;
+            const bool in = e < rows * S;
+            const double qv = (q4[q][0] + q4[q][1]) + (q4[q][2] + q4[q][3]);
+            if (in) Q[gq[q]] = qv;
+            sQ[e] = in ? qv : 0.0;
+            sP[e] = in ? pv[q] : 0.0;
         }
         __syncthreads();
         if (part) {
