@@ -917,12 +917,14 @@ mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out) {
             if (w > 1024 && nwg < w) continue;  // already capped by the tile count
             CK(launch_spmm(S, sh, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
             // In a solve the product follows kernels that stream far more
-            // than the 256 MB last-level cache through it, so each timed
-            // launch is preceded by a copy of 2 x 320 MB and timed alone;
-            // the median of 9 such launches counts.
+            // than the 256 MB last-level cache through it, the last of which
+            // has just written P; so each timed launch is preceded by a copy
+            // of 2 x 320 MB and by a write of the whole P block, and timed
+            // alone; the median of 9 such launches counts.
             float t[9];
             for (int r = 0; r < 9; ++r) {
                 CK(launch_stream_copy(flush + flush_bytes / 2, flush, flush_bytes / 2, c.stream));
+                CK(launch_stream_copy(c.P, c.W, (int64_t)sizeof(double) * c.n * S, c.stream));
                 CK(hipEventRecord(c.ev_a, c.stream));
                 CK(launch_spmm(S, sh, nwg, csr_of(c, true), c.P, c.Q, c.part_a, c.st, c.stream));
                 CK(hipEventRecord(c.ev_b, c.stream));
