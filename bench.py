@@ -26,6 +26,9 @@ Other workloads (--workload), each printing its own JSON line:
   batch        512 random-graph Laplacians (avg degree 8, + 1e-2 I, n
                log-uniform in [1e3, 2e5], s in {1,4,8}) in one persistent
                launch, against the same systems solved one after another
+Harder variants: --shift 1e-5 for the dense workloads (CG needs many
+iterations relative to n), --inclusions K [--contrast C] for diffusion3d
+(K highly conducting 4^3 cubes: a few isolated small eigenvalues).
 """
 from __future__ import annotations
 
