@@ -362,17 +362,11 @@ def bench_sparse(args):
 
 
 def dense_on_device(n, tag, torch, dev, shift):
-    """workloads.dense_spd's recipe with the n^3 product done on the GPU: G iid
-    N(0,1) from the same seeded stream, A = G G^T / n with the lower triangle
-    mirrored (bitwise symmetric), + shift I.  Input generation only."""
+    """workloads.dense_spd with the n^3 product done on the GPU (input
+    generation only; the product is exact, so the bytes equal the CPU
+    construction's)."""
     from paper_2608_07327_amd import workloads as W
-    g = torch.as_tensor(W.rng_for(tag).standard_normal((n, n)), device=dev)
-    a = torch.mm(g, g.t().contiguous())
-    del g
-    a /= n
-    a = torch.tril(a)
-    a = a + torch.tril(a, -1).t()
-    a.diagonal().add_(shift)
+    a = W.dense_spd_torch(n, tag, shift, device=dev)
     torch.cuda.synchronize()
     return a
 

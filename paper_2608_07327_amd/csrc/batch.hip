@@ -31,7 +31,8 @@ constexpr int ITEM_ELEMS = 1024;
 // gathers do best spread over many small items), with partial sums of their
 // own
 constexpr int PT = 128;
-constexpr int PSTRIDE = 48;    // doubles of partial sums per item
+constexpr int PSTRIDE = 96;    // doubles of partial sums per item (the double-double
+                               // Gram of the least squares at S = 8: 2 x 45)
 constexpr int BATCH_TERM_BARRIERS = 9;  // grid barriers of the termination
 constexpr int BSM = 4096;    // LDS doubles of the persistent kernel (32 KB)
 static_assert(SxsWs<8>::DOUBLES <= BSM, "s x s workspace of the widest batched system");
@@ -524,43 +525,51 @@ __device__ void ph_dir(const Item& m, double* sm) {
     __syncthreads();
 }
 
-// Gram of [b, D R] for the least-squares termination
+// double-double Gram of [B^, b] for the least-squares termination,
+// B^ = B - D R formed entry by entry as b_r - (d_r R_rj); columns j >= s zero
 template <int S>
 __device__ void ph_ls_gram(const Item& m, double* sm) {
     const BArgs& a = g_bargs;
     constexpr int NC = S + 1;
     constexpr int E = tri_count(NC);
+    static_assert(2 * E <= PSTRIDE, "least-squares partials per item");
     const BSys& y = a.sys[m.sys];
     constexpr int TB = item_rows(S);   // rows per item
     double* sM = sm;
     double* red = sm + TB * NC;
+    static_assert(TB * NC + 2 * MB_BLOCK <= BSM, "batched LDS");
     const int t = threadIdx.x;
+    const int s = y.s;
     const int64_t base = y.blk_off + m.r0 * S;
     const double* d = a.d + y.vec_off + m.r0;
     const double* b = a.b + y.vec_off + m.r0;
     for (int e = t; e < TB * S; e += MB_BLOCK) {
         const int rl = e / S, j = e % S;
-        sM[rl * NC + 1 + j] = rl < m.rows ? d[rl] * a.R[base + e] : 0.0;
+        sM[rl * NC + j] = (rl < m.rows && j < s) ? bhat_entry(b[rl], d[rl], a.R[base + e]) : 0.0;
     }
-    for (int rl = t; rl < TB; rl += MB_BLOCK) sM[rl * NC] = rl < m.rows ? b[rl] : 0.0;
+    for (int rl = t; rl < TB; rl += MB_BLOCK) sM[rl * NC + S] = rl < m.rows ? b[rl] : 0.0;
     __syncthreads();
-    TileSums<E> gs;
+    TileSumsDD<E> gs;
     gs.init();
-    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+    int gi[TileSumsDD<E>::EPT], gj[TileSumsDD<E>::EPT];
 #pragma unroll
-    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+    for (int k = 0; k < TileSumsDD<E>::EPT; ++k) {
         gi[k] = gj[k] = 0;
         if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
     }
-    gs.add_rows(m.rows, [&](int k, int r) { return sM[r * NC + gi[k]] * sM[r * NC + gj[k]]; });
+    gs.add_rows(m.rows, [&](int k, int r) {
+        return make_double2(sM[r * NC + gi[k]], sM[r * NC + gj[k]]);
+    });
     const int64_t it = m.it;
     gs.finish(red, a.part + it * PSTRIDE);
     __syncthreads();
 }
 
-// x = D^-1 (X~ + X0) c, r = y0 b + (D R) c, partial ||r||^2 into part[0]
+// x = D^-1 (X~ + X0) c^, r = b - B^ c^ (sums over the columns in column
+// order, rounded as written), partial ||r||^2 into part[0]
 template <int S>
 __device__ void ph_ls_apply(const Item& m, double* sm) {
+#pragma clang fp contract(off)
     const BArgs& a = g_bargs;
     const BSys& y = a.sys[m.sys];
     const DevState* st = a.st + m.sys;
@@ -568,21 +577,23 @@ __device__ void ph_ls_apply(const Item& m, double* sm) {
     const double* d = a.d + y.vec_off + m.r0;
     const double* b = a.b + y.vec_off + m.r0;
     double* x = a.x + y.vec_off + m.r0;
+    const int s = y.s;
     double c[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) c[j] = st->chat[j];
-    const double y0 = st->y0;
     double s2 = 0.0;
     for (int rl = threadIdx.x; rl < m.rows; rl += MB_BLOCK) {
-        double ax = 0.0, ar = 0.0;
-        const double dr = d[rl];
+        double ax = 0.0, ab = 0.0;
+        const double dr = d[rl], br = b[rl];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            ax += (a.Xt[base + rl * S + j] + a.X0[base + rl * S + j]) * c[j];
-            ar += (dr * a.R[base + rl * S + j]) * c[j];
+            if (j < s) {
+                ax += (a.Xt[base + rl * S + j] + a.X0[base + rl * S + j]) * c[j];
+                ab += bhat_entry(br, dr, a.R[base + rl * S + j]) * c[j];
+            }
         }
         x[rl] = ax / dr;
-        const double res = y0 * b[rl] + ar;
+        const double res = br - ab;
         s2 += res * res;
     }
     const int64_t it = m.it;
@@ -777,7 +788,7 @@ __global__ __launch_bounds__(MB_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
     SYNC_OR_QUIT
 
     // --- the iteration loop (Xi to the new Sigma) for every active system
-    for (int loop = 0; loop <= a.max_iter + 1; ++loop) {
+    for (int64_t loop = 0; loop <= (int64_t)a.max_iter + 1; ++loop) {
         FOR_PITEMS {
             const Item m = pitem_of(it_);
             if (a.st[m.sys].done) continue;
@@ -827,7 +838,7 @@ __global__ __launch_bounds__(MB_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
             DISPATCH_S(a.sys[m.sys].S, (ph_dir<SS, 0>(m, sm)))
         }
         SYNC_OR_QUIT
-        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->loops = loop + 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->loops = (int)(loop + 1);
     }
 
     // --- termination (least-squares combination)
@@ -842,7 +853,7 @@ __global__ __launch_bounds__(MB_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
         DevState* st = a.st + sy_;
         if (st->done != DONE_CONVERGED) continue;
         DISPATCH_S(y.S, tail_ls_body<SS>(a.part + (int64_t)y.item_off * PSTRIDE, y.ntile, PSTRIDE,
-                                         st, sm, smi))
+                                         y.n, st, sm, smi))
         __syncthreads();
     }
     SYNC_OR_QUIT

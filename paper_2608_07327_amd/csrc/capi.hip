@@ -280,7 +280,20 @@ mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
     if (!(common->tol > 0.0) || !std::isfinite(common->tol) || common->max_iter < 1 ||
         common->max_iter > (int64_t)INT32_MAX)
         return MBPCG_ERR_INVALID_ARG;
+    if (common->precond != MBPCG_PRECOND_NONE && common->precond != MBPCG_PRECOND_JACOBI &&
+        common->precond != MBPCG_PRECOND_BLOCK_JACOBI)
+        return MBPCG_ERR_INVALID_ARG;
+    if (!std::isfinite(common->tol_initial) || !std::isfinite(common->tau))
+        return MBPCG_ERR_INVALID_ARG;
+    if (common->precision != MBPCG_FP64 && common->precision != MBPCG_FP32_IR &&
+        common->precision != MBPCG_BF16_IR)
+        return MBPCG_ERR_INVALID_ARG;
+    // the batched kernel runs the FP64 method with diagonal scaling or none,
+    // and the paper's setting of equal tolerances
     if (common->precond == MBPCG_PRECOND_BLOCK_JACOBI) return MBPCG_ERR_UNSUPPORTED;
+    if (common->precision != MBPCG_FP64) return MBPCG_ERR_UNSUPPORTED;
+    if (common->tol_initial > 0.0 && common->tol_initial != common->tol)
+        return MBPCG_ERR_UNSUPPORTED;
     for (int32_t i = 0; i < nsys; ++i) {
         const mbpcg_system& y = systems[i];
         if (y.n < 1 || y.n >= (int64_t)INT32_MAX || y.nnz < 0 || y.nnz >= (int64_t)INT32_MAX)

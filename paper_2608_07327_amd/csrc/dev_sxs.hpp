@@ -6,6 +6,7 @@
 // stages separated by barriers; thread i owns row (or column) i.
 #pragma once
 #include "dev_common.hpp"
+#include "dev_dd.hpp"
 
 namespace mb {
 
@@ -151,9 +152,10 @@ template <int S>
 struct SxsWs {
     static constexpr int XI = 2 * RedWs<tri_count(S)>::N + 4 * S * S;
     static constexpr int QR = 2 * RedWs<tri_count(S) + S>::N + 5 * S * S;
-    static constexpr int LS = 2 * RedWs<tri_count(S + 1)>::N + 2 * (S + 1) * (S + 1) + 2 * (S + 1);
+    static constexpr int LS = 2 * tri_count(S + 1) + 2 * TAIL_THREADS + 2 * (S + 1) * (S + 1) +
+                              2 * (S + 1);
     static constexpr int DOUBLES = XI > QR ? (XI > LS ? XI : LS) : (QR > LS ? QR : LS);
-    static constexpr int INTS = S + 8;
+    static constexpr int INTS = S + 8;   // >= S + 2 for the least squares
 };
 
 // ---------------------------------------------------------------------------
@@ -357,89 +359,108 @@ __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride
 }
 
 // ---------------------------------------------------------------------------
-// Least squares of the termination (the combination c^).  Columns m_0 = b,
-// m_{j+1} = D R_j; K = M^T M (lower triangle from partials).  Minimise
-// ||M y|| subject to sum y = 1: with Delta = diag(||m_i||), K~ = Delta^-1 K
-// Delta^-1 and w = Delta^-1 1, y = Delta^-1 z / (w^T z) where K~ z = w,
-// solved by Cholesky over the independent columns (same dropping rule as
-// the Cholesky QR).  c_j = y_{j+1}.  Since b - B^ c = (1 - sum c) b + D R c,
-// this is the minimiser of ||b - B^ c||.
+// Least squares of the termination (Alg. 1, the combination c^ of the
+// columns of B^ = B - D R, which equals A X by Proposition 1):
+// c^ = argmin ||b - B^ c||.  The partials hold the double-double Gram of
+// [B^_0 .. B^_{S-1}, b] (columns j >= s zero).  It is factored G = U^T U
+// column by column in double-double, leaving out column j when its part
+// independent of the columns kept before it is not above 1e-12 of its norm
+// (pivot delta_j <= 1e-24 G_jj), when its norm is zero, or when n columns are
+// kept already; a left-out column gets coefficient 0.  This is the basic
+// solution that Householder QR of B^ with the same rule gives: in exact
+// arithmetic the pivots are the squared norms of the independent parts.
+// The Gram in double-double (about 106 bits) keeps the independent parts,
+// which are about |R| / |b| of a column's norm, well resolved although the
+// Gram squares the condition number of B^.  The last column's entries of U
+// are z = U_JJ^-T B^_J^T b, and U_JJ c_J = z.
 // ---------------------------------------------------------------------------
 template <int S>
-__device__ void tail_ls_body(const double* __restrict__ part, int nwg, int stride,
+__device__ void tail_ls_body(const double* __restrict__ part, int nwg, int stride, int64_t n,
                              DevState* __restrict__ st, double* sm, int* smi) {
     constexpr int NC = S + 1;
     constexpr int E = tri_count(NC);
-    constexpr int RN = RedWs<E>::N;
-    double* red = sm;
-    double* tmp = sm + RN;
-    double* K = sm + 2 * RN;
-    double* Lk = K + NC * NC;
-    double* dn = Lk + NC * NC;
-    double* z = dn + NC;
-    int* keep = smi;
+    double* ghi = sm;
+    double* glo = sm + E;
+    double* tmp = sm + 2 * E;                       // 2 * blockDim doubles
+    double* uhi = sm + 2 * E + 2 * TAIL_THREADS;    // U, row l at [l * NC]
+    double* ulo = uhi + NC * NC;
+    double* chi = ulo + NC * NC;                    // c^ (double-double)
+    double* clo = chi + NC;
+    int* keep = smi;                                // [S]
+    int* flags = smi + S;                           // [0] kept, [1] ok
     const int t = threadIdx.x;
-    reduce_partials(part, nwg, E, stride, red, tmp);
-    if (t < NC) dn[t] = sqrt(red[t * (t + 1) / 2 + t]);
-    __syncthreads();
-    for (int e = t; e < NC * NC; e += blockDim.x) {
-        const int i = e / NC, j = e % NC;
-        const int a = i >= j ? i : j, b = i >= j ? j : i;
-        const double den = dn[i] * dn[j];
-        K[e] = den > 0.0 ? red[a * (a + 1) / 2 + b] / den : 0.0;
-        Lk[e] = 0.0;
-    }
-    __syncthreads();
-    for (int l = 0; l < NC; ++l) {
-        if (t == 0) {
-            const double g = K[l * NC + l];
-            double dl = g;
-            for (int q = 0; q < l; ++q)
-                if (keep[q]) dl -= Lk[l * NC + q] * Lk[l * NC + q];
-            const int k = (dn[l] > 0.0) && (g > 0.0) && finite_d(dl) && (dl > st->tau * g);
-            keep[l] = k;
-            Lk[l * NC + l] = k ? sqrt(dl) : 1.0;
+    reduce_partials_dd(part, nwg, E, stride, ghi, glo, tmp);
+    const int s = st->s;
+    if (t < 64) {
+        const int i = t < NC ? t : NC - 1;   // lanes past the last row mirror it (discarded)
+        dd w[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int a = i >= k ? i : k, b = i >= k ? k : i;
+            w[k] = dd{ghi[a * (a + 1) / 2 + b], glo[a * (a + 1) / 2 + b]};
         }
-        __syncthreads();
-        if (keep[l] && t > l && t < NC) {
-            double v = K[t * NC + l];
-            for (int q = 0; q < l; ++q)
-                if (keep[q]) v -= Lk[t * NC + q] * Lk[l * NC + q];
-            Lk[t * NC + l] = v / Lk[l * NC + l];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        // forward L y = w, backward L^T z = y (kept columns only); y in z's slot first
         int kept = 0;
-        for (int i = 0; i < NC; ++i) {
-            z[i] = 0.0;
-            if (!keep[i]) continue;
-            ++kept;
-            double v = 1.0 / dn[i];
-            for (int q = 0; q < i; ++q)
-                if (keep[q]) v -= Lk[i * NC + q] * z[q];
-            z[i] = v / Lk[i * NC + i];
+        bool ok = true;
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            const double g = ghi[l * (l + 1) / 2 + l];   // squared norm of column l
+            const dd dl = lane_bcast_dd(w[l], l);        // pivot left by the kept columns
+            if (l < s && !finite_d(g)) ok = false;
+            const bool k = l < s && g > 0.0 && finite_d(g) && dd_finite(dl) &&
+                           dl.hi > 1e-24 * g && kept < n;   // wave-uniform
+            if (k) {
+                const dd ull = dd_sqrt(dl);
+                dd ci{0.0, 0.0};
+                if (i == l) ci = ull;
+                else if (i > l) ci = dd_div(w[l], ull);
+                if (t < NC) {
+                    uhi[l * NC + i] = ci.hi;
+                    ulo[l * NC + i] = ci.lo;
+                }
+#pragma unroll
+                for (int q = l + 1; q < NC; ++q) w[q] = dd_sub(w[q], dd_mul(ci, lane_bcast_dd(ci, q)));
+                ++kept;
+            }
+            if (t == 0) keep[l] = k ? 1 : 0;
         }
-        for (int i = NC - 1; i >= 0; --i) {
-            if (!keep[i]) continue;
-            double v = z[i];
-            for (int q = i + 1; q < NC; ++q)
-                if (keep[q]) v -= Lk[q * NC + i] * z[q];
-            z[i] = v / Lk[i * NC + i];
+        if (t == 0) {
+            flags[0] = kept;
+            flags[1] = ok ? 1 : 0;
         }
-        double wz = 0.0;
-        for (int i = 0; i < NC; ++i)
-            if (keep[i]) wz += z[i] / dn[i];
-        bool ok = wz > 0.0 && finite_d(wz);
-        for (int i = 0; i < NC; ++i) {
-            const double yi = keep[i] ? (z[i] / wz) / dn[i] : 0.0;
-            if (!finite_d(yi)) ok = false;
-            if (i == 0) st->y0 = yi;
-            else st->chat[i - 1] = yi;
+    }
+    __syncthreads();
+    // back substitution U_JJ c_J = z over the kept columns: lane l holds the
+    // running right-hand side of row l, c_q reaches the other lanes by readlane
+    if (t < 64) {
+        const int l = t < S ? t : S - 1;
+        const bool mine = t < S && keep[l];
+        dd acc = mine ? dd{uhi[l * NC + S], ulo[l * NC + S]} : dd{0.0, 0.0};
+        dd cl{0.0, 0.0};
+#pragma unroll
+        for (int q = S - 1; q >= 0; --q) {
+            if (!keep[q]) continue;   // wave-uniform
+            dd cq{0.0, 0.0};
+            if (t == q) cq = dd_div(acc, dd{uhi[q * NC + q], ulo[q * NC + q]});
+            cq = lane_bcast_dd(cq, q);
+            if (t == q) cl = cq;
+            if (mine && l < q) acc = dd_sub(acc, dd_mul(dd{uhi[l * NC + q], ulo[l * NC + q]}, cq));
         }
+        if (t < S) {
+            chi[t] = cl.hi;
+            clo[t] = cl.lo;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        bool ok = flags[1] && flags[0] > 0;
+        for (int j = 0; j < S; ++j) {
+            const double cj = keep[j] ? dd_to_double(dd{chi[j], clo[j]}) : 0.0;
+            if (!finite_d(cj)) ok = false;
+            st->chat[j] = cj;
+        }
+        st->y0 = 0.0;
         st->ls_ok = ok ? 1 : 0;
-        st->ls_width = kept;
+        st->ls_width = flags[0];
     }
     __syncthreads();
 }

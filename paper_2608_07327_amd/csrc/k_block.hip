@@ -7,6 +7,7 @@
 // the element-wise blocks (X~, R, W) are read and written in place with the
 // same linear layout.  Each thread owns one column j of the tile, which keeps
 // the column j of the s x s coefficients in registers for the whole kernel.
+#include "dev_dd.hpp"
 #include "kernels.hpp"
 
 #include <hip/hip_bf16.h>
@@ -498,10 +499,9 @@ __global__ __launch_bounds__(MB_BLOCK) void k_gram_nu(int64_t n, const double* _
 }
 
 // ---------------------------------------------------------------------------
-// Termination (least-squares combination of Alg. 1, Proposition 1).  The least-squares problem
-// min_c ||b - B^ c|| with B^ = B - D R is solved in the equivalent form
-// min ||y0 b + (D R) c|| subject to y0 + sum c = 1, whose FP64 Gram over the
-// columns [b, D R] is formed here (one pass over R).
+// Termination (least-squares combination of Alg. 1, Proposition 1): the
+// double-double Gram of [B^, b] with B^ = B - D R formed entry by entry as
+// b_r - (d_r R_rj) (one pass over R); columns j >= s are zero.
 // ---------------------------------------------------------------------------
 template <int S>
 __global__ __launch_bounds__(MB_BLOCK) void k_ls_gram(int64_t n, const double* __restrict__ b,
@@ -513,13 +513,14 @@ __global__ __launch_bounds__(MB_BLOCK) void k_ls_gram(int64_t n, const double* _
     constexpr int T = 64;
     constexpr int E = tri_count(NC);
     __shared__ double sM[T * NC];
-    __shared__ double red[MB_BLOCK];
+    __shared__ double red[2 * MB_BLOCK];
     const int t = threadIdx.x;
-    TileSums<E> gs;
+    const int s = st->s;
+    TileSumsDD<E> gs;
     gs.init();
-    int gi[TileSums<E>::EPT], gj[TileSums<E>::EPT];
+    int gi[TileSumsDD<E>::EPT], gj[TileSumsDD<E>::EPT];
 #pragma unroll
-    for (int k = 0; k < TileSums<E>::EPT; ++k) {
+    for (int k = 0; k < TileSumsDD<E>::EPT; ++k) {
         gi[k] = gj[k] = 0;
         if (gs.ent[k] >= 0) tri_ij(gs.ent[k], gi[k], gj[k]);
     }
@@ -530,17 +531,21 @@ __global__ __launch_bounds__(MB_BLOCK) void k_ls_gram(int64_t n, const double* _
         const int rows = (int)min((int64_t)T, n - r0);
         for (int e = t; e < T * S; e += MB_BLOCK) {
             const int rl = e / S, j = e % S;
-            sM[rl * NC + 1 + j] = rl < rows ? d[r0 + rl] * R[r0 * S + e] : 0.0;
+            sM[rl * NC + j] = (rl < rows && j < s) ? bhat_entry(b[r0 + rl], d[r0 + rl], R[r0 * S + e])
+                                                   : 0.0;
         }
-        for (int rl = t; rl < T; rl += MB_BLOCK) sM[rl * NC] = rl < rows ? b[r0 + rl] : 0.0;
+        for (int rl = t; rl < T; rl += MB_BLOCK) sM[rl * NC + S] = rl < rows ? b[r0 + rl] : 0.0;
         __syncthreads();
-        gs.add_rows(rows, [&](int k, int r) { return sM[r * NC + gi[k]] * sM[r * NC + gj[k]]; });
+        gs.add_rows(rows, [&](int k, int r) {
+            return make_double2(sM[r * NC + gi[k]], sM[r * NC + gj[k]]);
+        });
         __syncthreads();
     }
-    gs.finish(red, part + (int64_t)blockIdx.x * E);
+    gs.finish(red, part + (int64_t)blockIdx.x * 2 * E);
 }
 
-// x = D^-1 (X~ + X0) c;  r = y0 b + (D R) c  (= b - B^ c), partial ||r||^2
+// x = D^-1 (X~ + X0) c^ and r = b - B^ c^ (each sum over the columns in
+// column order, every product and sum rounded as written), partial ||r||^2
 template <int S>
 __global__ __launch_bounds__(MB_BLOCK) void k_ls_apply(int64_t n, const double* __restrict__ Xt,
                                                        const double* __restrict__ X0,
@@ -550,31 +555,34 @@ __global__ __launch_bounds__(MB_BLOCK) void k_ls_apply(int64_t n, const double* 
                                                        double* __restrict__ x,
                                                        double* __restrict__ part,
                                                        const DevState* __restrict__ st) {
+#pragma clang fp contract(off)
     __shared__ double red[MB_BLOCK];
     double c[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) c[j] = st->chat[j];
-    const double y0 = st->y0;
+    const int s = st->s;
     double s2 = 0.0;
     for (int64_t r = blockIdx.x * (int64_t)MB_BLOCK + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * MB_BLOCK) {
-        double ax = 0.0, ar = 0.0;
-        const double dr = d[r];
+        double ax = 0.0, ab = 0.0;
+        const double dr = d[r], br = b[r];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            ax += (Xt[r * S + j] + X0[r * S + j]) * c[j];
-            ar += (dr * R[r * S + j]) * c[j];
+            if (j < s) {
+                ax += (Xt[r * S + j] + X0[r * S + j]) * c[j];
+                ab += bhat_entry(br, dr, R[r * S + j]) * c[j];
+            }
         }
         x[r] = ax / dr;
-        const double res = y0 * b[r] + ar;
+        const double res = br - ab;
         s2 += res * res;
     }
     red[threadIdx.x] = s2;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int k = 0; k < MB_BLOCK; ++k) s += red[k];
-        part[blockIdx.x] = s;
+        double v = 0.0;
+        for (int k = 0; k < MB_BLOCK; ++k) v += red[k];
+        part[blockIdx.x] = v;
     }
 }
 

@@ -55,10 +55,10 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_qr(const double* __restri
 
 template <int S>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail_ls(const double* __restrict__ part, int nwg,
-                                                          DevState* __restrict__ st) {
+                                                          int64_t n, DevState* __restrict__ st) {
     __shared__ double sm[SxsWs<S>::DOUBLES];
     __shared__ int smi[SxsWs<S>::INTS];
-    tail_ls_body<S>(part, nwg, tri_count(S + 1), st, sm, smi);
+    tail_ls_body<S>(part, nwg, 2 * tri_count(S + 1), n, st, sm, smi);
 }
 
 // ||r|| of the LS combination and the accept test (the stop test on the combination)
@@ -245,9 +245,10 @@ hipError_t launch_tail_qr(int S, int nwg, const double* part, DevState* st, doub
     })
 }
 
-hipError_t launch_tail_ls(int S, int nwg, const double* part, DevState* st, hipStream_t s) {
+hipError_t launch_tail_ls(int S, int nwg, int64_t n, const double* part, DevState* st,
+                          hipStream_t s) {
     MB_TAIL_S(S, {
-        hipLaunchKernelGGL(k_tail_ls<SS>, dim3(1), dim3(TAIL_THREADS), 0, s, part, nwg, st);
+        hipLaunchKernelGGL(k_tail_ls<SS>, dim3(1), dim3(TAIL_THREADS), 0, s, part, nwg, n, st);
         return hipGetLastError();
     })
 }

@@ -24,7 +24,8 @@ inline int padded_width(int s) {
 // entries of one workgroup's partial for each reduction
 inline int part_entries_gram(int S) { return tri_count(S); }
 inline int part_entries_update(int S) { return tri_count(S) + S; }
-inline int part_entries_ls(int S) { return tri_count(S + 1); }
+// double-double Gram of the termination least squares: hi and lo per entry
+inline int part_entries_ls(int S) { return 2 * tri_count(S + 1); }
 
 // tile rows of the streaming n x S kernels: 4 rows per thread
 __host__ __device__ constexpr int stream_tile(int S) { return 1024 / S; }
@@ -172,7 +173,8 @@ hipError_t launch_part_reduce(int nwg, int E, const double* part, double* out, i
 hipError_t launch_tail_xi(int S, int nwg, const double* part, DevState* st, hipStream_t s);
 hipError_t launch_tail_qr(int S, int nwg, const double* part, DevState* st, double* hist,
                           int setup, hipStream_t s);
-hipError_t launch_tail_ls(int S, int nwg, const double* part, DevState* st, hipStream_t s);
+hipError_t launch_tail_ls(int S, int nwg, int64_t n, const double* part, DevState* st,
+                          hipStream_t s);
 hipError_t launch_tail_accept(int nwg, const double* part, DevState* st, hipStream_t s);
 hipError_t launch_tail_true(int nwg, const double* part, DevState* st, hipStream_t s);
 hipError_t launch_tail_pick(int nwg, const double* part, DevState* st, hipStream_t s);

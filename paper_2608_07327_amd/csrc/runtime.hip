@@ -549,7 +549,7 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
     } else {
         if (done == DONE_CONVERGED) {
             CK(launch_ls_gram(S, pl.nwg_ls, c.n, b, c.R, c.d, c.part_a, c.st, c.stream));
-            CK(launch_tail_ls(S, pl.nwg_ls, c.part_a, c.st, c.stream));
+            CK(launch_tail_ls(S, pl.nwg_ls, c.n, c.part_a, c.st, c.stream));
             CK(launch_ls_apply(S, pl.nwg_e, c.n, c.Xt, c.X0, c.R, b, c.d, x, c.part_b, c.st,
                                c.stream));
             CK(launch_tail_accept(pl.nwg_e, c.part_b, c.st, c.stream));

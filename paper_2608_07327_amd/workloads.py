@@ -19,7 +19,8 @@ headline configurations):
                                 harmonic-mean face weights, n = 2,097,152;
                                 optionally with highly conducting cubic
                                 inclusions (a few isolated small eigenvalues).
-* ``dense_spd(8192)``          A = G G^T / n + 1e-3 I, G iid N(0,1).
+* ``dense_spd(8192)``          A = G G^T / n + 1e-3 I, G iid N(0,1) on a
+                                2^-8 grid (the product is then exact).
 * ``graph_laplacian_batch``    random-graph Laplacians (average degree 8)
                                 plus 1e-2 I, n log-uniform in [1e3, 2e5].
 * ``tiny_spd``                 A = Q diag(lambda) Q^T with a set condition
@@ -172,18 +173,60 @@ def rhs(n: int, tag) -> np.ndarray:
     return rng_for((tag, 7777)).standard_normal(n)
 
 
-def dense_spd(n: int, tag=CFG_DENSE, shift: float = 1e-3) -> np.ndarray:
-    """A = G G^T / n + shift I in FP64 with G iid N(0,1) (n x n).  The lower
-    triangle is mirrored so A is bitwise symmetric; row-major and
-    column-major storage are then the same bytes."""
-    rng = rng_for(tag)
-    g = rng.standard_normal((n, n))
-    a = g @ g.T
+# G's entries are N(0,1) draws rounded to the grid 2^-8 (and clipped to
+# [-8, 8], which no draw reaches in practice): every product of two entries is
+# an integer multiple of 2^-16 below 2^6 in magnitude, so each entry of G G^T,
+# a sum of at most 2^14 such products for n <= 16384, is an exact FP64 value
+# whatever the order or blocking of the sum.  Any BLAS, on any host or GPU,
+# then returns the same bytes for A.
+DENSE_GRID = 256.0
+
+
+def dense_factor(n: int, tag=CFG_DENSE) -> np.ndarray:
+    """G (n x n) of the dense construction: iid N(0,1) on the 2^-8 grid."""
+    if n > 16384:
+        raise ValueError("dense_factor: the product is exact only for n <= 16384")
+    g = rng_for(tag).standard_normal((n, n))
+    np.rint(g * DENSE_GRID, out=g)
+    np.clip(g, -8 * DENSE_GRID, 8 * DENSE_GRID, out=g)
+    g /= DENSE_GRID
+    return g
+
+
+def _finish_dense(a, n: int, shift: float):
+    """A = P / n + shift I from the exact product P = G G^T, lower triangle
+    mirrored (A is bitwise symmetric; row- and column-major are the same
+    bytes).  `a` is a numpy array or a torch tensor."""
     a /= n
-    a = np.tril(a)
-    a = a + np.tril(a, -1).T
-    a[np.diag_indices(n)] += shift
-    return np.ascontiguousarray(a)
+    if isinstance(a, np.ndarray):
+        a = np.tril(a)
+        a = a + np.tril(a, -1).T
+        a[np.diag_indices(n)] += shift
+        return a
+    a = a.tril()
+    a = a + a.tril(-1).t()
+    a.diagonal().add_(shift)
+    return a
+
+
+def dense_spd(n: int, tag=CFG_DENSE, shift: float = 1e-3) -> np.ndarray:
+    """A = G G^T / n + shift I in FP64 with G iid N(0,1) on the 2^-8 grid
+    (n x n); the product is exact, so the bytes do not depend on the BLAS."""
+    g = dense_factor(n, tag)
+    a = g @ g.T
+    del g
+    return np.ascontiguousarray(_finish_dense(a, n, shift))
+
+
+def dense_spd_torch(n: int, tag=CFG_DENSE, shift: float = 1e-3, device="cuda:0"):
+    """dense_spd with the n^3 product done by torch on `device` (input
+    generation only); the same bytes as dense_spd because the product is
+    exact."""
+    import torch
+    g = torch.as_tensor(dense_factor(n, tag), device=device)
+    a = torch.mm(g, g.t().contiguous())
+    del g
+    return _finish_dense(a, n, shift).contiguous()
 
 
 def tiny_spd(n: int, cond: float, tag) -> np.ndarray:

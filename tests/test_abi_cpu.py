@@ -100,6 +100,22 @@ def test_batch_validation():
     sysv[0].s = 1
     p.precond = M.PRECOND_BLOCK_JACOBI
     assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_UNSUPPORTED
+    # an unknown preconditioner is an invalid argument, not a silent "none"
+    p.precond = 7
+    assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_INVALID_ARG
+    # unequal tolerances and low-precision refinement are single-system features
+    p = M.default_params()
+    p.tol_initial = 1e-6
+    assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_UNSUPPORTED
+    p = M.default_params()
+    p.precision = M.FP32_IR
+    assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_UNSUPPORTED
+    p = M.default_params()
+    p.max_iter = 2 ** 31
+    assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_INVALID_ARG
+    p = M.default_params()
+    p.tau = float("nan")
+    assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_INVALID_ARG
 
 
 def test_stream_copy_rejects_null():

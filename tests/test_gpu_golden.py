@@ -9,8 +9,8 @@ iteration count with sequential and with blocked-pairwise reductions (their
 difference is the method's own rounding-order noise), the exit diagnostics,
 the noise floor |x_pairwise - x| / |x|, and x at 4096 fixed indices.  The
 bar is the one of the small parity tests: iteration counts within the
-oracle's band (at least 1 %), and where the counts agree, the sampled x
-within max(1e-10, 10 x noise floor).
+oracle's band, and where the counts agree, the sampled x within
+max(1e-10, 10 x noise floor).
 """
 import hashlib
 import json
@@ -59,10 +59,12 @@ def system(gold):
     solver.close()
 
 
-def _band(o):
-    near = abs(o["rel_res_best"] - 1e-8) <= 1e-10
-    return max(abs(o["iterations"] - o["pairwise_iterations"]) + (1 if near else 0),
-               int(np.ceil(0.01 * o["iterations"])))
+def _band(o, tol=1e-8):
+    """The oracle's own rounding-order band: the difference of its two
+    orderings' counts, plus 1 when the deciding residual is within 1 % of
+    tol."""
+    near = abs(o["rel_res_best"] - tol) <= 0.01 * tol
+    return abs(o["iterations"] - o["pairwise_iterations"]) + (1 if near else 0)
 
 
 @pytest.mark.parametrize("s", [1, 2, 4, 8, 16])
@@ -76,10 +78,9 @@ def test_full_size_mbpcg_against_oracle_golden(gold, system, s, mode):
     assert info["status"] == o["status"] == 0
     assert abs(info["iterations"] - o["iterations"]) <= _band(o), (info["iterations"], o)
     assert info["rel_res_true"] < 2e-8
-    if o["iterations"] == o["pairwise_iterations"]:
+    if info["iterations"] == o["iterations"]:
         for key in ("final_width", "deflations", "used_fallback"):
             assert info[key] == o[key], (key, info[key], o[key])
-    if info["iterations"] == o["iterations"] == o["pairwise_iterations"]:
         xs = x.cpu().numpy()[idx]
         xo = np.asarray(o["x_sample"])
         err = np.linalg.norm(xs - xo) / np.linalg.norm(xo)
@@ -92,7 +93,10 @@ def test_full_size_cg_against_oracle_golden(gold, system):
     say("golden 128^3 CG")
     x, info = solver.cg_solve(bd, profile=1)
     assert info["status"] == 0
-    assert abs(info["iterations"] - o["iterations"]) <= int(np.ceil(0.01 * o["iterations"]))
+    # CG has no second ordering stored: its count must match, +-1 only when
+    # the oracle stopped within 1 % of tol
+    near = abs(o["rel_res_true"] - 1e-8) <= 1e-10
+    assert abs(info["iterations"] - o["iterations"]) <= (1 if near else 0)
     assert info["rel_res_true"] < 2e-8
     if info["iterations"] == o["iterations"]:
         xs = x.cpu().numpy()[idx]

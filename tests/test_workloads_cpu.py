@@ -92,7 +92,26 @@ def test_dense_spd_is_bitwise_symmetric_with_the_shift_as_floor():
     assert ev.min() >= 1e-3 * (1 - 1e-9)
     g = W.rng_for((72, 1)).standard_normal((n, n))
     ref = g @ g.T / n + 1e-3 * np.eye(n)
-    assert np.allclose(A, ref, rtol=0, atol=1e-13)
+    # G is N(0,1) rounded to the 2^-8 grid: within 2^-9 of the draw per entry
+    assert np.allclose(A, ref, rtol=0, atol=0.05)
+
+
+@pytest.mark.parametrize("n", [64, 600, 1024])
+def test_dense_spd_product_is_exact_and_blas_independent(n):
+    """The entries of G are integers over 2^8, so G G^T computed in integer
+    arithmetic is the exact product; numpy's BLAS and torch's matmul must
+    both return exactly it (then any GPU BLAS does too)."""
+    import torch
+    g = W.dense_factor(n, (72, 2))
+    k = np.rint(g * W.DENSE_GRID).astype(np.int64)
+    assert np.array_equal(k / W.DENSE_GRID, g)
+    exact = (k @ k.T).astype(np.float64) / W.DENSE_GRID ** 2
+    A = W.dense_spd(n, tag=(72, 2), shift=1e-3)
+    ref = exact / n
+    ref[np.diag_indices(n)] += 1e-3
+    assert np.array_equal(A, ref)
+    At = W.dense_spd_torch(n, tag=(72, 2), shift=1e-3, device="cpu").numpy()
+    assert np.array_equal(A, At)
 
 
 def test_seeds_and_right_hand_sides():
