@@ -192,16 +192,22 @@ void or_matmul_block(const or_matrix* A, int k, const double* X, double* Y)
                 Y[r * k + j] = acc;
             }
     } else {
-        memset(Y, 0, sizeof(double) * (size_t)(n * k));
+        /* the sum over the columns is a reduction over n terms: sequential in
+         * mode 0, blocked pairwise in mode 1 */
+        reducer Rd;
+        red_init(&Rd, (int)(n * k));
         for (int64_t c = 0; c < n; ++c) {
             const double* col = A->a + c * A->lda;
             const double* xr = X + c * k;
+            double* acc = red_row(&Rd);
             for (int64_t r = 0; r < n; ++r) {
                 double a = col[r];
-                double* yr = Y + r * k;
+                double* yr = acc + r * k;
                 for (int j = 0; j < k; ++j) yr[j] += a * xr[j];
             }
+            red_end_row(&Rd);
         }
+        red_finish(&Rd, Y);
     }
 }
 

@@ -15,16 +15,25 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mbpcg_oracle.c")
 LIB = os.path.join(HERE, "libmbpcg_oracle.so")
+# The same source compiled with multiply-adds contracted to fused
+# multiply-adds: a third rounding of the same arithmetic, used only to
+# measure the method's rounding noise (see set_variant).
+LIB_FMA = os.path.join(HERE, "libmbpcg_oracle_fma.so")
+
+_FLAGS = {LIB: ["-ffp-contract=off"], LIB_FMA: ["-ffp-contract=fast", "-mfma"]}
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
-            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "mbpcg_oracle.h"))):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (-O2, no fast-math; no FMA contraction in
+    the reference build, contraction in the noise-measurement build)."""
+    hdr = os.path.join(HERE, "mbpcg_oracle.h")
+    for lib_path, flags in _FLAGS.items():
+        if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < max(
+                os.path.getmtime(SRC), os.path.getmtime(hdr)):
+            tmp = lib_path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *flags,
+                                   "-Wall", "-o", tmp, SRC, "-lm"])
+            os.replace(tmp, lib_path)
     return LIB
 
 
@@ -53,34 +62,60 @@ class OrInfo(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-_lib = None
+_libs = {}
+_variant = "seq"
+
+
+def _load(path):
+    L = C.CDLL(path)
+    vp, i64, dbl = C.c_void_p, C.c_int64, C.c_double
+    L.or_set_summation.argtypes = [C.c_int]
+    L.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    L.or_splitmix64.restype = C.c_uint64
+    L.or_uniform_block.argtypes = [C.c_uint64, i64, C.c_int, vp]
+    L.or_matmul_block.argtypes = [vp, C.c_int, vp, vp]
+    L.or_round_bf16.argtypes = [dbl]
+    L.or_round_bf16.restype = dbl
+    L.or_gram.argtypes = [i64, C.c_int, vp, C.c_int, vp, vp]
+    L.or_cholesky.argtypes = [C.c_int, vp, vp]
+    L.or_spd_inverse.argtypes = [C.c_int, vp, vp]
+    L.or_cholqr_deflate.argtypes = [i64, C.c_int, vp, dbl, vp, vp, vp]
+    L.or_cholqr_deflate_prec.argtypes = [i64, C.c_int, vp, vp, dbl, vp, vp, vp, vp]
+    L.or_block_jacobi_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
+    L.or_lstsq.argtypes = [i64, C.c_int, vp, vp, vp]
+    L.or_mbpcg_solve.argtypes = [vp, vp, vp, vp, vp]
+    L.or_hs_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, C.c_int, vp, vp, vp]
+    L.or_cg_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, C.c_int, vp, vp, vp]
+    return L
 
 
 def lib():
-    global _lib
-    if _lib is None:
+    """The oracle library of the current variant (the reference build unless
+    set_variant chose the fused multiply-add build)."""
+    if not _libs:
         build()
-        L = C.CDLL(LIB)
-        vp, i64, dbl = C.c_void_p, C.c_int64, C.c_double
-        L.or_set_summation.argtypes = [C.c_int]
-        L.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
-        L.or_splitmix64.restype = C.c_uint64
-        L.or_uniform_block.argtypes = [C.c_uint64, i64, C.c_int, vp]
-        L.or_matmul_block.argtypes = [vp, C.c_int, vp, vp]
-        L.or_round_bf16.argtypes = [dbl]
-        L.or_round_bf16.restype = dbl
-        L.or_gram.argtypes = [i64, C.c_int, vp, C.c_int, vp, vp]
-        L.or_cholesky.argtypes = [C.c_int, vp, vp]
-        L.or_spd_inverse.argtypes = [C.c_int, vp, vp]
-        L.or_cholqr_deflate.argtypes = [i64, C.c_int, vp, dbl, vp, vp, vp]
-        L.or_cholqr_deflate_prec.argtypes = [i64, C.c_int, vp, vp, dbl, vp, vp, vp, vp]
-        L.or_block_jacobi_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
-        L.or_lstsq.argtypes = [i64, C.c_int, vp, vp, vp]
-        L.or_mbpcg_solve.argtypes = [vp, vp, vp, vp, vp]
-        L.or_hs_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, C.c_int, vp, vp, vp]
-        L.or_cg_cg.argtypes = [vp, vp, vp, dbl, i64, C.c_int, C.c_int, vp, vp, vp]
-        _lib = L
-    return _lib
+        _libs["ref"] = _load(LIB)
+        _libs["fma"] = _load(LIB_FMA)
+    return _libs["fma" if _variant == "fma" else "ref"]
+
+
+VARIANTS = ("seq", "pairwise", "fma")
+
+
+def set_variant(v: str):
+    """Rounding variant of every following call: "seq" (the reference:
+    sequential sums, every product and sum rounded separately), "pairwise"
+    (the same with blocked-pairwise sums over the n rows and the dense
+    product's n columns), or "fma" (sequential sums with multiply-adds
+    contracted to fused multiply-adds).  The three runs of one input measure
+    how much the method moves under a change of rounding alone."""
+    global _variant
+    if v not in VARIANTS:
+        raise ValueError(v)
+    _variant = v
+    lib()
+    for L in _libs.values():
+        L.or_set_summation(1 if v == "pairwise" else 0)
 
 
 def _p(a):
@@ -110,7 +145,8 @@ class Matrix:
 
 
 def set_summation(mode: int):
-    lib().or_set_summation(int(mode))
+    """0: the reference variant, 1: blocked-pairwise sums (set_variant)."""
+    set_variant("pairwise" if int(mode) == 1 else "seq")
 
 
 def splitmix64(seed: int, k: int) -> int:

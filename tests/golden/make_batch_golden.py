@@ -5,10 +5,11 @@ The batched workload: 512 random-graph Laplacians (average degree 8) plus
 {1, 4, 8}, Jacobi scaling, tolerance 1e-8 (workloads.graph_laplacian_batch).
 System i draws its initial block from SplitMix64 seeded with SEED + i, as a
 batched solve with common seed SEED does.  For every system the oracle's
-Algorithm 1 runs twice (sequential and blocked-pairwise reductions); stored
-per system: n, nnz, s, iteration counts, exit diagnostics, the noise floor
-|x_pairwise - x| / |x|, |x|, and x at 16 fixed indices; plus a hash of all
-input bytes and the oracle's total (sequential) time.
+Algorithm 1 runs in its three rounding variants (reference, blocked-pairwise
+sums, fused multiply-adds); stored per system: n, nnz, s, iteration counts,
+exit diagnostics, the noise floor (largest relative distance between two
+variants' x), |x|, and x at 16 fixed indices; plus a hash of all input
+bytes and the reference runs' total time.
 
     python tests/golden/make_batch_golden.py [--count 512] [--jobs 6]
 """
@@ -25,6 +26,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+import golden_common as G  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from paper_2608_07327_amd import workloads as W  # noqa: E402
 
@@ -46,10 +48,9 @@ def sample_index(i, n, k=16):
 
 
 def job(task):
-    i, mode = task
+    i, variant = task
     y = _SYS[i]
-    O.set_summation(mode)
-    x, info, _ = O.mbpcg_solve(y.A, y.b, y.s, seed=SEED + i)
+    x, info, _ = G.run_variant(variant, O.mbpcg_solve, y.A, y.b, y.s, seed=SEED + i)
     return task, info, x
 
 
@@ -65,34 +66,23 @@ def main():
     _SYS.extend(W.graph_laplacian_batch(count=args.count))
     print(f"generated {len(_SYS)} systems in {time.time() - t:.0f} s", flush=True)
     rec = {"count": args.count, "seed": SEED, "input_sha256": batch_hash(_SYS), "systems": []}
-    tasks = [(i, m) for i in range(len(_SYS)) for m in (0, 1)]
+    tasks = [(i, v) for i in range(len(_SYS)) for v in G.VARIANTS]
     res = {}
     with mp.get_context("fork").Pool(args.jobs) as pool:
-        for k, ((i, mode), info, x) in enumerate(pool.imap_unordered(job, tasks, chunksize=4)):
-            res[(i, mode)] = (info, x)
-            if (k + 1) % 128 == 0:
+        for k, ((i, v), info, x) in enumerate(pool.imap_unordered(job, tasks, chunksize=4)):
+            res.setdefault(i, {})[v] = (x, info)
+            if (k + 1) % 192 == 0:
                 print(f"{k + 1}/{len(tasks)} runs", flush=True)
     total = 0.0
     for i, y in enumerate(_SYS):
-        i0, x0 = res[(i, 0)]
-        i1, x1 = res[(i, 1)]
         idx = sample_index(i, y.A.n)
-        total += i0["seconds"]
-        rec["systems"].append({
-            "n": y.A.n, "nnz": y.A.nnz, "s": y.s, "iterations": i0["iterations"],
-            "status": i0["status"], "best_column": i0["best_column"],
-            "final_width": i0["final_width"], "deflations": i0["deflations"],
-            "used_fallback": i0["used_fallback"], "rel_res_best": i0["rel_res_best"],
-            "rel_res_true": i0["rel_res_true"], "seconds": i0["seconds"],
-            "pairwise_iterations": i1["iterations"],
-            "pairwise_used_fallback": i1["used_fallback"],
-            "noise_floor": float(np.linalg.norm(x1 - x0) / np.linalg.norm(x0)),
-            "x_norm": float(np.linalg.norm(x0)), "sample_index": idx.tolist(),
-            "x_sample": x0[idx].tolist(),
-        })
+        total += res[i]["seq"][1]["seconds"]
+        r = G.mbpcg_record(res[i], idx, n=y.A.n, nnz=y.A.nnz, s=y.s, seed=SEED + i,
+                           sample_index=idx.tolist())
+        rec["systems"].append(r)
     rec["oracle_seconds_total"] = total
     json.dump(rec, open(out, "w"))
-    print(f"oracle total {total:.0f} s (sequential runs, one thread each)", flush=True)
+    print(f"oracle total {total:.0f} s (reference runs, one thread each)", flush=True)
 
 
 if __name__ == "__main__":

@@ -3,15 +3,16 @@
 The dense FP64 workload: A = G G^T / n + 1e-3 I (n = 8192, G iid N(0,1) on
 the 2^-8 grid, so the bytes of A do not depend on the BLAS that forms it),
 b ~ N(0,1), no preconditioning, tolerance 1e-8.  For each block width s the
-oracle's Algorithm 1 runs twice -- sequential and blocked-pairwise
-reductions -- and the Chronopoulos-Gear CG once.  Stored: iteration counts,
-exit diagnostics, the rounding-order noise floor |x_pairwise - x| / |x|, and
-x at 4096 fixed indices, plus a hash of the input bytes.
+oracle's Algorithm 1, and the Chronopoulos-Gear CG, run in the oracle's three
+rounding variants (reference, blocked-pairwise sums, fused multiply-adds).
+Stored: iteration counts, exit diagnostics, the noise floor (largest
+relative distance between two variants' x), and x at 4096 fixed indices,
+plus a hash of the input bytes.
 
     python tests/golden/make_dense_golden.py [--n 8192] [--s 1,4,8,16,32] [--jobs 6]
 
-Each (s, summation order) is one job of a process pool; results are written
-as they arrive, and widths already in the output are skipped.
+Each (s, variant) is one job of a process pool; results are written as
+they arrive, and widths already in the output are skipped.
 """
 import argparse
 import hashlib
@@ -26,6 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+import golden_common as G  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from paper_2608_07327_amd import workloads as W  # noqa: E402
 
@@ -51,18 +53,16 @@ def sample_index(n, k=4096):
 
 
 def job(task):
-    n, kind, s, mode = task
+    n, kind, s, variant = task
     A, b = system(n)
-    idx = sample_index(n)
-    O.set_summation(mode)
     t = time.time()
     if kind == "cg":
-        x, info, _ = O.cg_cg(A, b, tol=TOL, jacobi=False)
+        x, info, _ = G.run_variant(variant, O.cg_cg, A, b, tol=TOL, jacobi=False)
     else:
-        x, info, _ = O.mbpcg_solve(A, b, s, tol=TOL, jacobi=False,
+        x, info, _ = G.run_variant(variant, O.mbpcg_solve, A, b, s, tol=TOL, jacobi=False,
                                    seed=W.uniform_block_seed(W.CFG_DENSE, s))
     info["seconds_wall"] = time.time() - t
-    return task, info, x[idx].tolist(), float(np.linalg.norm(x)), x
+    return task, info, x
 
 
 def main():
@@ -75,46 +75,29 @@ def main():
     out = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                    f"dense_{args.n}.json")
     A, b = system(args.n)
+    idx = sample_index(args.n)
     rec = json.load(open(out)) if os.path.exists(out) else {}
     rec.update({"n": args.n, "shift": 1e-3, "tol": TOL, "input_sha256": input_hash(A, b),
-                "sample_index": sample_index(args.n).tolist()})
+                "sample_index": idx.tolist()})
     rec.setdefault("mbpcg", {})
-    tasks = []
-    if "cg" not in rec:
-        tasks.append((args.n, "cg", 1, 0))
-    for s in [int(v) for v in args.s.split(",")]:
-        if str(s) not in rec["mbpcg"]:
-            tasks += [(args.n, "mbpcg", s, 0), (args.n, "mbpcg", s, 1)]
-    # longest jobs first
-    tasks.sort(key=lambda t: -t[2])
-    partial = {}
+    keys = [] if "cg" in rec else [("cg", 1)]
+    keys += [("mbpcg", s) for s in [int(v) for v in args.s.split(",")]
+             if str(s) not in rec["mbpcg"]]
+    tasks = [(args.n, kind, s, v) for kind, s in keys for v in G.VARIANTS]
+    tasks.sort(key=lambda t: -t[2])   # longest jobs first
+    got = {}
     with mp.get_context("fork").Pool(args.jobs) as pool:
-        for (n, kind, s, mode), info, xs, xn, x in pool.imap_unordered(job, tasks):
-            print(kind, s, "pairwise" if mode else "sequential", info["iterations"],
-                  f"{info['seconds_wall']:.0f} s", flush=True)
+        for (n, kind, s, v), info, x in pool.imap_unordered(job, tasks):
+            print(kind, s, v, info["iterations"], f"{info['seconds_wall']:.0f} s", flush=True)
+            got.setdefault((kind, s), {})[v] = (x, info)
+            if len(got[(kind, s)]) < len(G.VARIANTS):
+                continue
+            runs = got.pop((kind, s))
             if kind == "cg":
-                rec["cg"] = {"iterations": info["iterations"], "status": info["status"],
-                             "rel_res_true": info["rel_res_true"],
-                             "seconds": info["seconds"], "x_sample": xs, "x_norm": xn}
+                rec["cg"] = G.mbpcg_record(runs, idx)
             else:
-                partial.setdefault(s, {})[mode] = (info, xs, xn, x)
-                if len(partial[s]) == 2:
-                    i0, xs0, xn0, x0 = partial[s][0]
-                    i1, _, _, x1 = partial[s][1]
-                    rec["mbpcg"][str(s)] = {
-                        "seed": W.uniform_block_seed(W.CFG_DENSE, s),
-                        "iterations": i0["iterations"], "status": i0["status"],
-                        "best_column": i0["best_column"], "final_width": i0["final_width"],
-                        "deflations": i0["deflations"], "used_fallback": i0["used_fallback"],
-                        "rel_res_best": i0["rel_res_best"], "rel_res_ls": i0["rel_res_ls"],
-                        "rel_res_true": i0["rel_res_true"], "ls_kept": i0["ls_kept"],
-                        "seconds": i0["seconds"],
-                        "pairwise_iterations": i1["iterations"],
-                        "pairwise_used_fallback": i1["used_fallback"],
-                        "noise_floor": float(np.linalg.norm(x1 - x0) / np.linalg.norm(x0)),
-                        "x_sample": xs0, "x_norm": xn0,
-                    }
-                    del partial[s]
+                rec["mbpcg"][str(s)] = G.mbpcg_record(runs, idx,
+                                                      seed=W.uniform_block_seed(W.CFG_DENSE, s))
             json.dump(rec, open(out, "w"))
 
 

@@ -1,19 +1,21 @@
 """The FP64 parity contract between a GPU solve and the CPU oracle.
 
-The oracle runs twice on the same input, with sequential and with
-blocked-pairwise reductions; that pair fixes how much the method itself
-moves when only the rounding order changes (its noise floor).  The GPU adds
-in yet another fixed order and is held to that band:
+The oracle runs three times on the same input, in three roundings of the
+same arithmetic: sequential sums with every product and sum rounded (the
+reference), blocked-pairwise sums over the n rows and the dense product's
+n columns, and sequential sums with multiply-adds fused.  Their spread fixes
+how much the method itself moves when only the rounding changes (its noise
+floor).  The GPU, which sums in fixed trees and fuses multiply-adds, is held
+to that band:
 
 * status equal;
-* iteration count within |it_seq - it_pairwise|, plus 1 when the best
-  column's relative residual at the deciding iteration (the last one, or the
-  one before it) is within 1 % of tol;
-* when the GPU's count equals the oracle's (either ordering's): x within
-  max(floor, 10 f) of that ordering's x, with f = |x_pairwise - x_seq| /
-  |x_seq| and floor 1e-10; used_fallback,
-  final_width and deflations equal wherever the two oracle orderings agree
-  on them;
+* iteration count within the three runs' range (max - min), plus 1 when the
+  best column's relative residual at the deciding iteration (the last one,
+  or the one before it) is within 1 % of tol, around the reference count;
+* when the GPU's count equals one of the runs' counts: x within
+  max(floor, 10 f) of that run's x, with f the largest relative distance
+  between two of the three runs' x and floor 1e-10; used_fallback,
+  final_width and deflations equal wherever the three runs agree on them;
 * converged solves: FP64 true residual below 2 tol.
 
 No case is exempt: the least squares of the termination computes the same
@@ -28,18 +30,33 @@ from oracle import oracle as O
 
 
 def oracle_band(A, b, s, **kw):
-    """Oracle run with sequential and with blocked-pairwise reductions;
-    returns (x_seq, info_seq, x_pair, info_pair) with the best-column
-    residual histories in info['history']."""
-    xs, i_s, es = O.mbpcg_solve(A, b, s, want_history=True, **kw)
-    O.set_summation(1)
+    """The oracle in its three rounding variants; returns (x_seq, info_seq,
+    x_others, info_others) with the best-column residual histories in
+    info['history'] (the others: pairwise, fused multiply-add)."""
+    runs = []
     try:
-        xp, i_p, ep = O.mbpcg_solve(A, b, s, want_history=True, **kw)
+        for v in O.VARIANTS:
+            O.set_variant(v)
+            x, i, e = O.mbpcg_solve(A, b, s, want_history=True, **kw)
+            i["history"] = e["history"]
+            i["variant"] = v
+            runs.append((x, i))
     finally:
-        O.set_summation(0)
-    i_s["history"] = es["history"]
-    i_p["history"] = ep["history"]
-    return xs, i_s, xp, i_p
+        O.set_variant("seq")
+    (xs, i_s), others = runs[0], runs[1:]
+    return xs, i_s, [x for x, _ in others], [i for _, i in others]
+
+
+def in_variants(fn, *a, **kw):
+    """fn(*a, **kw) under each rounding variant of the oracle, reference first."""
+    out = []
+    try:
+        for v in O.VARIANTS:
+            O.set_variant(v)
+            out.append(fn(*a, **kw))
+    finally:
+        O.set_variant("seq")
+    return out
 
 
 def near_tol(io, tol):
@@ -51,8 +68,9 @@ def near_tol(io, tol):
     return any(abs(v - tol) <= 0.01 * tol for v in vals)
 
 
-def iteration_band(io, ip, tol):
-    return abs(io["iterations"] - ip["iterations"]) + (1 if near_tol(io, tol) else 0)
+def iteration_band(io, ips, tol):
+    its = [io["iterations"]] + [ip["iterations"] for ip in ips]
+    return max(its) - min(its) + (1 if near_tol(io, tol) else 0)
 
 
 def rel(a, b):
@@ -60,22 +78,30 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
-def check(x, info, xo, io, xp, ip, tol, floor=1e-10, what=""):
-    """Assert the contract above; returns the measured |x - x_seq| / |x_seq|
-    (None when the counts differ)."""
+def noise_floor(xo, xps):
+    xs = [xo] + list(xps)
+    nb = float(np.linalg.norm(xo))
+    if nb == 0.0:
+        return 0.0
+    return max(float(np.linalg.norm(a - c)) / nb for k, a in enumerate(xs) for c in xs[k + 1:])
+
+
+def check(x, info, xo, io, xps, ips, tol, floor=1e-10, what=""):
+    """Assert the contract above; returns the measured |x - x_ref| / |x_ref|
+    against the run with the same count (None when no run has it)."""
     assert info["status"] == io["status"], (what, info, io)
-    band = iteration_band(io, ip, tol)
+    band = iteration_band(io, ips, tol)
     assert abs(info["iterations"] - io["iterations"]) <= band, \
-        (what, info["iterations"], io["iterations"], ip["iterations"])
+        (what, info["iterations"], io["iterations"], [ip["iterations"] for ip in ips])
+    f = noise_floor(xo, xps)
     err = None
-    f = rel(xp, xo)
-    for ref, iref in ((xo, io), (xp, ip)):
-        # against the oracle ordering that took the same number of steps
+    for ref, iref in [(xo, io)] + list(zip(xps, ips)):
+        # against an oracle run that took the same number of steps
         if info["iterations"] == iref["iterations"]:
             err = rel(x, ref)
-            assert err <= max(floor, 10 * f), (what, err, f)
+            assert err <= max(floor, 10 * f), (what, iref.get("variant"), err, f)
             for key in ("used_fallback", "final_width", "deflations"):
-                if io[key] == ip[key]:
+                if all(ip[key] == io[key] for ip in ips):
                     assert info[key] == iref[key], (what, key, info[key], iref[key])
             break
     if io["status"] == 0:

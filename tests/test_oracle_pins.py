@@ -400,6 +400,48 @@ def test_true_residual_fallback_leaves_a_good_combination_alone():
     assert ib["rel_res_true"] < 1e-8
 
 
+def test_two_tolerances_try_the_combination_from_tol_initial():
+    # Alg. 1's two tests: once the best column's residual is below
+    # tol_initial, the least-squares combination is tried at every iteration
+    # and the solve ends at the first one where it meets tol.  Replayed here
+    # independently: the state after k iterations (a run capped at k with
+    # equal tolerances, which cannot stop earlier) gives numpy's least
+    # squares on B^ = B - D R.
+    A = W.poisson2d(32)
+    b = W.rhs(A.n, 41)
+    s, seed, tol, tol0 = 4, 3, 1e-8, 1e-6
+    d = np.sqrt(A.to_scipy().diagonal())
+    nb = np.linalg.norm(b)
+    _, i_eq, _ = O.mbpcg_solve(A, b, s, seed=seed, tol=tol)
+    x2, i2, _ = O.mbpcg_solve(A, b, s, seed=seed, tol=tol, tol_initial=tol0)
+    k_star = i2["iterations"]
+    assert i2["status"] == 0 and i2["used_fallback"] == 0 and k_star < i_eq["iterations"]
+
+    def state(k):
+        _, ik, ek = O.mbpcg_solve(A, b, s, seed=seed, tol=tol, max_iter=k, want_X=True)
+        assert ik["status"] == 1 and ik["iterations"] == k
+        Bh = b[:, None] - d[:, None] * ek["R"]
+        c = np.linalg.lstsq(Bh, b, rcond=None)[0]
+        return np.linalg.norm(b - Bh @ c) / nb, ik["rel_res_best"], ek["X"] @ c / d
+
+    first = None
+    for k in range(1, k_star + 1):
+        res, nu, xk = state(k)
+        if nu < tol0 and first is None:
+            first = k
+        if first is not None and k < k_star:
+            assert res >= tol and nu >= tol, k          # tried and rejected
+    assert first is not None and first < k_star
+    assert res < tol and nu >= tol                      # accepted at k_star
+    assert abs(i2["rel_res_ls"] - res) <= 1e-6 * res
+    assert np.linalg.norm(x2 - xk) <= 1e-8 * np.linalg.norm(xk)
+    # tol_initial below tol: the first test alone decides (the combination is
+    # at least as good as the best column), later than with equal tolerances
+    x3, i3, _ = O.mbpcg_solve(A, b, s, seed=seed, tol=tol, tol_initial=1e-9)
+    assert i3["status"] == 0 and i3["rel_res_best"] < 1e-9
+    assert i3["iterations"] > i_eq["iterations"] and i3["rel_res_ls"] <= i3["rel_res_best"]
+
+
 def test_lstsq_leaves_out_dependent_columns():
     # an exact duplicate and more columns than rows: the dependent columns get
     # coefficient 0 and the residual is numpy's minimum
@@ -447,17 +489,40 @@ def test_iterations_fall_as_width_grows():
     assert its == sorted(its, reverse=True) and its[-1] < its[0]
 
 
-def test_summation_order_noise_floor_is_small():
+def test_rounding_variants_noise_floor_is_small():
     A = W.poisson2d(64)
     b = W.rhs(A.n, W.CFG_POISSON2D)
     x0, i0, _ = O.mbpcg_solve(A, b, 4, seed=4004)
-    O.set_summation(1)
+    for v in ("pairwise", "fma"):
+        O.set_variant(v)
+        try:
+            x1, i1, _ = O.mbpcg_solve(A, b, 4, seed=4004)
+        finally:
+            O.set_variant("seq")
+        assert i0["iterations"] == i1["iterations"]
+        assert 0 < np.linalg.norm(x1 - x0) <= 1e-9 * np.linalg.norm(x0)
+
+
+def test_pairwise_variant_sums_the_dense_product_in_blocks():
+    # the dense product's sum over the n columns is a reduction like the
+    # others: the pairwise variant adds blocks of 64 columns and combines the
+    # block sums as a binary counter.  On integer-valued data every order is
+    # exact (equal), on real data the two orders differ by rounding only.
+    rng = np.random.default_rng(11)
+    n = 300
+    Ai = rng.integers(-50, 50, (n, n)).astype(np.float64)
+    Xi = rng.integers(-50, 50, (n, 3)).astype(np.float64)
+    A = rng.standard_normal((n, n))
+    X = rng.standard_normal((n, 3))
+    y0i, y0 = O.matmul_block(Ai, Xi), O.matmul_block(A, X)
+    O.set_variant("pairwise")
     try:
-        x1, i1, _ = O.mbpcg_solve(A, b, 4, seed=4004)
+        y1i, y1 = O.matmul_block(Ai, Xi), O.matmul_block(A, X)
     finally:
-        O.set_summation(0)
-    assert i0["iterations"] == i1["iterations"]
-    assert np.linalg.norm(x1 - x0) <= 1e-9 * np.linalg.norm(x0)
+        O.set_variant("seq")
+    assert np.array_equal(y0i, Ai @ Xi) and np.array_equal(y1i, y0i)
+    assert not np.array_equal(y1, y0)
+    assert np.abs(y1 - y0).max() <= 4 * n * 2.0 ** -53 * (np.abs(A) @ np.abs(X)).max()
 
 
 # -------------------------------------------------------------- edge cases
