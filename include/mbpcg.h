@@ -72,7 +72,13 @@ typedef enum { MBPCG_MEM_HOST = 0, MBPCG_MEM_DEVICE = 1 } mbpcg_mem;
 typedef struct {
     int32_t s;              /* copies (block width), 1..32                               */
     double tol;             /* convergence tolerance on ||b - A x|| / ||b|| (Alg. 1)     */
-    double tol_initial;     /* best-column tolerance; <= 0 means tol (the paper's setting) */
+    double tol_initial;     /* best-column tolerance of Alg. 1's first stop test; <= 0   */
+                            /* means tol (the paper's setting).  Once the best column's  */
+                            /* residual is below it, the least-squares combination is   */
+                            /* tried every iteration and the solve ends when that meets  */
+                            /* tol or the best column does (Alg. 1's second test).       */
+                            /* Single-system FP64 solves; IR inner solves and batches    */
+                            /* use tol (a batch with tol_initial != tol: UNSUPPORTED)    */
     int64_t max_iter;       /* iteration cap (inner cap in IR mode)                      */
     mbpcg_precond precond;  /* NONE, JACOBI (Sec. 1 scaling) or BLOCK_JACOBI (above)     */
     uint64_t seed;          /* SplitMix64 seed of the Uniform(-1,1) initial block         */

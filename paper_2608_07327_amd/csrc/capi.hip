@@ -174,8 +174,6 @@ static mbpcg_status check_params(mbpcg_ctx ctx, const double* b, double* x, mbpc
     if (p->s < 1) return MBPCG_ERR_INVALID_ARG;
     if (p->s > 32) return MBPCG_ERR_UNSUPPORTED;
     if (!std::isfinite(p->tol_initial) || !std::isfinite(p->tau)) return MBPCG_ERR_INVALID_ARG;
-    // the library runs the paper's setting of equal tolerances
-    if (p->tol_initial > 0.0 && p->tol_initial != p->tol) return MBPCG_ERR_UNSUPPORTED;
     if (p->precision != MBPCG_FP64 && p->precision != MBPCG_FP32_IR &&
         p->precision != MBPCG_BF16_IR)
         return MBPCG_ERR_INVALID_ARG;

@@ -28,6 +28,9 @@ enum DoneCode : int32_t {
     DONE_NOTSPD = 4,
     DONE_NONFINITE = 5,
     DONE_ZERO_RHS = 6,
+    // the best column met tol_initial > tol: the host runs the least squares
+    // and either finishes the solve or resumes the loop (Alg. 1's two tests)
+    DONE_LS = 7,
 };
 
 // Per-solve state resident in device memory.  The host reads `done` and
@@ -52,7 +55,13 @@ struct DevState {
     // 1 from the Xi tail of an iteration whose update runs until the next
     // Xi tail: tells the direction update to apply that iteration's
     // X~ += P alpha even when the QR tail has just stopped the loop
-    int32_t xt_pending, pad3;
+    int32_t xt_pending;
+    // 1 when tol_initial > tol: the stop test on the best column hands over to
+    // the least squares (DONE_LS) instead of finishing the solve
+    int32_t ls_inloop;
+    // 1 after a resumed Cholesky QR: the direction kernel of that iteration
+    // leaves X~ alone (its update was applied when the loop stopped)
+    int32_t xt_skip, pad3;
 };
 
 __host__ __device__ constexpr int tri_count(int S) { return S * (S + 1) / 2; }

@@ -267,6 +267,11 @@ template <int S>
 __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride,
                             DevState* __restrict__ st, double* __restrict__ hist, int setup,
                             double* sm, int* smi) {
+    // setup 2: resume after a least squares that did not finish the solve --
+    // the best column and the stop test of this iteration are done, only the
+    // Cholesky QR is left (the direction kernel then leaves X~ alone)
+    const int resume = setup == 2;
+    if (resume) setup = 0;
     constexpr int E = tri_count(S);
     constexpr int ET = E + S;
     constexpr int RN = RedWs<ET>::N;
@@ -282,8 +287,11 @@ __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride
     int* stop = smi + S + 1;
     const int t = threadIdx.x;
     reduce_partials(part, nwg, ET, stride, red, tmp);
-    if (t < st->s) st->nu[t] = sqrt(red[E + t]) / st->bnorm;
-    if (t == 0) {
+    if (!resume && t < st->s) st->nu[t] = sqrt(red[E + t]) / st->bnorm;
+    if (t == 0 && resume) {
+        st->xt_skip = 1;
+        *stop = 0;
+    } else if (t == 0) {
         // best column in the original residual norm (Sec. 1: R = D R~)
         const int s = st->s;
         int h = 0;
@@ -306,7 +314,7 @@ __device__ int tail_qr_body(const double* __restrict__ part, int nwg, int stride
                 st->done = DONE_NONFINITE;
                 stp = 1;
             } else if (nu_h < st->tol0) {
-                st->done = DONE_CONVERGED;
+                st->done = st->ls_inloop ? DONE_LS : DONE_CONVERGED;
                 stp = 1;
             }
         }

@@ -254,6 +254,8 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
     constexpr bool XD = !FIRST && xt_in_dir<S>();
     const int stop = st->done;
     if (stop && !(XD && st->xt_pending)) return;
+    // after a resumed Cholesky QR this iteration's X~ update is already done
+    const bool xd = XD && !st->xt_skip;
     constexpr int RPP = Tiles<S>::RPP, T = Tiles<S>::T;
     constexpr int RT = T / RPP;   // rows per thread
     __shared__ double sV[T * S];
@@ -279,10 +281,12 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
         if (PREC && !stop) sty.load(Yp + r0 * S, rows * S);
         double xo[XD ? RT : 1];
         if constexpr (XD) {
+            if (xd) {
 #pragma unroll
-            for (int k = 0; k < RT; ++k) {
-                const int rl = rl0 + k * RPP;
-                xo[k] = stream_load(Xt + (r0 + (rl < rows ? rl : 0)) * S + j);
+                for (int k = 0; k < RT; ++k) {
+                    const int rl = rl0 + k * RPP;
+                    xo[k] = stream_load(Xt + (r0 + (rl < rows ? rl : 0)) * S + j);
+                }
             }
         }
         if (!stop) stv.store(sV);
@@ -295,10 +299,12 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dirupdate(int64_t n, double* __res
             if (rl >= rows) continue;
             const int64_t g = (r0 + rl) * S + j;
             if constexpr (XD) {
-                double tx = 0.0;
+                if (xd) {
+                    double tx = 0.0;
 #pragma unroll
-                for (int l = 0; l < S; ++l) tx += sP[rl * S + l] * al[l];
-                stream_store(Xt + g, xo[k] + tx);
+                    for (int l = 0; l < S; ++l) tx += sP[rl * S + l] * al[l];
+                    stream_store(Xt + g, xo[k] + tx);
+                }
             }
             if (stop) continue;
             double w = 0.0;

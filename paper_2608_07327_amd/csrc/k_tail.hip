@@ -37,6 +37,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_xi(const double* __restri
     }
     __shared__ double sm[SxsWs<S>::DOUBLES];
     __shared__ int smi[SxsWs<S>::INTS];
+    if (threadIdx.x == 0) st->xt_skip = 0;
     tail_xi_body<S>(part, nwg, tri_count(S), st, sm, smi);
     __syncthreads();
     // the update runs unless this tail stopped the loop (P^T A P not SPD)
@@ -47,7 +48,7 @@ template <int S>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail_qr(const double* __restrict__ part, int nwg,
                                                           DevState* __restrict__ st,
                                                           double* __restrict__ hist, int setup) {
-    if (st->done) return;
+    if (st->done) return;   // (a resume is launched with done cleared)
     __shared__ double sm[SxsWs<S>::DOUBLES];
     __shared__ int smi[SxsWs<S>::INTS];
     tail_qr_body<S>(part, nwg, tri_count(S) + S, st, hist, setup, sm, smi);
@@ -61,14 +62,20 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_ls(const double* __restri
     tail_ls_body<S>(part, nwg, 2 * tri_count(S + 1), n, st, sm, smi);
 }
 
-// ||r|| of the LS combination and the accept test (the stop test on the combination)
+// ||r|| of the LS combination and the accept test (the stop test on the
+// combination).  After a DONE_LS stop (tol_initial > tol) the solve ends when
+// the combination is accepted or the best column itself meets tol, and the
+// loop resumes otherwise (done back to 0).
 __global__ void k_tail_accept(const double* __restrict__ part, int nwg, DevState* __restrict__ st) {
     __shared__ double out[1], tmp[TAIL_THREADS];
     reduce_partials(part, nwg, 1, 1, out, tmp);
     if (threadIdx.x == 0) {
         const double rel = sqrt(out[0]) / st->bnorm;
+        const int done = st->done;
         st->rel_ls = rel;
-        st->accepted = (st->done == DONE_CONVERGED) && st->ls_ok && finite_d(rel) && (rel < st->tol);
+        const bool ok = st->ls_ok && finite_d(rel) && (rel < st->tol);
+        st->accepted = (done == DONE_CONVERGED || done == DONE_LS) && ok;
+        if (done == DONE_LS) st->done = (ok || st->nu_h < st->tol) ? DONE_CONVERGED : DONE_RUNNING;
     }
 }
 
@@ -206,6 +213,7 @@ __global__ void k_state_init(DevState* st, int s, int max_iter, double tol, doub
         st->tau = tau;
         st->n_hist = n_hist;
         st->width = s;
+        st->ls_inloop = tol0 > tol;
     }
     if (threadIdx.x < MB_SM) st->active[threadIdx.x] = threadIdx.x < s;
 }

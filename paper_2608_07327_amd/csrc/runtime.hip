@@ -374,6 +374,8 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
                             double* prof_ms, double* prof_n) {
     const int m = p.poll_every > 0 ? p.poll_every : auto_poll(c, cg);
     const double t0 = now_ms();
+    // iterations done before this call (a loop resumed after a least squares)
+    const int64_t it0 = c.st_host->iter;
     if (p.profile) {
         // The iterations are launched directly, with HIP events between the
         // kernels of every iteration (the per-step timing of Sec. 3, Table 2;
@@ -409,7 +411,7 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
         CK(hipStreamSynchronize(c.stream));
         *ms_loop = now_ms() - t0;
         CKS(read_state(c));
-        const int64_t ran = std::min<int64_t>(c.st_host->iter, issued);
+        const int64_t ran = std::min<int64_t>(c.st_host->iter - it0, issued);
         for (int64_t i = 0; i < ran; ++i) {
             const hipEvent_t* ev = &c.pev[i * EV];
             for (int k = 0; k + 1 < EV; ++k) {
@@ -540,20 +542,45 @@ static mbpcg_status run_mbpcg(Ctx& c, const double* b, double* x, const double* 
 
     double ms_loop = 0.0, prof_ms = 0.0, prof_n = 0.0;
     for (double& v : c.phase_ms) v = 0.0;
-    CKS(run_loop(c, pl, p, 0, &ms_loop, &prof_ms, &prof_n));
-    CKS(read_state(c));
+    // least squares of the termination: c^, x = D^-1 (X~ + X0) c^ and the
+    // accept test (its partials avoid part_b, which a resumed Cholesky QR
+    // still reads)
+    auto least_squares = [&]() -> mbpcg_status {
+        CK(launch_ls_gram(S, pl.nwg_ls, c.n, b, c.R, c.d, c.part_a, c.st, c.stream));
+        CK(launch_tail_ls(S, pl.nwg_ls, c.n, c.part_a, c.st, c.stream));
+        CK(launch_ls_apply(S, pl.nwg_e, c.n, c.Xt, c.X0, c.R, b, c.d, x, c.part_c, c.st,
+                           c.stream));
+        CK(launch_tail_accept(pl.nwg_e, c.part_c, c.st, c.stream));
+        return MBPCG_OK;
+    };
+    bool ls_done = false;
+    for (;;) {
+        double ms = 0.0;
+        CKS(run_loop(c, pl, p, 0, &ms, &prof_ms, &prof_n));
+        ms_loop += ms;
+        CKS(read_state(c));
+        if (c.st_host->done != DONE_LS) break;
+        // tol_initial > tol (Alg. 1's two tests): the best column met
+        // tol_initial, so this iteration's combination is tried; the solve
+        // ends if it meets tol or the best column does, else the loop goes on
+        // from this iteration's Cholesky QR and direction update
+        CKS(least_squares());
+        CKS(read_state(c));
+        ls_done = c.st_host->done != DONE_RUNNING;
+        if (ls_done) break;
+        const double* pr;
+        int pn;
+        CK(staged_partials(c, pl.nwg_upd, tri_count(S) + S, c.part_b, &pr, &pn));
+        CK(launch_tail_qr(S, pn, pr, c.st, nullptr, 2, c.stream));
+        CK(launch_dirupdate(S, pl.nwg_dir, c.n, c.W, c.P, c.Plo, kind, 0, c.st, c.stream,
+                            pl.bs ? c.Y : nullptr, c.Xt));
+    }
     const int done = c.st_host->done;
 
     if (done == DONE_ZERO_RHS) {
         CK(hipMemsetAsync(x, 0, sizeof(double) * c.n, c.stream));
     } else {
-        if (done == DONE_CONVERGED) {
-            CK(launch_ls_gram(S, pl.nwg_ls, c.n, b, c.R, c.d, c.part_a, c.st, c.stream));
-            CK(launch_tail_ls(S, pl.nwg_ls, c.n, c.part_a, c.st, c.stream));
-            CK(launch_ls_apply(S, pl.nwg_e, c.n, c.Xt, c.X0, c.R, b, c.d, x, c.part_b, c.st,
-                               c.stream));
-            CK(launch_tail_accept(pl.nwg_e, c.part_b, c.st, c.stream));
-        }
+        if (done == DONE_CONVERGED && !ls_done) CKS(least_squares());
         CK(launch_select(S, c.n, c.Xt, c.X0, c.d, x, c.st, 0, c.stream));
         if (true_resid) {
             // partial sums of ||b - A v||^2 (original A) into part_a
