@@ -158,6 +158,21 @@ mbpcg_status mbpcg_cg_solve(mbpcg_ctx ctx, const double* b, double* x, mbpcg_mem
 mbpcg_status mbpcg_block_product(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond,
                                  const double* P, double* Q, double* C);
 
+/* mbpcg_block_product without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, arithmetic and results
+ * (Q bitwise; C bitwise when the grid below is not lowered).  CSR contexts
+ * only (MBPCG_ERR_UNSUPPORTED for dense ones).  The Gram's per-workgroup
+ * partial sums go to a fixed 4 MiB device array, one per GPU, held until the
+ * process ends; the product's grid is lowered where needed so that they fit
+ * (at most 992 workgroups at s = 32), and a call whose partials would not fit
+ * returns MBPCG_ERR_UNSUPPORTED with mbpcg_last_error set.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU race (serialise
+ * them).  The context's own buffers (scaling, state) are allocated by
+ * mbpcg_create_csr. */
+mbpcg_status mbpcg_block_product_noalloc(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond,
+                                         const double* P, double* Q, double* C);
+
 /* Time `reps` launches of the block-product kernel of mbpcg_block_product with
  * HIP events on the context's stream; *ms_avg receives the mean duration. */
 mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps,

@@ -12,6 +12,8 @@ mbpcg_status ctx_init_common(Ctx& c, hipStream_t user_stream);
 mbpcg_status solve_entry(Ctx& c, const double* b, double* x, mbpcg_mem mem, const mbpcg_params& p,
                          mbpcg_info& info, int cg);
 mbpcg_status block_product_entry(Ctx& c, int s, int jacobi, const double* P, double* Q, double* C);
+mbpcg_status block_product_noalloc_entry(Ctx& c, int s, int jacobi, const double* P, double* Q,
+                                         double* C);
 mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, double* Q,
                                       double* ms_avg);
 mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out);
@@ -106,6 +108,9 @@ mbpcg_status mbpcg_create_csr(mbpcg_ctx* out, int64_t n, int64_t nnz, const int3
     if (st == MBPCG_OK) st = alloc((void**)&c.rowptr, sizeof(int32_t) * (n + 1));
     if (st == MBPCG_OK) st = alloc((void**)&c.colind, sizeof(int32_t) * nnz);
     if (st == MBPCG_OK) st = alloc((void**)&c.vals, sizeof(double) * nnz);
+    // the scaled copy of the values, here rather than at the first solve, so
+    // that the allocation-free block product finds it
+    if (st == MBPCG_OK) st = alloc((void**)&c.vals_s, sizeof(double) * nnz);
     const hipMemcpyKind kind = mem == MBPCG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     if (st == MBPCG_OK && hipMemcpy(c.rowptr, rowptr, sizeof(int32_t) * (n + 1), kind) != hipSuccess)
         st = MBPCG_ERR_HIP;
@@ -228,6 +233,14 @@ mbpcg_status mbpcg_block_product(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond
     if (!pow2_width(s)) return MBPCG_ERR_UNSUPPORTED;
     if (precond != MBPCG_PRECOND_NONE && precond != MBPCG_PRECOND_JACOBI) return MBPCG_ERR_INVALID_ARG;
     return mb::block_product_entry(ctx->c, s, precond == MBPCG_PRECOND_JACOBI, P, Q, C);
+}
+
+mbpcg_status mbpcg_block_product_noalloc(mbpcg_ctx ctx, int32_t s, mbpcg_precond precond,
+                                         const double* P, double* Q, double* C) {
+    if (!ctx || !P || !Q || !C) return MBPCG_ERR_INVALID_ARG;
+    if (!pow2_width(s)) return MBPCG_ERR_UNSUPPORTED;
+    if (precond != MBPCG_PRECOND_NONE && precond != MBPCG_PRECOND_JACOBI) return MBPCG_ERR_INVALID_ARG;
+    return mb::block_product_noalloc_entry(ctx->c, s, precond == MBPCG_PRECOND_JACOBI, P, Q, C);
 }
 
 mbpcg_status mbpcg_time_block_product(mbpcg_ctx ctx, int32_t s, int32_t reps, const double* P,

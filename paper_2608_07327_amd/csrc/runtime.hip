@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace mb {
 
@@ -867,6 +868,89 @@ mbpcg_status block_product_entry(Ctx& c, int s, int jacobi, const double* P, dou
     CK(launch_product(c, pl, P, Q, c.part_a, c.st));
     hipError_t launch_gram_out(int S, int nwg, const double* part, double* C, hipStream_t s);
     CK(launch_gram_out(pl.S, pl.nwg_prod, c.part_a, C, c.stream));
+    CK(hipStreamSynchronize(c.stream));
+    return MBPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The block product without any allocation, for callers that cannot allocate
+// (code under graph capture, serving loops).  Its Gram partial sums go to a
+// fixed device array instead of the context's buffers; each GPU holds its
+// own copy until the process ends, and every call on that GPU shares it, so
+// calls that overlap on one GPU race.  The product's grid is capped so that
+// its partials fit; every slot a call reads is written by that call first.
+// ---------------------------------------------------------------------------
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = 1 << 19;   // 4 MiB of partial sums
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[256] = {};
+
+// device address of this GPU's scratch array (the device must be current)
+static mbpcg_status scratch_address(Ctx& c, double** out) {
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 256) {
+        c.err = "device index out of range for the fixed scratch array";
+        return MBPCG_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        CK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MBPCG_OK;
+}
+
+mbpcg_status block_product_noalloc_entry(Ctx& c, int s, int jacobi, const double* P, double* Q,
+                                         double* C) {
+    if (c.dense) {
+        c.err = "the allocation-free block product takes CSR matrices only (the dense product's "
+                "split-K partials exceed the fixed scratch array)";
+        return MBPCG_ERR_UNSUPPORTED;
+    }
+    if (!c.vals_s) {
+        c.err = "context has no scaled-value buffer";
+        return MBPCG_ERR_UNSUPPORTED;
+    }
+    CK(hipSetDevice(c.device));
+    double* part = nullptr;
+    CKS(scratch_address(c, &part));
+    CK(hipEventRecord(c.ev_user, c.user_stream));
+    CK(hipStreamWaitEvent(c.stream, c.ev_user, 0));
+    // the launch plan of the allocating entry (tuned shape and grid); the
+    // grid is lowered to the largest multiple of 8 (the XCD-aware tile order)
+    // whose partials fit when it would not fit
+    const Plan pl = make_plan(c, s, DENSE_F64);
+    const int S = pl.S;
+    const int E = tri_count(S);
+    const SpmmShape sh = pl.sp;
+    int64_t nwg = pl.nwg_spmm;
+    const int64_t cap = NOALLOC_SCRATCH_DOUBLES / E / 8 * 8;
+    if (cap < 1) {
+        c.err = "block width too large for the fixed scratch array";
+        return MBPCG_ERR_UNSUPPORTED;
+    }
+    nwg = std::max<int64_t>(1, std::min(nwg, cap));
+    if (nwg * E > NOALLOC_SCRATCH_DOUBLES) {
+        c.err = "Gram partial sums exceed the fixed scratch array";
+        return MBPCG_ERR_UNSUPPORTED;
+    }
+    // scaling of the matrix (Sec. 1) into the context's buffers, as the
+    // allocating entry does
+    CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
+    CK(launch_diag_csr(csr_of(c, false), jacobi, c.d, c.st, c.stream));
+    if (jacobi) {
+        CK(launch_scale_csr(csr_of(c, false), c.d, c.vals_s, c.stream));
+    } else {
+        CK(hipMemcpyAsync(c.vals_s, c.vals, sizeof(double) * c.nnz, hipMemcpyDeviceToDevice,
+                          c.stream));
+    }
+    CK(launch_state_init(c.st, s, 1, 1.0, 1.0, 1e-12, 0, c.stream));
+    CK(launch_spmm(S, sh, (int)nwg, csr_of(c, true), P, Q, part, c.st, c.stream));
+    CK(launch_gram_out(S, (int)nwg, part, C, c.stream));
     CK(hipStreamSynchronize(c.stream));
     return MBPCG_OK;
 }

@@ -24,7 +24,8 @@ FP64, FP32_IR, BF16_IR = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 
 EXPORTS = ("mbpcg_autotune", "mbpcg_default_params", "mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve",
-           "mbpcg_cg_solve", "mbpcg_block_product", "mbpcg_time_block_product",
+           "mbpcg_cg_solve", "mbpcg_block_product", "mbpcg_block_product_noalloc",
+           "mbpcg_time_block_product",
            "mbpcg_solve_batch", "mbpcg_stream_copy", "mbpcg_destroy", "mbpcg_status_str",
            "mbpcg_last_error", "mbpcg_tile_shapes", "mbpcg_set_tile_shape")
 
@@ -95,6 +96,7 @@ def load():
     L.mbpcg_solve.argtypes = [vp, vp, vp, C.c_int, C.POINTER(Params), C.POINTER(Info)]
     L.mbpcg_cg_solve.argtypes = [vp, vp, vp, C.c_int, C.POINTER(Params), C.POINTER(Info)]
     L.mbpcg_block_product.argtypes = [vp, i32, C.c_int, vp, vp, vp]
+    L.mbpcg_block_product_noalloc.argtypes = [vp, i32, C.c_int, vp, vp, vp]
     L.mbpcg_time_block_product.argtypes = [vp, i32, i32, vp, vp, C.POINTER(C.c_double)]
     L.mbpcg_solve_batch.argtypes = [i32, C.POINTER(System), C.POINTER(Params), C.POINTER(Info),
                                     C.c_int, vp]
@@ -109,7 +111,8 @@ def load():
     L.mbpcg_last_error.argtypes = [vp]
     L.mbpcg_last_error.restype = C.c_char_p
     for f in ("mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve", "mbpcg_cg_solve",
-              "mbpcg_block_product", "mbpcg_time_block_product", "mbpcg_solve_batch",
+              "mbpcg_block_product", "mbpcg_block_product_noalloc", "mbpcg_time_block_product",
+              "mbpcg_solve_batch",
               "mbpcg_stream_copy", "mbpcg_autotune", "mbpcg_tile_shapes", "mbpcg_set_tile_shape"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -288,6 +291,13 @@ class Solver:
         """Q = A~ P and lower triangle of C = P^T Q (device tensors)."""
         st = load().mbpcg_block_product(self._h, int(s), int(precond), P.data_ptr(), Q.data_ptr(),
                                         Cmat.data_ptr())
+        _check(st, self._h, allow=(OK,))
+
+    def block_product_noalloc(self, P, Q, Cmat, s, precond=PRECOND_JACOBI):
+        """block_product without any allocation (fixed per-GPU scratch array;
+        CSR contexts only; overlapping calls on one GPU race)."""
+        st = load().mbpcg_block_product_noalloc(self._h, int(s), int(precond), P.data_ptr(),
+                                                Q.data_ptr(), Cmat.data_ptr())
         _check(st, self._h, allow=(OK,))
 
     def autotune(self, s):
