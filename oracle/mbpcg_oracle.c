@@ -167,8 +167,17 @@ void or_matmul_block(const or_matrix* A, int k, const double* X, double* Y)
 {
     int64_t n = A->n;
     if (A->dense && A->lo) {
-        float* acc = (float*)calloc((size_t)(n * k), sizeof(float));
+        /* FP32 sums over the columns: sequential in mode 0; in mode 1 blocks
+         * of OR_BLOCK columns are summed and the block sums combined as a
+         * binary counter, all in FP32 */
+        const size_t E = (size_t)(n * k);
+        float* acc = (float*)calloc(E, sizeof(float));
         float* xr = (float*)malloc(sizeof(float) * (size_t)k);
+        float* lvl = NULL;
+        int used[OR_LEVELS];
+        memset(used, 0, sizeof(used));
+        int in_block = 0;
+        if (g_sum_mode == 1) lvl = (float*)calloc(E * OR_LEVELS, sizeof(float));
         for (int64_t c = 0; c < n; ++c) {
             const double* col = A->a + c * A->lda;
             for (int j = 0; j < k; ++j) xr[j] = (float)round_lo(A->lo, X[c * k + j]);
@@ -177,8 +186,26 @@ void or_matmul_block(const or_matrix* A, int k, const double* X, double* Y)
                 float* yr = acc + r * k;
                 for (int j = 0; j < k; ++j) yr[j] = yr[j] + a * xr[j];
             }
+            if (g_sum_mode == 1 && (++in_block == OR_BLOCK || c == n - 1)) {
+                int l = 0;   /* acc holds a block sum: carry it up the counter */
+                while (l < OR_LEVELS && used[l]) {
+                    for (size_t e = 0; e < E; ++e) acc[e] = lvl[(size_t)l * E + e] + acc[e];
+                    used[l] = 0;
+                    ++l;
+                }
+                memcpy(lvl + (size_t)l * E, acc, sizeof(float) * E);
+                used[l] = 1;
+                memset(acc, 0, sizeof(float) * E);
+                in_block = 0;
+            }
         }
-        for (int64_t e = 0; e < n * k; ++e) Y[e] = (double)acc[e];
+        if (g_sum_mode == 1) {
+            for (int l = 0; l < OR_LEVELS; ++l)
+                if (used[l])
+                    for (size_t e = 0; e < E; ++e) acc[e] = acc[e] + lvl[(size_t)l * E + e];
+            free(lvl);
+        }
+        for (size_t e = 0; e < E; ++e) Y[e] = (double)acc[e];
         free(xr);
         free(acc);
         return;

@@ -10,9 +10,11 @@ b ~ N(0,1), no preconditioning.  Stored:
   the two solutions;
 * for s in {8, 16, 32}: the oracle's iterative refinement to 1e-10 with FP32
   inner products emulated (A and the blocks rounded to FP32, products
-  accumulated in FP32), i.e. the arithmetic of the GPU's FP32 path in the
-  oracle's summation order -- outer and inner iteration counts, the FP64
-  residual, the error against the reference, and sampled x.
+  accumulated in FP32), i.e. the arithmetic of the GPU's FP32 path, once
+  with sequential FP32 sums over the 16384 columns ("ir_fp32") and once
+  with blocked-pairwise FP32 sums ("ir_fp32_pairwise") -- outer and inner
+  iteration counts, the FP64 residual, the error against the reference, and
+  sampled x.
 
     python tests/golden/make_dense_mixed_golden.py [--n 16384] [--s 8,16,32] [--jobs 4]
 
@@ -50,6 +52,7 @@ def job(task):
     b = W.rhs(n, W.CFG_DENSE_MIXED)
     seed = W.uniform_block_seed(W.CFG_DENSE_MIXED, s)
     t = time.time()
+    O.set_variant("pairwise" if kind == "ir_pairwise" else "seq")
     if kind == "ref":
         # A is symmetric: its transpose view is the column-major matrix, no copy
         x, info, _ = O.mbpcg_solve(np.asarray(A).T, b, s, tol=REF_TOL, jacobi=False, seed=seed)
@@ -66,7 +69,10 @@ def main():
     ap.add_argument("--s", default="8,16,32")
     ap.add_argument("--jobs", type=int, default=4)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--kinds", default="ref,ir,ir_pairwise",
+                    help="which runs to add when missing from the output")
     args = ap.parse_args()
+    kinds = set(args.kinds.split(","))
     n = args.n
     out = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                    f"dense_mixed_{n}.json")
@@ -82,18 +88,23 @@ def main():
                 "sample_index": idx.tolist(), "ref_s": REF_S, "ref_tol": REF_TOL,
                 "ir_tol": IR_TOL, "inner_tol": INNER_TOL})
     rec.setdefault("ir_fp32", {})
+    rec.setdefault("ir_fp32_pairwise", {})
     print(f"inputs {time.time() - t:.0f} s", flush=True)
     x_np = None
-    if "ref" not in rec:
+    if "ref" not in rec and "ref" in kinds:
         t = time.time()
         x_np = np.linalg.solve(A, b)
         print(f"numpy solve {time.time() - t:.0f} s", flush=True)
     path = f"/dev/shm/mbpcg_golden_dense_{n}_{os.getpid()}.npy"
     np.save(path, A)
     del A
-    tasks = [] if "ref" in rec else [(path, n, "ref", REF_S)]
-    tasks += [(path, n, "ir", s) for s in [int(v) for v in args.s.split(",")]
-              if str(s) not in rec["ir_fp32"]]
+    tasks = [] if ("ref" in rec or "ref" not in kinds) else [(path, n, "ref", REF_S)]
+    widths = [int(v) for v in args.s.split(",")]
+    if "ir" in kinds:
+        tasks += [(path, n, "ir", s) for s in widths if str(s) not in rec["ir_fp32"]]
+    if "ir_pairwise" in kinds:
+        tasks += [(path, n, "ir_pairwise", s) for s in widths
+                  if str(s) not in rec["ir_fp32_pairwise"]]
     tasks.sort(key=lambda q: -q[3])
     x_ref = None
     irs = {}
@@ -115,12 +126,13 @@ def main():
                         "vs_numpy_solve": float(np.linalg.norm(x - x_np) / np.linalg.norm(x_np)),
                         "numpy_x_sample": x_np[idx].tolist(),
                     }
-                    for s2, (i2, x2) in list(irs.items()):
-                        rec["ir_fp32"][str(s2)]["err_vs_ref"] = float(
+                    for (key, s2), (i2, x2) in list(irs.items()):
+                        rec[key][str(s2)]["err_vs_ref"] = float(
                             np.linalg.norm(x2 - x_ref) / np.linalg.norm(x_ref))
                 else:
-                    irs[s] = (info, x)
-                    rec["ir_fp32"][str(s)] = {
+                    key = "ir_fp32" if kind == "ir" else "ir_fp32_pairwise"
+                    irs[(key, s)] = (info, x)
+                    rec[key][str(s)] = {
                         "seed": W.uniform_block_seed(W.CFG_DENSE_MIXED, s),
                         "outer_iterations": info["outer_iterations"],
                         "iterations": info["iterations"],
@@ -130,6 +142,11 @@ def main():
                         "err_vs_ref": (float(np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref))
                                        if x_ref is not None else None),
                     }
+                    if x_ref is None and "ref" in rec:
+                        # the reference of an earlier invocation: its sampled entries
+                        xr = np.asarray(rec["ref"]["x_sample"])
+                        rec[key][str(s)]["err_vs_ref_sampled"] = float(
+                            np.linalg.norm(x[idx] - xr) / np.linalg.norm(xr))
                 json.dump(rec, open(out, "w"))
     finally:
         os.unlink(path)

@@ -107,3 +107,33 @@ def check(x, info, xo, io, xps, ips, tol, floor=1e-10, what=""):
     if io["status"] == 0:
         assert info["rel_res_true"] < 2 * tol, (what, info["rel_res_true"])
     return err
+
+
+def check_golden(x_sample, info, o, tol, floor=1e-10, what=""):
+    """The same contract against a stored oracle record (golden file written
+    by tests/golden/*: the reference run's diagnostics, the three variants'
+    counts and sampled x, the noise floor over the full vectors).  x_sample
+    is the GPU's x at the record's sample indices."""
+    assert info["status"] == o["status"], (what, info["status"], o["status"])
+    its = [o["iterations"], o["pairwise_iterations"], o["fma_iterations"]]
+    near = abs(o["rel_res_best"] - tol) <= 0.01 * tol
+    band = max(its) - min(its) + (1 if near else 0)
+    assert abs(info["iterations"] - o["iterations"]) <= band, (what, info["iterations"], its)
+    err = None
+    for key, xsk in (("iterations", "x_sample"), ("pairwise_iterations", "pairwise_x_sample"),
+                     ("fma_iterations", "fma_x_sample")):
+        if info["iterations"] == o[key]:
+            xr = np.asarray(o[xsk])
+            err = float(np.linalg.norm(np.asarray(x_sample) - xr) / np.linalg.norm(xr))
+            assert err <= max(floor, 10 * o["noise_floor"]), (what, key, err, o["noise_floor"])
+            if key == "iterations":
+                for k2 in ("final_width", "deflations"):
+                    if k2 in info:
+                        assert info[k2] == o[k2], (what, k2, info[k2], o[k2])
+            if (o["used_fallback"] == o["pairwise_used_fallback"] == o["fma_used_fallback"]
+                    and "used_fallback" in info):
+                assert info["used_fallback"] == o["used_fallback"], (what, info, o)
+            break
+    if o["status"] == 0:
+        assert info["rel_res_true"] < 2 * tol, (what, info["rel_res_true"])
+    return err
