@@ -1,0 +1,90 @@
+"""Per-kernel summary of rocprofv3 runs of the benchmark: the average duration
+of the launches that did work (from a --kernel-trace database), HBM bytes
+per launch from a FETCH_SIZE and a WRITE_SIZE counter pass (each scaled by
+what the counter reads for the library's 1 GiB streaming copy, which the
+benchmark runs), and optionally the MFMA counters of a third pass.
+
+    python3 -m paper_2608_07327_amd.rocprof_summary TRACE_DB FETCH_CSV WRITE_CSV [MFMA_CSV]
+
+Launches that exit at once (iterations issued after the solve stopped) are
+left out: a kernel's launches shorter than a fifth of its longest are
+dropped.  MFMA: executed MFMA flops per launch from
+SQ_INSTS_VALU_MFMA_MOPS_* (x 512), and the MFMA-busy share of the SIMD
+cycles (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE per XCD times the
+SIMDs)."""
+import argparse, collections, csv, re, sqlite3, statistics
+
+ap = argparse.ArgumentParser()
+ap.add_argument("db"); ap.add_argument("fetch"); ap.add_argument("write")
+ap.add_argument("mfma", nargs="?")
+ap.add_argument("--filter", default="")
+ap.add_argument("--simds", type=int, default=1024)
+ap.add_argument("--xcds", type=int, default=8)
+ap.add_argument("--top", type=int, default=30)
+a = ap.parse_args()
+
+def short(name):
+    name = re.sub(r'\(.*$', '', name)
+    return name.replace('void ', '').replace('mb::', '')
+
+con = sqlite3.connect(a.db)
+cur = con.cursor()
+tab = [r[0] for r in cur.execute("select name from sqlite_master where name like 'rocpd_kernel_dispatch%'")][0]
+stab = [r[0] for r in cur.execute("select name from sqlite_master where name like 'rocpd_info_kernel_symbol%'")][0]
+scols = [r[1] for r in cur.execute(f"pragma table_info({stab})")]
+names = {r[0]: r[1] for r in cur.execute(f"select id, {'display_name' if 'display_name' in scols else 'kernel_name'} from {stab}")}
+dur = collections.defaultdict(list)
+for kid, s, e in cur.execute(f"select kernel_id, start, end from {tab}"):
+    dur[short(names.get(kid, str(kid)))].append((e - s) / 1000.0)
+
+def load(path):
+    per = collections.defaultdict(dict)   # (kernel, dispatch) -> counter -> value
+    t = {}
+    for r in csv.DictReader(open(path)):
+        key = (short(r['Kernel_Name']), int(r['Dispatch_Id']))
+        per[key][r['Counter_Name']] = per[key].get(r['Counter_Name'], 0.0) + float(r['Counter_Value'])
+        t[key] = (int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1000.0
+    out = collections.defaultdict(list)
+    for key, cs in per.items():
+        out[key[0]].append((cs, t[key]))
+    return out
+
+F, Wr = load(a.fetch), load(a.write)
+Mf = load(a.mfma) if a.mfma else {}
+cf = max(c['FETCH_SIZE'] for c, _ in F['k_stream_copy'])
+cw = max(c['WRITE_SIZE'] for c, _ in Wr['k_stream_copy'])
+ff, fw = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
+print(f"calibration (1 GiB k_stream_copy): FETCH_SIZE {cf:.0f} KiB (factor {ff:.3f}), "
+      f"WRITE_SIZE {cw:.0f} KiB (factor {fw:.3f})")
+
+def busy(xs, key):
+    if not xs: return []
+    m = max(key(x) for x in xs)
+    return [x for x in xs if key(x) >= 0.2 * m]
+
+rows = []
+for k in sorted(set(dur) | set(F)):
+    if a.filter and not re.search(a.filter, k): continue
+    d = busy(dur.get(k, []), lambda x: x)
+    f = busy(F.get(k, []), lambda x: x[1])
+    w = busy(Wr.get(k, []), lambda x: x[1])
+    avg = statistics.mean(d) if d else float('nan')
+    fm = statistics.mean(c['FETCH_SIZE'] for c, _ in f) * 1024 * ff / 1e6 if f else float('nan')
+    wm = statistics.mean(c['WRITE_SIZE'] for c, _ in w) * 1024 * fw / 1e6 if w else float('nan')
+    extra = ""
+    if Mf.get(k):
+        m = busy(Mf[k], lambda x: x[1])
+        busyc = sum(c.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) for c, _ in m)
+        gui = sum(c.get('GRBM_GUI_ACTIVE', 0) for c, _ in m)
+        mops = {p: sum(c.get(f'SQ_INSTS_VALU_MFMA_MOPS_{p}', 0) for c, _ in m) / len(m) for p in ('F64', 'F32', 'BF16')}
+        # GRBM_GUI_ACTIVE is counted on every XCD and summed
+        util = 100.0 * busyc / (gui / a.xcds * a.simds) if gui else float('nan')
+        mt = statistics.mean(t for _, t in m)
+        fl = {p: v * 512 for p, v in mops.items() if v}
+        extra = f"  MFMA busy {util:5.1f}%" + "".join(f"  {p} {v/1e9:.1f} GFLOP/launch ({v/(mt*1e-6)/1e12:.1f} TFLOP/s)" for p, v in fl.items())
+    rows.append((sum(d), k, len(d), avg, fm, wm, extra))
+rows.sort(reverse=True)
+print(f"| kernel | launches | avg us | fetch MB/launch | write MB/launch | MFMA |")
+print("|---|---:|---:|---:|---:|---|")
+for tot, k, nl, avg, fm, wm, extra in rows[:a.top]:
+    print(f"| `{k[:80]}` | {nl} | {avg:.2f} | {fm:.1f} | {wm:.1f} | {extra.strip()} |")
