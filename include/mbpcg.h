@@ -229,6 +229,43 @@ mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
                                const mbpcg_params* common, mbpcg_info* per_system,
                                mbpcg_mem mem, void* hip_stream);
 
+/* A batch context: the systems of mbpcg_solve_batch uploaded once (CSR and b
+ * copied into library-owned device memory; the caller's x pointers receive
+ * each solve's results), with the persistent kernel captured in a HIP graph
+ * that every solve replays.  mbpcg_solve_batch is create + solve + destroy.
+ * Validation as in mbpcg_solve_batch; errors: mbpcg_last_error(NULL). */
+typedef struct mbpcg_batch_s* mbpcg_batch;
+
+mbpcg_status mbpcg_batch_create(mbpcg_batch* batch, int32_t nsys, const mbpcg_system* systems,
+                                mbpcg_mem mem, void* hip_stream);
+
+/* Solve every system of the batch with parameters `common` (as in
+ * mbpcg_solve_batch), writing x through the pointers given at create and
+ * per_system[nsys] (may be NULL).  Returns when the batch has finished. */
+mbpcg_status mbpcg_batch_solve(mbpcg_batch batch, const mbpcg_params* common,
+                               mbpcg_info* per_system, void* hip_stream);
+
+/* Result of mbpcg_batch_autotune. */
+typedef struct {
+    int32_t workgroups;        /* grid of the persistent kernel chosen                   */
+    int32_t classes;           /* (block width, row-length class) pairs in the batch     */
+    int32_t two_slot_classes;  /* classes given two lane groups per row                  */
+    int32_t trials;            /* timed trial solves run                                 */
+    double ms;                 /* kernel time of the best trial (capped at 12 iterations) */
+} mbpcg_batch_tuning;
+
+/* Choose the batched kernel's free parameters by timed trials (solves capped
+ * at 12 iterations, which overwrite x): lane groups per CSR row for each
+ * (padded width, row-length class) of the batch -- [0, 16), [16, 48), 48 or
+ * more nonzeros per row -- and the grid (all co-resident workgroups, 3/4,
+ * 1/2).  The per-class choice is kept for the process: a later batch whose
+ * classes are all known skips those trials.  Later solves of this batch use
+ * the choice. */
+mbpcg_status mbpcg_batch_autotune(mbpcg_batch batch, const mbpcg_params* common,
+                                  mbpcg_batch_tuning* out);
+
+void mbpcg_batch_destroy(mbpcg_batch batch);
+
 /* Copy `bytes` bytes device-to-device with the library's plain streaming copy
  * kernel on `hip_stream`; used to calibrate hardware byte counters. */
 mbpcg_status mbpcg_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -960,7 +961,9 @@ __global__ void k_batch_state_init(int nsys, DevState* st, const BSys* sys, int 
 }
 
 // ---------------------------------------------------------------------------
-// host side
+// host side: a batch context uploads the systems once and keeps its captured
+// graph; each solve writes the kernel's arguments, resets the per-system
+// states and replays the graph
 // ---------------------------------------------------------------------------
 struct BatchBufs {
     std::vector<void*> ptrs;
@@ -975,33 +978,80 @@ struct BatchBufs {
     }
 };
 
-// slots per row: a second lane group per row pays off for long rows
-static int batch_slots(const mbpcg_system& y) { return (y.nnz >= 16 * y.n) ? 2 : 1; }
+// row-length class of a system (average nonzeros per row) for the choice of
+// lane groups per row: [0, 16), [16, 48), [48, ...)
+static int row_class(int64_t n, int64_t nnz) {
+    const double r = (double)nnz / (double)std::max<int64_t>(n, 1);
+    return r < 16.0 ? 0 : (r < 48.0 ? 1 : 2);
+}
+// untuned: a second lane group per row for long rows
+static int default_slots(int cls) { return cls == 0 ? 1 : 2; }
 
-mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_params& p,
-                         mbpcg_info* per_system, mbpcg_mem mem, hipStream_t user_stream,
-                         std::string& err) {
+// tuned lane groups per row, per (padded width, row class), kept for the
+// process: a later batch whose classes are all known skips those trials
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, int> g_slot_cache;
+
+// the kernel's arguments live in one device symbol: one batched solve at a
+// time in this process
+static std::mutex g_batch_mu;
+
+struct BatchCtx {
+    int device = 0;
+    int nsys = 0;
+    mbpcg_mem mem = MBPCG_MEM_DEVICE;
+    std::vector<mbpcg_system> sys;   // the caller's descriptors (x receives the results)
+    std::vector<BSys> hs;
+    int items = 0, pitems = 0;
+    BatchBufs B;
+    BArgs a;                 // device pointers; the per-solve fields are set by each solve
+    BSys* d_sys = nullptr;
+    double* d_x = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr, ev0 = nullptr, ev1 = nullptr;
+    int resident = 0;        // workgroups that fit on the GPU at once
+    int grid = 0;            // grid of the persistent kernel
+    hipGraphExec_t exec = nullptr;
+    int exec_grid = 0;
+    long long* d_ts = nullptr;
+    int64_t ts_cap = 0;
+    std::string err;
+    ~BatchCtx() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (d_ts) (void)hipFree(d_ts);
+        if (ev) (void)hipEventDestroy(ev);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+BatchCtx* batch_new() { return new (std::nothrow) BatchCtx; }
+void batch_delete(BatchCtx* c) { delete c; }
+const char* batch_error(const BatchCtx* c) { return c ? c->err.c_str() : ""; }
+
 #define BCK(expr)                                                              \
     do {                                                                       \
         hipError_t _e = (expr);                                                \
         if (_e != hipSuccess) {                                                \
             (void)hipGetLastError(); /* reported through the status */         \
-            err = std::string(#expr) + ": " + hipGetErrorString(_e);          \
+            c.err = std::string(#expr) + ": " + hipGetErrorString(_e);        \
             return _e == hipErrorOutOfMemory ? MBPCG_ERR_OOM : MBPCG_ERR_HIP;  \
         }                                                                      \
     } while (0)
-    // the kernel reads its arguments from one device symbol (g_bargs): one
-    // batched solve at a time in this process
-    static std::mutex batch_mu;
-    std::lock_guard<std::mutex> batch_lock(batch_mu);
-    const auto t0 = std::chrono::steady_clock::now();
-    std::vector<BSys> hs(nsys);
+
+mbpcg_status batch_create(BatchCtx& c, int32_t nsys, const mbpcg_system* systems, mbpcg_mem mem,
+                          hipStream_t user_stream) {
+    c.nsys = nsys;
+    c.mem = mem;
+    c.sys.assign(systems, systems + nsys);
+    c.hs.resize(nsys);
     std::vector<int32_t> item_sys, pitem_sys;
     int64_t rp = 0, nz = 0, vec = 0, blk = 0;
     int items = 0, pitems = 0;
     for (int i = 0; i < nsys; ++i) {
         const mbpcg_system& y = systems[i];
-        BSys& b = hs[i];
+        BSys& b = c.hs[i];
         b.n = y.n;
         b.rp_off = rp;
         b.nz_off = nz;
@@ -1009,7 +1059,7 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
         b.blk_off = blk;
         b.s = y.s;
         b.S = padded_width(y.s);
-        b.SL = batch_slots(y);
+        b.SL = default_slots(row_class(y.n, y.nnz));
         b.ntile = (int)((y.n + item_rows(b.S) - 1) / item_rows(b.S));
         b.item_off = items;
         b.pntile = (int)((y.n + PT - 1) / PT);
@@ -1023,90 +1073,72 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
         nz += y.nnz;
         vec += y.n;
         blk += y.n * b.S;
+        if (items >= INT32_MAX / 2 || pitems >= INT32_MAX / 2) {
+            c.err = "batch too large";
+            return MBPCG_ERR_UNSUPPORTED;
+        }
     }
-    if (items >= INT32_MAX / 2 || pitems >= INT32_MAX / 2) {
-        err = "batch too large";
-        return MBPCG_ERR_UNSUPPORTED;
-    }
-    int dev = 0;
-    BCK(hipGetDevice(&dev));
-    hipStream_t stream = nullptr;
-    BCK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-    struct StreamGuard {
-        hipStream_t s;
-        ~StreamGuard() { (void)hipStreamDestroy(s); }
-    } sg{stream};
-    hipEvent_t ev = nullptr;
-    BCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    struct EventGuard {
-        hipEvent_t e;
-        ~EventGuard() { (void)hipEventDestroy(e); }
-    } eg{ev};
-    BCK(hipEventRecord(ev, user_stream));
-    BCK(hipStreamWaitEvent(stream, ev, 0));
+    c.items = items;
+    c.pitems = pitems;
+    BCK(hipGetDevice(&c.device));
+    BCK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    BCK(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+    BCK(hipEventCreate(&c.ev0));
+    BCK(hipEventCreate(&c.ev1));
+    BCK(hipEventRecord(c.ev, user_stream));
+    BCK(hipStreamWaitEvent(c.stream, c.ev, 0));
 
-    BatchBufs B;
-    BArgs a;
+    BArgs& a = c.a;
     memset(&a, 0, sizeof(a));
-    int32_t *d_rp, *d_ci, *d_items;
-    double *d_va, *d_vs, *d_b, *d_x, *d_d, *d_bb;
-    BSys* d_sys;
+    int32_t *d_rp, *d_ci, *d_items, *d_pitems;
+    double *d_va, *d_vs, *d_b, *d_d, *d_bb;
     DevState* d_st;
     BCtl* d_ctl;
+    BatchBufs& B = c.B;
     BCK(B.alloc(&d_rp, rp));
     BCK(B.alloc(&d_ci, nz));
     BCK(B.alloc(&d_va, nz));
     BCK(B.alloc(&d_vs, nz));
     BCK(B.alloc(&d_b, vec));
-    BCK(B.alloc(&d_x, vec));
+    BCK(B.alloc(&c.d_x, vec));
     BCK(B.alloc(&d_d, vec));
     BCK(B.alloc(&d_bb, vec));
     BCK(B.alloc(&d_items, items));
-    int32_t* d_pitems;
     BCK(B.alloc(&d_pitems, pitems));
-    BCK(B.alloc(&d_sys, nsys));
+    BCK(B.alloc(&c.d_sys, nsys));
     BCK(B.alloc(&d_st, nsys));
     BCK(B.alloc(&d_ctl, 1));
     double* blocks[8];
     for (auto& q : blocks) BCK(B.alloc(&q, blk));
-    double* d_part;
+    double *d_part, *d_ppart;
     BCK(B.alloc(&d_part, (size_t)items * PSTRIDE));
-    double* d_ppart;
     BCK(B.alloc(&d_ppart, (size_t)pitems * PSTRIDE));
 
     const hipMemcpyKind kind = mem == MBPCG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     for (int i = 0; i < nsys; ++i) {
         const mbpcg_system& y = systems[i];
-        const BSys& b = hs[i];
-        BCK(hipMemcpyAsync(d_rp + b.rp_off, y.rowptr, sizeof(int32_t) * (y.n + 1), kind, stream));
+        const BSys& b = c.hs[i];
+        BCK(hipMemcpyAsync(d_rp + b.rp_off, y.rowptr, sizeof(int32_t) * (y.n + 1), kind, c.stream));
         if (y.nnz > 0) {
-            BCK(hipMemcpyAsync(d_ci + b.nz_off, y.colind, sizeof(int32_t) * y.nnz, kind, stream));
-            BCK(hipMemcpyAsync(d_va + b.nz_off, y.vals, sizeof(double) * y.nnz, kind, stream));
+            BCK(hipMemcpyAsync(d_ci + b.nz_off, y.colind, sizeof(int32_t) * y.nnz, kind, c.stream));
+            BCK(hipMemcpyAsync(d_va + b.nz_off, y.vals, sizeof(double) * y.nnz, kind, c.stream));
         }
-        BCK(hipMemcpyAsync(d_b + b.vec_off, y.b, sizeof(double) * y.n, kind, stream));
+        BCK(hipMemcpyAsync(d_b + b.vec_off, y.b, sizeof(double) * y.n, kind, c.stream));
     }
     BCK(hipMemcpyAsync(d_items, item_sys.data(), sizeof(int32_t) * items, hipMemcpyHostToDevice,
-                       stream));
+                       c.stream));
     BCK(hipMemcpyAsync(d_pitems, pitem_sys.data(), sizeof(int32_t) * pitems,
-                       hipMemcpyHostToDevice, stream));
-    BCK(hipMemcpyAsync(d_sys, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, stream));
-    BCK(hipMemsetAsync(d_ctl, 0, sizeof(BCtl), stream));
-    hipLaunchKernelGGL(k_batch_state_init, dim3(nsys), dim3(MB_BLOCK), 0, stream, nsys, d_st, d_sys,
-                       (int)p.max_iter, p.tol, p.tau > 0 ? p.tau : 1e-12);
-    BCK(hipGetLastError());
+                       hipMemcpyHostToDevice, c.stream));
+    BCK(hipMemcpyAsync(c.d_sys, c.hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, c.stream));
+    BCK(hipStreamSynchronize(c.stream));
 
     a.nsys = nsys;
     a.total_items = items;
     a.total_pitems = pitems;
     a.pitem_sys = d_pitems;
     a.ppart = d_ppart;
-    a.max_iter = (int)p.max_iter;
-    a.jacobi = p.precond == MBPCG_PRECOND_JACOBI;
-    a.tol = p.tol;
-    a.tau = p.tau > 0 ? p.tau : 1e-12;
-    a.seed = p.seed;
     a.spin_limit = 1ll << 24;
-    a.sys = d_sys;
+    a.sys = c.d_sys;
     a.st = d_st;
     a.ctl = d_ctl;
     a.item_sys = d_items;
@@ -1115,7 +1147,7 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     a.vals = d_va;
     a.vals_s = d_vs;
     a.b = d_b;
-    a.x = d_x;
+    a.x = c.d_x;
     a.d = d_d;
     a.bbar = d_bb;
     a.U = blocks[0];
@@ -1127,84 +1159,131 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
     a.P = blocks[6];
     a.Q = blocks[7];
     a.part = d_part;
-    // profile: one steady-clock stamp per grid barrier (setup 7, 5 per
-    // iteration, 4 in the last, termination 9, plus start and end)
-    const int64_t max_loops = std::min<int64_t>(p.max_iter, INT32_MAX) + 2;
-    const int64_t nstamps = 1 + 7 + 5 * max_loops + 4 + BATCH_TERM_BARRIERS + 1;
-    long long* d_ts = nullptr;
-    if (p.profile) BCK(B.alloc(&d_ts, nstamps));
-    a.tstamp = d_ts;
 
     // grid: every workgroup co-resident (the barrier needs it)
     int per_cu = 0, cus = 0;
     BCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, MB_BLOCK, 0));
-    BCK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    BCK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
     if (per_cu < 1) {
-        err = "batched kernel does not fit on a compute unit";
+        c.err = "batched kernel does not fit on a compute unit";
         return MBPCG_ERR_HIP;
     }
-    const int grid = std::max(1, std::min(std::max(items, pitems), per_cu * cus));
+    c.resident = per_cu * cus;
+    c.grid = std::max(1, std::min(std::max(items, pitems), c.resident));
+    return MBPCG_OK;
+}
 
-    // one persistent kernel, captured in a graph and launched once
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+// lane groups per row of every system of class (S, cls); uploads the table
+static mbpcg_status set_slots(BatchCtx& c, int S, int cls, int SL) {
+    for (int i = 0; i < c.nsys; ++i)
+        if (c.hs[i].S == S && row_class(c.sys[i].n, c.sys[i].nnz) == cls) c.hs[i].SL = SL;
+    BCK(hipMemcpyAsync(c.d_sys, c.hs.data(), sizeof(BSys) * c.nsys, hipMemcpyHostToDevice,
+                       c.stream));
+    BCK(hipStreamSynchronize(c.stream));
+    return MBPCG_OK;
+}
+
+mbpcg_status batch_solve(BatchCtx& c, const mbpcg_params& p, mbpcg_info* per_system,
+                         hipStream_t user_stream, double* kernel_ms) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BCK(hipSetDevice(c.device));
+    const auto t0 = std::chrono::steady_clock::now();
+    BCK(hipEventRecord(c.ev, user_stream));
+    BCK(hipStreamWaitEvent(c.stream, c.ev, 0));
+    const int nsys = c.nsys;
+    BArgs& a = c.a;
+    // profile: one steady-clock stamp per grid barrier (setup 7, 5 per
+    // iteration, 4 in the last, termination 9, plus start and end)
+    const int64_t max_loops = std::min<int64_t>(p.max_iter, INT32_MAX) + 2;
+    const int64_t nstamps = 1 + 7 + 5 * max_loops + 4 + BATCH_TERM_BARRIERS + 1;
+    if (p.profile && nstamps > c.ts_cap) {
+        if (c.d_ts) (void)hipFree(c.d_ts);
+        c.d_ts = nullptr;
+        c.ts_cap = 0;
+        BCK(hipMalloc(&c.d_ts, sizeof(long long) * nstamps));
+        c.ts_cap = nstamps;
+    }
+    a.max_iter = (int)p.max_iter;
+    a.jacobi = p.precond == MBPCG_PRECOND_JACOBI;
+    a.tol = p.tol;
+    a.tau = p.tau > 0 ? p.tau : 1e-12;
+    a.seed = p.seed;
+    a.tstamp = p.profile ? c.d_ts : nullptr;
+    BCK(hipMemsetAsync(a.ctl, 0, sizeof(BCtl), c.stream));
+    hipLaunchKernelGGL(k_batch_state_init, dim3(nsys), dim3(MB_BLOCK), 0, c.stream, nsys, a.st,
+                       c.d_sys, (int)p.max_iter, p.tol, a.tau);
+    BCK(hipGetLastError());
     BCK(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_bargs), &a, sizeof(BArgs), 0, hipMemcpyHostToDevice,
-                               stream));
-    BCK(hipStreamSynchronize(stream));
-    BCK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(MB_BLOCK), 0, stream);
-    hipError_t le = hipGetLastError();
-    hipError_t ce = hipStreamEndCapture(stream, &graph);
-    if (le != hipSuccess || ce != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        err = std::string("capture of the batched kernel failed: ") +
-              hipGetErrorString(le != hipSuccess ? le : ce);
-        return MBPCG_ERR_HIP;
+                               c.stream));
+    // the persistent kernel, captured once per grid and replayed
+    if (!c.exec || c.exec_grid != c.grid) {
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
+        c.exec = nullptr;
+        hipStream_t cs = nullptr;
+        BCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (be == hipSuccess) {
+            hipLaunchKernelGGL(k_batch, dim3(c.grid), dim3(MB_BLOCK), 0, cs);
+            const hipError_t le = hipGetLastError();
+            const hipError_t ce = hipStreamEndCapture(cs, &graph);
+            be = le != hipSuccess ? le : ce;
+        }
+        (void)hipStreamDestroy(cs);
+        if (be != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            c.err = std::string("capture of the batched kernel failed: ") + hipGetErrorString(be);
+            return MBPCG_ERR_HIP;
+        }
+        const hipError_t ie = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            c.exec = nullptr;
+            c.err = std::string("instantiate: ") + hipGetErrorString(ie);
+            return MBPCG_ERR_HIP;
+        }
+        c.exec_grid = c.grid;
     }
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) {
-        err = std::string("instantiate: ") + hipGetErrorString(ie);
-        return MBPCG_ERR_HIP;
-    }
-    const auto t1 = std::chrono::steady_clock::now();
-    hipError_t ge = hipGraphLaunch(exec, stream);
-    if (ge == hipSuccess) ge = hipStreamSynchronize(stream);
-    const auto t2 = std::chrono::steady_clock::now();
-    (void)hipGraphExecDestroy(exec);
-    BCK(ge);
+    BCK(hipEventRecord(c.ev0, c.stream));
+    BCK(hipGraphLaunch(c.exec, c.stream));
+    BCK(hipEventRecord(c.ev1, c.stream));
+    BCK(hipEventSynchronize(c.ev1));
+    float kms = 0.f;
+    BCK(hipEventElapsedTime(&kms, c.ev0, c.ev1));
+    const double ms_kernel = kms;
+    if (kernel_ms) *kernel_ms = ms_kernel;
 
     BCtl hctl;
-    BCK(hipMemcpy(&hctl, d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost));
+    BCK(hipMemcpy(&hctl, a.ctl, sizeof(BCtl), hipMemcpyDeviceToHost));
     if (hctl.abort) {
-        err = "batched kernel: grid barrier wait exceeded its bound (grid not co-resident?)";
+        c.err = "batched kernel: grid barrier wait exceeded its bound (grid not co-resident?)";
         return MBPCG_ERR_HIP;
     }
     // results
     const size_t head = offsetof(DevState, Xi);
     static_assert(offsetof(DevState, Xi) % 4 == 0, "state head");
     std::vector<char> hst(head * (size_t)nsys);
-    uint32_t* d_pack = reinterpret_cast<uint32_t*>(d_part);   // the partials are free now
-    hipLaunchKernelGGL(k_batch_state_pack, dim3(std::min(nsys, 1024)), dim3(MB_BLOCK), 0, stream, nsys,
-                       d_st, (int)(head / 4), d_pack);
+    uint32_t* d_pack = reinterpret_cast<uint32_t*>(a.part);   // the partials are free now
+    hipLaunchKernelGGL(k_batch_state_pack, dim3(std::min(nsys, 1024)), dim3(MB_BLOCK), 0, c.stream,
+                       nsys, a.st, (int)(head / 4), d_pack);
     BCK(hipGetLastError());
-    BCK(hipMemcpyAsync(hst.data(), d_pack, head * (size_t)nsys, hipMemcpyDeviceToHost, stream));
-    const hipMemcpyKind back = mem == MBPCG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    BCK(hipMemcpyAsync(hst.data(), d_pack, head * (size_t)nsys, hipMemcpyDeviceToHost, c.stream));
+    const hipMemcpyKind back = c.mem == MBPCG_MEM_HOST ? hipMemcpyDeviceToHost
+                                                       : hipMemcpyDeviceToDevice;
     for (int i = 0; i < nsys; ++i)
-        BCK(hipMemcpyAsync(systems[i].x, d_x + hs[i].vec_off, sizeof(double) * systems[i].n, back,
-                           stream));
-    BCK(hipStreamSynchronize(stream));
-    const double ms_kernel = std::chrono::duration<double, std::milli>(t2 - t1).count();
+        BCK(hipMemcpyAsync(c.sys[i].x, c.d_x + c.hs[i].vec_off, sizeof(double) * c.sys[i].n, back,
+                           c.stream));
+    BCK(hipStreamSynchronize(c.stream));
     // phase totals as in mbpcg_info.ms_phase: 0 block product, 1 Xi tail,
     // 2 update, 3 QR tail, 4 direction update, 5 termination, 6 setup
     double ph_ms[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (d_ts) {
+    if (p.profile) {
         const int64_t L = hctl.loops;
         const int64_t used = 1 + 7 + 5 * L + 4 + BATCH_TERM_BARRIERS + 1;
         std::vector<long long> ts(used);
-        BCK(hipMemcpy(ts.data(), d_ts, sizeof(long long) * used, hipMemcpyDeviceToHost));
+        BCK(hipMemcpy(ts.data(), c.d_ts, sizeof(long long) * used, hipMemcpyDeviceToHost));
         int khz = 0;
-        BCK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        BCK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device));
         const double ms_per_tick = khz > 0 ? 1.0 / khz : 0.0;
         auto span = [&](int64_t i) { return (double)(ts[i] - ts[i - 1]) * ms_per_tick; };
         for (int64_t i = 1; i <= 7; ++i) ph_ms[6] += span(i);
@@ -1212,7 +1291,8 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
             for (int q = 0; q < (it < L ? 5 : 4); ++q) ph_ms[q] += span(8 + 5 * it + q);
         for (int64_t i = 8 + 5 * L + 4; i < used; ++i) ph_ms[5] += span(i);
     }
-    const double ms_all = std::chrono::duration<double, std::milli>(t2 - t0).count();
+    const double ms_all =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     mbpcg_status worst = MBPCG_OK;
     for (int i = 0; i < nsys; ++i) {
         DevState s;
@@ -1245,12 +1325,131 @@ mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_
                 f.ms_phase[q] = ph_ms[q];
                 acc += ph_ms[q];
             }
-            f.ms_phase[7] = d_ts ? std::max(0.0, ms_kernel - acc) : ms_kernel;
+            f.ms_phase[7] = p.profile ? std::max(0.0, ms_kernel - acc) : ms_kernel;
             f.status = st;
         }
     }
     return worst;
+}
+
+// Timed trials of the persistent kernel's free parameters: lane groups per
+// row for each (width, row class) present -- tried flipped one class at a
+// time, kept when faster -- and then the grid (all co-resident workgroups,
+// three quarters, half).  Trials are solves capped at a few iterations.  The
+// per-class choice is kept for the process; a batch whose classes are all
+// known skips those trials.
+mbpcg_status batch_tune(BatchCtx& c, const mbpcg_params& p, mbpcg_batch_tuning* out) {
+    mbpcg_params q = p;
+    q.max_iter = std::min<int64_t>(p.max_iter, 12);
+    q.profile = 0;
+    std::vector<std::pair<int, int>> classes;
+    for (int i = 0; i < c.nsys; ++i) {
+        const std::pair<int, int> k{c.hs[i].S, row_class(c.sys[i].n, c.sys[i].nnz)};
+        if (std::find(classes.begin(), classes.end(), k) == classes.end()) classes.push_back(k);
+    }
+    std::sort(classes.begin(), classes.end());
+    int trials = 0;
+    auto trial = [&](double* ms) -> mbpcg_status {
+        ++trials;
+        double best = 1e30;
+        for (int r = 0; r < 2; ++r) {   // the faster of two runs
+            double t = 0.0;
+            const mbpcg_status st = batch_solve(c, q, nullptr, c.stream, &t);
+            if (st != MBPCG_OK && st != MBPCG_NOT_CONVERGED && st != MBPCG_ERR_NOT_SPD &&
+                st != MBPCG_ERR_BREAKDOWN && st != MBPCG_ERR_NONFINITE)
+                return st;
+            best = std::min(best, t);
+        }
+        *ms = best;
+        return MBPCG_OK;
+    };
+    bool all_known = true;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto& k : classes) {
+            auto it = g_slot_cache.find(k);
+            if (it == g_slot_cache.end()) all_known = false;
+        }
+        for (const auto& k : classes) {
+            auto it = g_slot_cache.find(k);
+            const int SL = it != g_slot_cache.end() ? it->second : default_slots(k.second);
+            for (int i = 0; i < c.nsys; ++i)
+                if (c.hs[i].S == k.first && row_class(c.sys[i].n, c.sys[i].nnz) == k.second)
+                    c.hs[i].SL = SL;
+        }
+    }
+    BCK(hipMemcpyAsync(c.d_sys, c.hs.data(), sizeof(BSys) * c.nsys, hipMemcpyHostToDevice,
+                       c.stream));
+    BCK(hipStreamSynchronize(c.stream));
+    double best = 0.0;
+    mbpcg_status st = trial(&best);
+    if (st != MBPCG_OK) return st;
+    if (!all_known) {
+        for (const auto& k : classes) {
+            int cur = 1;
+            for (int i = 0; i < c.nsys; ++i)
+                if (c.hs[i].S == k.first && row_class(c.sys[i].n, c.sys[i].nnz) == k.second)
+                    cur = c.hs[i].SL;
+            const int alt = cur == 1 ? 2 : 1;
+            if ((st = set_slots(c, k.first, k.second, alt)) != MBPCG_OK) return st;
+            double t = 0.0;
+            if ((st = trial(&t)) != MBPCG_OK) return st;
+            if (t < 0.99 * best) {
+                best = t;
+            } else if ((st = set_slots(c, k.first, k.second, cur)) != MBPCG_OK) {
+                return st;
+            }
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto& k : classes)
+            for (int i = 0; i < c.nsys; ++i)
+                if (c.hs[i].S == k.first && row_class(c.sys[i].n, c.sys[i].nnz) == k.second) {
+                    g_slot_cache[k] = c.hs[i].SL;
+                    break;
+                }
+    }
+    const int full = std::max(1, std::min(std::max(c.items, c.pitems), c.resident));
+    int best_grid = c.grid;
+    for (int g : {full, full * 3 / 4 / 8 * 8, full / 2 / 8 * 8}) {
+        if (g < 8 || g == c.grid) continue;
+        const int keep = c.grid;
+        c.grid = g;
+        double t = 0.0;
+        if ((st = trial(&t)) != MBPCG_OK) return st;
+        if (t < 0.99 * best) {
+            best = t;
+            best_grid = g;
+        }
+        c.grid = keep;
+    }
+    c.grid = best_grid;
+    if (out) {
+        *out = mbpcg_batch_tuning{};
+        out->workgroups = c.grid;
+        out->classes = (int32_t)classes.size();
+        for (const auto& k : classes)
+            for (int i = 0; i < c.nsys; ++i)
+                if (c.hs[i].S == k.first && row_class(c.sys[i].n, c.sys[i].nnz) == k.second) {
+                    out->two_slot_classes += c.hs[i].SL == 2;
+                    break;
+                }
+        out->trials = trials;
+        out->ms = best;
+    }
+    return MBPCG_OK;
+}
+
 #undef BCK
+
+// one call: upload, solve, free
+mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_params& p,
+                         mbpcg_info* per_system, mbpcg_mem mem, hipStream_t user_stream,
+                         std::string& err) {
+    BatchCtx c;
+    mbpcg_status st = batch_create(c, nsys, systems, mem, user_stream);
+    if (st == MBPCG_OK) st = batch_solve(c, p, per_system, user_stream, nullptr);
+    if (!c.err.empty()) err = c.err;
+    return st;
 }
 
 }  // namespace mb

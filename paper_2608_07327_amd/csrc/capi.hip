@@ -18,6 +18,15 @@ mbpcg_status time_block_product_entry(Ctx& c, int s, int reps, const double* P, 
                                       double* ms_avg);
 mbpcg_status tune_entry(Ctx& c, int s, mbpcg_tile_shape* out);
 mbpcg_status set_shape_entry(Ctx& c, int s, const mbpcg_tile_shape& t);
+struct BatchCtx;
+BatchCtx* batch_new();
+void batch_delete(BatchCtx* c);
+const char* batch_error(const BatchCtx* c);
+mbpcg_status batch_create(BatchCtx& c, int32_t nsys, const mbpcg_system* systems, mbpcg_mem mem,
+                          hipStream_t user_stream);
+mbpcg_status batch_solve(BatchCtx& c, const mbpcg_params& p, mbpcg_info* per_system,
+                         hipStream_t user_stream, double* kernel_ms);
+mbpcg_status batch_tune(BatchCtx& c, const mbpcg_params& p, mbpcg_batch_tuning* out);
 mbpcg_status batch_entry(int32_t nsys, const mbpcg_system* systems, const mbpcg_params& common,
                          mbpcg_info* per_system, mbpcg_mem mem, hipStream_t stream,
                          std::string& err);
@@ -283,11 +292,8 @@ mbpcg_status mbpcg_set_tile_shape(mbpcg_ctx ctx, int32_t s, const mbpcg_tile_sha
     return mb::set_shape_entry(ctx->c, s, *shape);
 }
 
-mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
-                               const mbpcg_params* common, mbpcg_info* per_system, mbpcg_mem mem,
-                               void* hip_stream) {
-    if (nsys < 1 || !systems || !common) return MBPCG_ERR_INVALID_ARG;
-    if (mem != MBPCG_MEM_HOST && mem != MBPCG_MEM_DEVICE) return MBPCG_ERR_INVALID_ARG;
+static mbpcg_status check_batch_params(const mbpcg_params* common) {
+    if (!common) return MBPCG_ERR_INVALID_ARG;
     if (!(common->tol > 0.0) || !std::isfinite(common->tol) || common->max_iter < 1 ||
         common->max_iter > (int64_t)INT32_MAX)
         return MBPCG_ERR_INVALID_ARG;
@@ -305,6 +311,13 @@ mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
     if (common->precision != MBPCG_FP64) return MBPCG_ERR_UNSUPPORTED;
     if (common->tol_initial > 0.0 && common->tol_initial != common->tol)
         return MBPCG_ERR_UNSUPPORTED;
+    return MBPCG_OK;
+}
+
+static mbpcg_status check_batch_systems(int32_t nsys, const mbpcg_system* systems,
+                                        mbpcg_mem mem) {
+    if (nsys < 1 || !systems) return MBPCG_ERR_INVALID_ARG;
+    if (mem != MBPCG_MEM_HOST && mem != MBPCG_MEM_DEVICE) return MBPCG_ERR_INVALID_ARG;
     for (int32_t i = 0; i < nsys; ++i) {
         const mbpcg_system& y = systems[i];
         if (y.n < 1 || y.n >= (int64_t)INT32_MAX || y.nnz < 0 || y.nnz >= (int64_t)INT32_MAX)
@@ -321,12 +334,74 @@ mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
                 if (y.colind[k] < 0 || (int64_t)y.colind[k] >= y.n) return MBPCG_ERR_INVALID_ARG;
         }
     }
+    return MBPCG_OK;
+}
+
+mbpcg_status mbpcg_solve_batch(int32_t nsys, const mbpcg_system* systems,
+                               const mbpcg_params* common, mbpcg_info* per_system, mbpcg_mem mem,
+                               void* hip_stream) {
+    if (nsys < 1 || !systems || !common) return MBPCG_ERR_INVALID_ARG;
+    if (mem != MBPCG_MEM_HOST && mem != MBPCG_MEM_DEVICE) return MBPCG_ERR_INVALID_ARG;
+    mbpcg_status v = check_batch_params(common);
+    if (v == MBPCG_OK) v = check_batch_systems(nsys, systems, mem);
+    if (v != MBPCG_OK) return v;
     std::string err;
     mbpcg_status st = mb::batch_entry(nsys, systems, *common, per_system, mem,
                                       (hipStream_t)hip_stream, err);
     if (st != MBPCG_OK) g_create_error = err;
     return st;
 }
+
+struct mbpcg_batch_s {
+    mb::BatchCtx* c = nullptr;
+    ~mbpcg_batch_s() { mb::batch_delete(c); }
+};
+
+mbpcg_status mbpcg_batch_create(mbpcg_batch* out, int32_t nsys, const mbpcg_system* systems,
+                                mbpcg_mem mem, void* hip_stream) {
+    if (!out) return MBPCG_ERR_INVALID_ARG;
+    *out = nullptr;
+    mbpcg_status v = check_batch_systems(nsys, systems, mem);
+    if (v != MBPCG_OK) return v;
+    mbpcg_batch h = new (std::nothrow) mbpcg_batch_s;
+    if (!h) return MBPCG_ERR_OOM;
+    h->c = mb::batch_new();
+    if (!h->c) {
+        delete h;
+        return MBPCG_ERR_OOM;
+    }
+    const mbpcg_status st = mb::batch_create(*h->c, nsys, systems, mem, (hipStream_t)hip_stream);
+    if (st != MBPCG_OK) {
+        g_create_error = mb::batch_error(h->c);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return MBPCG_OK;
+}
+
+mbpcg_status mbpcg_batch_solve(mbpcg_batch batch, const mbpcg_params* common,
+                               mbpcg_info* per_system, void* hip_stream) {
+    if (!batch || !common) return MBPCG_ERR_INVALID_ARG;
+    mbpcg_status v = check_batch_params(common);
+    if (v != MBPCG_OK) return v;
+    const mbpcg_status st = mb::batch_solve(*batch->c, *common, per_system,
+                                            (hipStream_t)hip_stream, nullptr);
+    if (st != MBPCG_OK) g_create_error = mb::batch_error(batch->c);
+    return st;
+}
+
+mbpcg_status mbpcg_batch_autotune(mbpcg_batch batch, const mbpcg_params* common,
+                                  mbpcg_batch_tuning* out) {
+    if (!batch || !common) return MBPCG_ERR_INVALID_ARG;
+    mbpcg_status v = check_batch_params(common);
+    if (v != MBPCG_OK) return v;
+    const mbpcg_status st = mb::batch_tune(*batch->c, *common, out);
+    if (st != MBPCG_OK) g_create_error = mb::batch_error(batch->c);
+    return st;
+}
+
+void mbpcg_batch_destroy(mbpcg_batch batch) { delete batch; }
 
 mbpcg_status mbpcg_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream) {
     if (!dst || !src || bytes < 0) return MBPCG_ERR_INVALID_ARG;

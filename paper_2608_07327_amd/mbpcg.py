@@ -26,7 +26,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 EXPORTS = ("mbpcg_autotune", "mbpcg_default_params", "mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve",
            "mbpcg_cg_solve", "mbpcg_block_product", "mbpcg_block_product_noalloc",
            "mbpcg_time_block_product",
-           "mbpcg_solve_batch", "mbpcg_stream_copy", "mbpcg_destroy", "mbpcg_status_str",
+           "mbpcg_solve_batch", "mbpcg_batch_create", "mbpcg_batch_solve", "mbpcg_batch_autotune",
+           "mbpcg_batch_destroy", "mbpcg_stream_copy", "mbpcg_destroy", "mbpcg_status_str",
            "mbpcg_last_error", "mbpcg_tile_shapes", "mbpcg_set_tile_shape")
 
 
@@ -70,6 +71,14 @@ class TileShape(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchTuning(C.Structure):
+    _fields_ = [("workgroups", C.c_int32), ("classes", C.c_int32),
+                ("two_slot_classes", C.c_int32), ("trials", C.c_int32), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class MbpcgError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"mbpcg status {status}: {msg}")
@@ -101,6 +110,11 @@ def load():
     L.mbpcg_solve_batch.argtypes = [i32, C.POINTER(System), C.POINTER(Params), C.POINTER(Info),
                                     C.c_int, vp]
     L.mbpcg_stream_copy.argtypes = [vp, vp, i64, vp]
+    L.mbpcg_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(System), C.c_int, vp]
+    L.mbpcg_batch_solve.argtypes = [vp, C.POINTER(Params), C.POINTER(Info), vp]
+    L.mbpcg_batch_autotune.argtypes = [vp, C.POINTER(Params), C.POINTER(BatchTuning)]
+    L.mbpcg_batch_destroy.argtypes = [vp]
+    L.mbpcg_batch_destroy.restype = None
     L.mbpcg_autotune.argtypes = [vp, i32, C.POINTER(TileShape)]
     L.mbpcg_tile_shapes.argtypes = [i32, C.POINTER(TileShape), i32, C.POINTER(i32)]
     L.mbpcg_set_tile_shape.argtypes = [vp, i32, C.POINTER(TileShape)]
@@ -112,7 +126,7 @@ def load():
     L.mbpcg_last_error.restype = C.c_char_p
     for f in ("mbpcg_create_csr", "mbpcg_create_dense", "mbpcg_solve", "mbpcg_cg_solve",
               "mbpcg_block_product", "mbpcg_block_product_noalloc", "mbpcg_time_block_product",
-              "mbpcg_solve_batch",
+              "mbpcg_solve_batch", "mbpcg_batch_create", "mbpcg_batch_solve", "mbpcg_batch_autotune",
               "mbpcg_stream_copy", "mbpcg_autotune", "mbpcg_tile_shapes", "mbpcg_set_tile_shape"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -322,6 +336,71 @@ class Solver:
                                              Q.data_ptr(), C.byref(ms))
         _check(st, self._h, allow=(OK,))
         return ms.value
+
+
+def _systems(systems):
+    arr = (System * len(systems))()
+    mem = None
+    for i, y in enumerate(systems):
+        pr, m = _ptr_mem(y["rowptr"])
+        mem = m if mem is None else mem
+        if m != mem:
+            raise ValueError("all systems must be in the same memory kind")
+        vals = y["vals"]
+        nnz = int(vals.numel() if _is_torch(vals) else vals.size)
+        arr[i] = System(int(y["n"]), nnz, pr, _ptr_mem(y["colind"])[0], _ptr_mem(vals)[0],
+                        _ptr_mem(y["b"])[0], _ptr_mem(y["x"])[0], int(y["s"]))
+    return arr, mem
+
+
+class Batch:
+    """A batch context: the systems (dicts as for solve_batch) uploaded once,
+    the persistent kernel's graph replayed by every solve; x is written
+    through the systems' "x" arrays.  The arrays must outlive the context."""
+
+    def __init__(self, systems, stream=None):
+        L = load()
+        self._keep = systems
+        arr, mem = _systems(systems)
+        h = C.c_void_p()
+        st = L.mbpcg_batch_create(C.byref(h), len(systems), arr, mem, _stream_ptr(stream))
+        _check(st, None, allow=(OK,))
+        self._h = h
+        self.n = len(systems)
+
+    def solve(self, stream=None, **kw):
+        """Returns (status, infos)."""
+        p = default_params(**kw)
+        infos = (Info * self.n)()
+        st = load().mbpcg_batch_solve(self._h, C.byref(p), infos, _stream_ptr(stream))
+        _check(st, None, allow=(OK, NOT_CONVERGED, ERR_NOT_SPD, ERR_BREAKDOWN, ERR_NONFINITE))
+        return st, [infos[i].as_dict() for i in range(self.n)]
+
+    def autotune(self, **kw):
+        """Timed trials of the batched kernel's lane groups per row and grid;
+        returns the choice as a dict (overwrites x)."""
+        p = default_params(**kw)
+        t = BatchTuning()
+        st = load().mbpcg_batch_autotune(self._h, C.byref(p), C.byref(t))
+        _check(st, None, allow=(OK,))
+        return t.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mbpcg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def solve_batch(systems, **kw):

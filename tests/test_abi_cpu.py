@@ -118,6 +118,28 @@ def test_batch_validation():
     assert L.mbpcg_solve_batch(1, sysv, C.byref(p), None, M.MEM_HOST, None) == M.ERR_INVALID_ARG
 
 
+def test_batch_context_validation():
+    L = M.load()
+    rp = np.array([0, 1], np.int32)
+    ci = np.array([0], np.int32)
+    v = np.array([2.0])
+    b = np.ones(1)
+    x = np.zeros(1)
+    h = C.c_void_p()
+    sysv = (M.System * 1)(M.System(1, 1, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                                   b.ctypes.data, x.ctypes.data, 9))
+    assert L.mbpcg_batch_create(C.byref(h), 1, sysv, M.MEM_HOST, None) == M.ERR_UNSUPPORTED
+    sysv[0].s = 1
+    sysv[0].rowptr = None
+    assert L.mbpcg_batch_create(C.byref(h), 1, sysv, M.MEM_HOST, None) == M.ERR_INVALID_ARG
+    assert L.mbpcg_batch_create(None, 1, sysv, M.MEM_HOST, None) == M.ERR_INVALID_ARG
+    p = M.default_params()
+    assert L.mbpcg_batch_solve(None, C.byref(p), None, None) == M.ERR_INVALID_ARG
+    t = M.BatchTuning()
+    assert L.mbpcg_batch_autotune(None, C.byref(p), C.byref(t)) == M.ERR_INVALID_ARG
+    L.mbpcg_batch_destroy(None)
+
+
 def test_stream_copy_rejects_null():
     assert M.load().mbpcg_stream_copy(None, None, 8, None) == M.ERR_INVALID_ARG
 

@@ -89,6 +89,43 @@ def test_batch_near_singular_laplacians_against_oracle():
     assert st == 0
 
 
+def test_batch_context_replays_and_matches_the_one_call_solve():
+    # a batch context uploads once and replays its graph: repeated solves
+    # are bitwise the one-call solve's
+    systems = W.graph_laplacian_batch(count=6, n_lo=300, n_hi=4000, tag=(5, 3))
+    items = to_items(systems)
+    say("batch context")
+    st0, i0 = M.solve_batch(items, seed=31)
+    x0 = [it["x"].clone() for it in items]
+    with M.Batch(items) as bt:
+        for rep in range(3):
+            for it in items:
+                it["x"].zero_()
+            st, infos = bt.solve(seed=31, profile=rep == 1)
+            assert st == st0
+            for a, b2, ia, ib in zip(items, x0, infos, i0):
+                assert ia["iterations"] == ib["iterations"]
+                assert torch.equal(a["x"], b2)
+
+
+def test_batch_autotune_then_parity():
+    # the tuned lane groups per row and grid change only the summation order:
+    # every system still meets the parity contract
+    systems = W.graph_laplacian_batch(count=8, n_lo=300, n_hi=6000, tag=(5, 4))
+    # one system with long rows (dense block) so two row classes are present
+    A = W.dense_to_csr(W.dense_spd(40, tag=(5, 41)))
+    systems.append(W.BatchSystem(A, W.rng_for((5, 42)).standard_normal(40), 4))
+    items = to_items(systems)
+    say("batch autotune")
+    with M.Batch(items) as bt:
+        t = bt.autotune(seed=40)
+        assert t["trials"] >= 1 and t["workgroups"] >= 1 and t["classes"] >= 2
+        st, infos = bt.solve(seed=40)
+    for i, (y, it, info) in enumerate(zip(systems, items, infos)):
+        xo, io, xp, ip = PC.oracle_band(y.A, y.b, y.s, seed=40 + i)
+        PC.check(it["x"].cpu().numpy(), info, xo, io, xp, ip, 1e-8, what=f"tuned system {i}")
+
+
 def test_batch_matches_single_solves():
     systems = W.graph_laplacian_batch(count=4, n_lo=500, n_hi=3000, tag=(5, 2))
     items = to_items(systems)
