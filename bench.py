@@ -94,10 +94,14 @@ def kernel_source_hash() -> str:
 
 
 def shape_key(S: int, t: dict) -> str:
-    """S,T,SL,V,U,W of a tile shape as returned by Solver.autotune."""
+    """S,T,SL,V,U,W@workgroups of a tile shape and grid as returned by
+    Solver.autotune (the counter record is keyed by both: the traffic of one
+    shape depends on the grid, which sets how far apart the tiles in flight
+    lie)."""
     slots = t["lanes_per_row"] * t["cols_per_lane"] // S
     return ",".join(str(v) for v in (S, t["tile_rows"], slots, t["cols_per_lane"],
-                                     t["loads_in_flight"], t["waves_per_simd"]))
+                                     t["loads_in_flight"], t["waves_per_simd"])) + \
+        f"@{t['workgroups']}"
 
 
 def traffic_from_profiles(name: str, key: str, sources=SPMM_SOURCES):
@@ -258,7 +262,13 @@ def leg_sparse(args, pois, steps, warmup):
             inf = check(solver.solve(bd, x=x, s=sw, seed=W.uniform_block_seed(cfg, sw),
                                      profile=1)[1], f"sweep s={sw}")
             ms = inf["ms_spmm"] / max(1, inf["spmm_launches"])
+            tr = traffic_from_profiles("spmm_diffusion3d_128_traffic.json",
+                                       shape_key(pad(sw), tuned[sw]))
+            alg_sw = 12 * A.nnz + 4 * (A.n + 1) + 16 * A.n * pad(sw)
             sweep[str(sw)] = {
+                "spmm_shape": shape_key(pad(sw), tuned[sw]),
+                "spmm_traffic": tr,
+                "spmm_traffic_over_algorithmic": None if tr is None else round(tr / alg_sw, 3),
                 "iterations": inf["iterations"],
                 "seconds": round(inf["ms_total"] / 1e3, 5),
                 "ms_per_iter": round(inf["ms_per_iter"], 4),

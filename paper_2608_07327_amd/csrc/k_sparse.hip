@@ -7,8 +7,10 @@
 // loads, so A is read from HBM once per product for all S columns.  A row is
 // handled by LPR = (S / V) * SL lanes: lane (slot, jv) accumulates the V
 // adjacent columns jv .. jv+V-1 of P (16-byte loads for V = 2, 4) over every
-// SL-th nonzero of the row, with U gathers in flight.  Q leaves the lanes'
-// registers with coalesced vector stores.
+// SL-th nonzero of the row, with U gathers in flight; for S > 2 the tile's own
+// rows of P are staged in LDS (the Gram's operand) and a nonzero whose
+// column falls inside the tile reads its P row from there.  Q leaves the
+// lanes' registers with coalesced non-temporal vector stores.
 //
 // Gram epilogue, chosen by width so that it costs few registers (the kernel
 // lives on occupancy: its gathers' latency is hidden by other wavefronts):
@@ -55,14 +57,22 @@ __device__ __forceinline__ void load_cols(const double* p, double* x) {
     }
 }
 
+// Q rows leave with non-temporal stores: nothing in the product reads them
+// again, and holding them in the L2 would evict rows of P that later tiles
+// gather
 template <int V>
 __device__ __forceinline__ void store_cols(double* p, const double* x) {
     if constexpr (V == 1) {
-        p[0] = x[0];
+        __builtin_nontemporal_store(x[0], p);
     } else {
+        typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int h = 0; h < V / 2; ++h)
-            reinterpret_cast<double2*>(p)[h] = make_double2(x[2 * h], x[2 * h + 1]);
+        for (int h = 0; h < V / 2; ++h) {
+            d2 t;
+            t.x = x[2 * h];
+            t.y = x[2 * h + 1];
+            __builtin_nontemporal_store(t, reinterpret_cast<d2*>(p) + h);
+        }
     }
 }
 
@@ -135,14 +145,12 @@ void k_spmm(const int32_t* __restrict__ rowptr,
             rpv[q] = rowptr[q0 + (e <= qrows ? e : 0)];
         }
         if constexpr (!REG) {
-            if (gram) {
 #pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    const int e = tid + q * MB_BLOCK;
-                    const bool in = e < qrows * S;
-                    const double v = P[q0 * S + (in ? e : 0)];
-                    ppv[q] = in ? v : 0.0;
-                }
+            for (int q = 0; q < PPT; ++q) {
+                const int e = tid + q * MB_BLOCK;
+                const bool in = e < qrows * S;
+                const double v = P[q0 * S + (in ? e : 0)];
+                ppv[q] = in ? v : 0.0;
             }
         }
         h_nzb = rowptr[q0];
@@ -193,12 +201,10 @@ void k_spmm(const int32_t* __restrict__ rowptr,
             if (e <= rows) sRp[e] = rpv[q];
         }
         if constexpr (!REG) {
-            if (gram) {
 #pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    const int e = tid + q * MB_BLOCK;
-                    if (e < T * S) sP[e] = ppv[q];
-                }
+            for (int q = 0; q < PPT; ++q) {
+                const int e = tid + q * MB_BLOCK;
+                if (e < T * S) sP[e] = ppv[q];
             }
         }
         put_csr(min(NZC, nzt));
@@ -250,7 +256,14 @@ void k_spmm(const int32_t* __restrict__ rowptr,
                         const bool ok = kk < kend;
                         const int c = ok ? sC[kk - cb] : 0;
                         v[u] = ok ? sV[kk - cb] : 0.0;
-                        load_cols<V>(P + (int64_t)c * S + jv, x[u]);
+                        // a column inside this tile's rows: its P row is in LDS
+                        const unsigned lc = (unsigned)(c - (int)r0);
+                        if (!REG && lc < (unsigned)rows) {
+#pragma unroll
+                            for (int q = 0; q < V; ++q) x[u][q] = sP[lc * S + jv + q];
+                        } else {
+                            load_cols<V>(P + (int64_t)c * S + jv, x[u]);
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < U; ++u)
