@@ -9,7 +9,8 @@ benchmark runs), and optionally the MFMA counters of a third pass.
 
 Launches that exit at once (iterations issued after the solve stopped) are
 left out: a kernel's launches shorter than a fifth of its longest are
-dropped.  MFMA: executed MFMA flops per launch from
+dropped (--busy-frac; a larger fraction also leaves out shortened trial
+runs, such as the batched kernel's autotuning trials).  MFMA: executed MFMA flops per launch from
 SQ_INSTS_VALU_MFMA_MOPS_* (x 512), and the MFMA-busy share of the SIMD
 cycles (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE per XCD times the
 SIMDs).
@@ -33,6 +34,9 @@ ap.add_argument("--record", default="")
 ap.add_argument("--sources", default="")
 ap.add_argument("--record-filter", default="k_spmm")
 ap.add_argument("--workload", default="")
+ap.add_argument("--busy-frac", type=float, default=0.2,
+                help="launches shorter than this fraction of their kernel's (and grid's) "
+                     "longest are left out")
 a = ap.parse_args()
 
 def short(name):
@@ -80,7 +84,7 @@ print(f"calibration (1 GiB k_stream_copy): FETCH_SIZE {cf:.0f} KiB (factor {ff:.
 def busy(xs, key):
     if not xs: return []
     m = max(key(x) for x in xs)
-    return [x for x in xs if key(x) >= 0.2 * m]
+    return [x for x in xs if key(x) >= a.busy_frac * m]
 
 rows = []
 for k in sorted(set(dur) | set(F)):
