@@ -250,24 +250,37 @@ void k_spmm(const int32_t* __restrict__ rowptr,
                 const int kend = min(ke, cb + cn);
                 for (; k < kend; k += U * SL) {
                     double v[U], x[U][V];
+                    unsigned lc[U];
+                    // gathers of the columns outside this tile's rows, all
+                    // issued before the first is consumed; a column inside
+                    // the tile reads its P row from LDS when it is consumed
+                    // (after the gathers have landed: an LDS read into the
+                    // registers of a gather in flight would make the
+                    // compiler wait for every gather issued before it)
+                    int c[U];
+                    // every slot's column and value first (a slot past the
+                    // row reads the row's last entry, in bounds, unused), so
+                    // that one LDS round trip serves all of them
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int kk = k + u * SL;
-                        const bool ok = kk < kend;
-                        const int c = ok ? sC[kk - cb] : 0;
-                        v[u] = ok ? sV[kk - cb] : 0.0;
-                        // a column inside this tile's rows: its P row is in LDS
-                        const unsigned lc = (unsigned)(c - (int)r0);
-                        if (!REG && lc < (unsigned)rows) {
+                        const int kc = (kk < kend ? kk : kend - 1) - cb;
+                        c[u] = sC[kc];
+                        v[u] = sV[kc];
+                    }
 #pragma unroll
-                            for (int q = 0; q < V; ++q) x[u][q] = sP[lc * S + jv + q];
-                        } else {
-                            load_cols<V>(P + (int64_t)c * S + jv, x[u]);
-                        }
+                    for (int u = 0; u < U; ++u) {
+                        lc[u] = REG ? ~0u : (unsigned)(c[u] - (int)r0);
+                        if (k + u * SL < kend && (REG || lc[u] >= (unsigned)rows))
+                            load_cols<V>(P + (int64_t)c[u] * S + jv, x[u]);
                     }
 #pragma unroll
                     for (int u = 0; u < U; ++u)
                         if (k + u * SL < kend) {
+                            if (!REG && lc[u] < (unsigned)rows) {
+#pragma unroll
+                                for (int q = 0; q < V; ++q) x[u][q] = sP[lc[u] * S + jv + q];
+                            }
 #pragma unroll
                             for (int q = 0; q < V; ++q) acc[i][q] += v[u] * x[u][q];
                         }

@@ -20,8 +20,57 @@ name matches --record-filter, keyed "S,T,SL,V,U,W@workgroups" for the block
 product (the template arguments of its tile shape) and by the full name
 otherwise, with a hash of the listed kernel sources (under the package's
 csrc/) so that a reader can tell whether the record still describes the
-kernel it is used for."""
-import argparse, collections, csv, re, sqlite3, statistics
+kernel it is used for.
+
+    python3 -m paper_2608_07327_amd.rocprof_summary --counters A.csv [B.csv ...] [--filter RE]
+
+tabulates instead the mean of every counter (and derived metric) of the
+given --pmc passes per (kernel, grid), for the kernels matching --filter."""
+import argparse, collections, csv, re, sqlite3, statistics, sys
+
+
+def counters_table(paths, filt, busy_frac):
+    """Mean of each counter over the busy launches of every (kernel, grid)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    cols = []
+    for path in paths:
+        disp = collections.defaultdict(dict)
+        meta = {}
+        for r in csv.DictReader(open(path)):
+            k = re.sub(r'\(.*$', '', r['Kernel_Name']).replace('void ', '').replace('mb::', '')
+            if filt and not re.search(filt, k):
+                continue
+            key = (k, int(r['Dispatch_Id']))
+            name = r['Counter_Name']
+            disp[key][name] = disp[key].get(name, 0.0) + float(r['Counter_Value'])
+            meta[key] = (int(r['Grid_Size']) // max(1, int(r['Workgroup_Size'])),
+                         int(r['End_Timestamp']) - int(r['Start_Timestamp']))
+            if name not in cols:
+                cols.append(name)
+        groups = collections.defaultdict(list)
+        for key, cs in disp.items():
+            groups[(key[0], meta[key][0])].append((meta[key][1], cs))
+        for g, xs in groups.items():
+            m = max(t for t, _ in xs)
+            for t, cs in xs:
+                if t >= busy_frac * m:
+                    for name, v in cs.items():
+                        per[g][name].append(v)
+    print("| kernel | grid | " + " | ".join(cols) + " |")
+    print("|---|---:|" + "---:|" * len(cols))
+    for (k, g), cs in sorted(per.items()):
+        vals = [f"{statistics.mean(cs[c]):.4g}" if cs.get(c) else "" for c in cols]
+        print(f"| `{k[:70]}` | {g} | " + " | ".join(vals) + " |")
+
+
+if "--counters" in sys.argv:
+    cp = argparse.ArgumentParser()
+    cp.add_argument("--counters", nargs="+", required=True)
+    cp.add_argument("--filter", default="")
+    cp.add_argument("--busy-frac", type=float, default=0.2)
+    ca = cp.parse_args()
+    counters_table(ca.counters, ca.filter, ca.busy_frac)
+    sys.exit(0)
 
 ap = argparse.ArgumentParser()
 ap.add_argument("db"); ap.add_argument("fetch"); ap.add_argument("write")
