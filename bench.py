@@ -237,14 +237,16 @@ def leg_sparse(args, pois, steps, warmup):
     def cg(**kw):
         return check(solver.cg_solve(bd, x=x, **kw)[1], "cg")
 
-    # timed region: the headline solves (profile mode: the production launch
-    # sequence with HIP events between the kernels, which time the product)
+    # timed region: the headline solves (profile level 2: the production
+    # launch sequence, kernel by kernel, with HIP events around the block
+    # product only, which time it)
     infos = []
-    sec, _ = timed_runs(lambda: infos.append(mb(profile=1)) or infos[-1], steps, warmup, torch)
+    sec, _ = timed_runs(lambda: infos.append(mb(profile=2)) or infos[-1], steps, warmup, torch)
     infos = infos[warmup:]
-    cg_sec, cg_info = timed_runs(lambda: cg(profile=1), steps, 0, torch)
+    cg_sec, cg_info = timed_runs(lambda: cg(profile=2), steps, 0, torch)
     sec_graph, _ = timed_runs(lambda: mb(), steps, 0, torch)
     cg_sec_graph, _ = timed_runs(lambda: cg(), steps, 0, torch)
+    iphase = mb(profile=1)   # every phase timed (outside the timed region)
     mb()   # x of the MBPCG solve for the error against the oracle
     xs = x.cpu().numpy()
 
@@ -253,15 +255,15 @@ def leg_sparse(args, pois, steps, warmup):
     achieved = bytes_alg / (spmm_ms * 1e-3) / 1e9
     traffic = None if pois else traffic_from_profiles("spmm_diffusion3d_128_traffic.json",
                                                       shape_key(S, tuned[s]))
-    it = infos[-1]["iterations"]
-    phases = [v / max(1, it) for v in infos[-1]["ms_phase"][:5]]
+    it = iphase["iterations"]
+    phases = [v / max(1, it) for v in iphase["ms_phase"][:5]]
 
     sweep = None
     if not (args.no_sweep or pois):
         sweep = {}
         for sw in (1, 2, 4, 8, 16):
             inf = check(solver.solve(bd, x=x, s=sw, seed=W.uniform_block_seed(cfg, sw),
-                                     profile=1)[1], f"sweep s={sw}")
+                                     profile=2)[1], f"sweep s={sw}")
             ms = inf["ms_spmm"] / max(1, inf["spmm_launches"])
             tr = traffic_from_profiles("spmm_diffusion3d_128_traffic.json",
                                        shape_key(pad(sw), tuned[sw]))
@@ -449,14 +451,14 @@ def leg_dense(args, steps, warmup):
 
     runs = {}
     cg_sec, cg_info = timed_runs(lambda: check(solver.cg_solve(
-        bd, x=x, tol=tol, precond=M.PRECOND_NONE, profile=1)[1], "cg"), steps, warmup, torch)
+        bd, x=x, tol=tol, precond=M.PRECOND_NONE, profile=2)[1], "cg"), steps, warmup, torch)
     cg_r = true_res()
     cg_err = golden_err(g["cg"], cg_info, x.cpu().numpy(), g["sample_index"]) \
         if g is not None and "cg" in g else None
     for sw in (1, 4, 8, 16, 32):
         sec, info = timed_runs(lambda: check(solver.solve(
             bd, x=x, s=sw, tol=tol, precond=M.PRECOND_NONE, seed=W.uniform_block_seed(cfg, sw),
-            profile=1)[1], f"s={sw}"), steps, warmup, torch)
+            profile=2)[1], f"s={sw}"), steps, warmup, torch)
         r = true_res()
         err = None
         if g is not None and str(sw) in g.get("mbpcg", {}):
@@ -540,18 +542,18 @@ def leg_dense_mixed(args, steps, warmup):
 
     runs = {}
     cg_sec, cg_info = timed_runs(lambda: solver.cg_solve(
-        bd, x=x, tol=tol, precond=M.PRECOND_NONE, profile=1)[1], steps, warmup, torch)
+        bd, x=x, tol=tol, precond=M.PRECOND_NONE, profile=2)[1], steps, warmup, torch)
     runs["fp64_cg"] = (cg_sec, cg_info, true_res(), err_ref(), 1, "fp64")
     for prec, name, widths in ((M.FP32_IR, "fp32", (8, 16, 32)), (M.BF16_IR, "bf16", (8,))):
         for sw in widths:
             sec, info = timed_runs(lambda: solver.solve(
                 bd, x=x, s=sw, precision=prec, ir_tol=tol, precond=M.PRECOND_NONE,
-                seed=W.uniform_block_seed(cfg, sw), profile=1)[1],
+                seed=W.uniform_block_seed(cfg, sw), profile=2)[1],
                 steps if name == "fp32" else 1, warmup if name == "fp32" else 0, torch)
             runs[f"{name}_ir_s{sw}"] = (sec, info, true_res(), err_ref(), sw, name)
     sec, info = timed_runs(lambda: solver.solve(
         bd, x=x, s=16, tol=tol, precond=M.PRECOND_NONE, seed=W.uniform_block_seed(cfg, 16),
-        profile=1)[1], steps, warmup, torch)
+        profile=2)[1], steps, warmup, torch)
     runs["fp64_s16"] = (sec, info, true_res(), err_ref(), 16, "fp64")
     fp32 = {k: v for k, v in runs.items() if k.startswith("fp32")}
     ok = {k: v for k, v in fp32.items() if v[1]["status"] == 0}

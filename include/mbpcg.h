@@ -92,7 +92,8 @@ typedef struct {
     int32_t max_outer;      /* IR: outer iteration cap                                   */
     double* history;        /* optional host array [max_iter]: ||R_h|| / ||b|| per step  */
     int32_t poll_every;     /* iterations per graph launch between host checks; 0 = auto */
-    int32_t profile;        /* 1: time each phase with HIP events (no graphs)            */
+    int32_t profile;        /* 1: time each phase with HIP events (no graphs); 2: time
+                               only the block product (two events per iteration)       */
     int32_t block_size;     /* BLOCK_JACOBI: rows per diagonal block, 4, 8, 16 or 32     */
     double* X_out;          /* optional n x s row-major, same memory kind as b: the block */
                             /* iterate X = X~ + X0 at exit in the scaled space (Sec. 1), */

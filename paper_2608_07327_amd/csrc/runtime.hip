@@ -273,13 +273,15 @@ static mbpcg_status setup_bjac(Ctx& c, const Plan& pl) {
 // One iteration of Alg. 1's loop, from Xi to the new Sigma.  With ev (six
 // events) the phase boundaries are recorded: ev[0] before the product, ev[1]
 // after it, ev[2] after the Xi tail, ev[3] after the update, ev[4] after the
-// QR tail, ev[5] after the direction update.
+// QR tail, ev[5] after the direction update; at level 2 only ev[0] and ev[1].
 static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist,
-                                   const hipEvent_t* ev = nullptr) {
+                                   const hipEvent_t* ev = nullptr, int level = 1) {
     hipError_t e;
     const double* pr;
     int pn;
-    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], c.stream) : hipSuccess; };
+    auto mark = [&](int k) {
+        return ev && (level == 1 || k <= 1) ? hipEventRecord(ev[k], c.stream) : hipSuccess;
+    };
     if ((e = mark(0)) != hipSuccess) return e;
     if ((e = launch_product(c, pl, c.P, c.Q, c.part_a, c.st)) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
@@ -303,11 +305,15 @@ static hipError_t launch_iteration(Ctx& c, const Plan& pl, double* hist,
 }
 
 // One CG-CG step.  With ev: ev[0] before the vector update, ev[1] after it,
-// ev[2] after the SpMV, ev[3..5] after the tail.
+// ev[2] after the SpMV, ev[3..5] after the tail; at level 2 only ev[1] and
+// ev[2].
 static hipError_t launch_cg_iteration(Ctx& c, const Plan& pl, double* hist,
-                                      const hipEvent_t* ev = nullptr) {
+                                      const hipEvent_t* ev = nullptr, int level = 1) {
     hipError_t e;
-    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], c.stream) : hipSuccess; };
+    auto mark = [&](int k) {
+        return ev && (level == 1 || k == 1 || k == 2) ? hipEventRecord(ev[k], c.stream)
+                                                      : hipSuccess;
+    };
     if ((e = mark(0)) != hipSuccess) return e;
     if ((e = launch_cg_update(pl.nwg_e, c.n, c.P, c.W, c.Xt, c.R, c.Q, c.d, c.part_c, c.st,
                               c.stream, bj_of(c, pl))) != hipSuccess)
@@ -382,8 +388,10 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
         // kernels of every iteration (the per-step timing of Sec. 3, Table 2;
         // events recorded inside graphs do not carry timestamps here), and
         // polled like the graph path so the host never waits inside an
-        // iteration.
+        // iteration.  Level 2 records only the two events around the block
+        // product.
         constexpr int EV = 6;
+        const int level = p.profile == 2 ? 2 : 1;
         const int64_t max_it = p.max_iter + 2 * (int64_t)m + 2;
         int64_t issued = 0;
         auto issue_batch = [&](int slot) -> mbpcg_status {
@@ -394,7 +402,8 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
                     c.pev.push_back(e);
                 }
                 const hipEvent_t* ev = &c.pev[issued * EV];
-                CK(cg ? launch_cg_iteration(c, pl, c.hist, ev) : launch_iteration(c, pl, c.hist, ev));
+                CK(cg ? launch_cg_iteration(c, pl, c.hist, ev, level)
+                      : launch_iteration(c, pl, c.hist, ev, level));
             }
             CK(hipMemcpyAsync(c.pinned + 2 * slot, c.st, 8, hipMemcpyDeviceToHost, c.stream));
             CK(hipEventRecord(c.ev_poll[slot], c.stream));
@@ -416,6 +425,7 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
         for (int64_t i = 0; i < ran; ++i) {
             const hipEvent_t* ev = &c.pev[i * EV];
             for (int k = 0; k + 1 < EV; ++k) {
+                if (level == 2 && k != (cg ? 1 : 0)) continue;
                 float ms = 0.f;
                 CK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
                 const int q = cg ? (k == 1 ? 0 : (k == 0 ? 2 : 7)) : k;

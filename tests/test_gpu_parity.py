@@ -546,6 +546,28 @@ def test_repeat_solves_are_bitwise_identical():
     solver.close()
 
 
+def test_launch_modes_give_the_same_solve():
+    # graph mode, every phase timed, and only the block product timed: the
+    # same kernels in the same order, so bitwise the same x
+    A = W.diffusion3d(16)
+    b = W.rhs(A.n, 9)
+    say("launch modes")
+    solver = M.Solver.from_matrix(A)
+    x0, i0 = solver.solve(dev(b), s=4, seed=3)
+    x1, i1 = solver.solve(dev(b), s=4, seed=3, profile=1)
+    x2, i2 = solver.solve(dev(b), s=4, seed=3, profile=2)
+    assert i0["iterations"] == i1["iterations"] == i2["iterations"]
+    assert torch.equal(x0, x1) and torch.equal(x0, x2)
+    assert i2["spmm_launches"] == i1["spmm_launches"] > 0 and i2["ms_spmm"] > 0
+    assert all(v > 0 for v in i1["ms_phase"][:5])
+    assert all(v == 0 for v in i2["ms_phase"][1:5]) and i2["ms_phase"][0] > 0
+    c1, j1 = solver.cg_solve(dev(b), profile=1)
+    c2, j2 = solver.cg_solve(dev(b), profile=2)
+    assert j1["iterations"] == j2["iterations"] and torch.equal(c1, c2)
+    assert j2["spmm_launches"] == j1["spmm_launches"] > 0 and j2["ms_spmm"] > 0
+    solver.close()
+
+
 # ------------------------------------------------------ mixed precision (IR)
 def test_fp32_iterative_refinement_reaches_1e10():
     n = 512
