@@ -14,8 +14,10 @@ to that band:
   or the one before it) is within 1 % of tol, around the reference count;
 * when the GPU's count equals one of the runs' counts: x within
   max(floor, 10 f) of that run's x, with f the largest relative distance
-  between two of the three runs' x and floor 1e-10; used_fallback,
-  final_width and deflations equal wherever the three runs agree on them;
+  between two of the three runs' x and floor 1e-10 -- both normwise and
+  entry by entry (the largest entry difference over the largest entry,
+  against the same measure between the runs); used_fallback, final_width
+  and deflations equal wherever the three runs agree on them;
 * converged solves: FP64 true residual below 2 tol.
 
 No case is exempt: the least squares of the termination computes the same
@@ -86,6 +88,22 @@ def noise_floor(xo, xps):
     return max(float(np.linalg.norm(a - c)) / nb for k, a in enumerate(xs) for c in xs[k + 1:])
 
 
+def noise_floor_entries(xo, xps):
+    """The noise floor entry by entry: the largest difference of one entry
+    between two runs, over the reference run's largest entry."""
+    xs = [np.asarray(xo)] + [np.asarray(v) for v in xps]
+    m = float(np.max(np.abs(xs[0]))) if xs[0].size else 0.0
+    if m == 0.0:
+        return 0.0
+    return max(float(np.max(np.abs(a - c))) / m for k, a in enumerate(xs) for c in xs[k + 1:])
+
+
+def rel_entries(a, b):
+    m = float(np.max(np.abs(b))) if np.asarray(b).size else 0.0
+    d = float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) if np.asarray(b).size else 0.0
+    return d / m if m > 0 else d
+
+
 def check(x, info, xo, io, xps, ips, tol, floor=1e-10, what=""):
     """Assert the contract above; returns the measured |x - x_ref| / |x_ref|
     against the run with the same count (None when no run has it)."""
@@ -100,6 +118,9 @@ def check(x, info, xo, io, xps, ips, tol, floor=1e-10, what=""):
         if info["iterations"] == iref["iterations"]:
             err = rel(x, ref)
             assert err <= max(floor, 10 * f), (what, iref.get("variant"), err, f)
+            fe = noise_floor_entries(xo, xps)
+            ee = rel_entries(x, ref)
+            assert ee <= max(floor, 10 * fe), (what, "entries", iref.get("variant"), ee, fe)
             for key in ("used_fallback", "final_width", "deflations"):
                 if all(ip[key] == io[key] for ip in ips):
                     assert info[key] == iref[key], (what, key, info[key], iref[key])
@@ -126,6 +147,11 @@ def check_golden(x_sample, info, o, tol, floor=1e-10, what=""):
             xr = np.asarray(o[xsk])
             err = float(np.linalg.norm(np.asarray(x_sample) - xr) / np.linalg.norm(xr))
             assert err <= max(floor, 10 * o["noise_floor"]), (what, key, err, o["noise_floor"])
+            # entry by entry on the sampled indices, against the same measure
+            # between the three runs' sampled x
+            fe = noise_floor_entries(o["x_sample"], [o["pairwise_x_sample"], o["fma_x_sample"]])
+            ee = rel_entries(x_sample, xr)
+            assert ee <= max(floor, 10 * fe), (what, key, "entries", ee, fe)
             if key == "iterations":
                 for k2 in ("final_width", "deflations"):
                     if k2 in info:
