@@ -197,6 +197,23 @@ def test_diffusion3d_against_oracle(s):
     check_against_oracle(A, b, s, seed=W.uniform_block_seed(2, s))
 
 
+@pytest.mark.parametrize("s", [5, 6, 7, 12, 24])
+def test_padded_widths_against_oracle(s):
+    # s below the padded block width S (8, 16, 32): the inactive columns
+    # stay zero through the product, the Grams, the Cholesky QR and the
+    # least squares
+    A = W.diffusion3d(20)
+    b = W.rhs(A.n, W.CFG_DIFFUSION3D)
+    check_against_oracle(A, b, s, seed=W.uniform_block_seed(2, s))
+
+
+@pytest.mark.parametrize("s", [5, 12, 20])
+def test_padded_widths_dense_against_oracle(s):
+    A = W.dense_spd(600, tag=(3, 41))
+    b = W.rng_for((3, 42)).standard_normal(600)
+    check_against_oracle(A, b, s, jacobi=False, seed=W.uniform_block_seed(3, s))
+
+
 @pytest.mark.parametrize("s", [1, 4, 8, 16, 32])
 def test_dense_against_oracle(s):
     # n = 600: two 256-row tiles and a ragged tail, two column ranges
