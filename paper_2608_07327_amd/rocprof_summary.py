@@ -63,146 +63,161 @@ def counters_table(paths, filt, busy_frac):
         print(f"| `{k[:70]}` | {g} | " + " | ".join(vals) + " |")
 
 
-if "--counters" in sys.argv:
+def counters_main(argv=None):
     cp = argparse.ArgumentParser()
     cp.add_argument("--counters", nargs="+", required=True)
     cp.add_argument("--filter", default="")
     cp.add_argument("--busy-frac", type=float, default=0.2)
-    ca = cp.parse_args()
+    ca = cp.parse_args(argv)
     counters_table(ca.counters, ca.filter, ca.busy_frac)
-    sys.exit(0)
 
-ap = argparse.ArgumentParser()
-ap.add_argument("db"); ap.add_argument("fetch"); ap.add_argument("write")
-ap.add_argument("mfma", nargs="?")
-ap.add_argument("--filter", default="")
-ap.add_argument("--simds", type=int, default=1024)
-ap.add_argument("--xcds", type=int, default=8)
-ap.add_argument("--top", type=int, default=30)
-ap.add_argument("--record", default="")
-ap.add_argument("--sources", default="")
-ap.add_argument("--record-filter", default="k_spmm")
-ap.add_argument("--workload", default="")
-ap.add_argument("--busy-frac", type=float, default=0.2,
-                help="launches shorter than this fraction of their kernel's (and grid's) "
-                     "longest are left out")
-a = ap.parse_args()
 
-def short(name):
-    name = re.sub(r'\(.*$', '', name)
-    return name.replace('void ', '').replace('mb::', '')
+def summary(argv=None):
+    """The per-kernel summary (and the counter record) of a trace and two
+    counter passes."""
+    ap = argparse.ArgumentParser()
+    ap.add_argument("db"); ap.add_argument("fetch"); ap.add_argument("write")
+    ap.add_argument("mfma", nargs="?")
+    ap.add_argument("--filter", default="")
+    ap.add_argument("--simds", type=int, default=1024)
+    ap.add_argument("--xcds", type=int, default=8)
+    ap.add_argument("--top", type=int, default=30)
+    ap.add_argument("--record", default="")
+    ap.add_argument("--sources", default="")
+    ap.add_argument("--record-filter", default="k_spmm")
+    ap.add_argument("--workload", default="")
+    ap.add_argument("--busy-frac", type=float, default=0.2,
+                    help="launches shorter than this fraction of their kernel's (and grid's) "
+                         "longest are left out")
+    a = ap.parse_args(argv)
 
-con = sqlite3.connect(a.db)
-cur = con.cursor()
-tab = [r[0] for r in cur.execute("select name from sqlite_master where name like 'rocpd_kernel_dispatch%'")][0]
-stab = [r[0] for r in cur.execute("select name from sqlite_master where name like 'rocpd_info_kernel_symbol%'")][0]
-scols = [r[1] for r in cur.execute(f"pragma table_info({stab})")]
-names = {r[0]: r[1] for r in cur.execute(f"select id, {'display_name' if 'display_name' in scols else 'kernel_name'} from {stab}")}
-dcols = [r[1] for r in cur.execute(f"pragma table_info({tab})")]
-has_grid = 'grid_size_x' in dcols and 'workgroup_size_x' in dcols
-dur = collections.defaultdict(list)
-dur_grid = collections.defaultdict(list)   # (kernel, workgroups) -> durations
-q = f"select kernel_id, start, end{', grid_size_x, workgroup_size_x' if has_grid else ''} from {tab}"
-for row in cur.execute(q):
-    kid, s, e = row[:3]
-    dur[short(names.get(kid, str(kid)))].append((e - s) / 1000.0)
-    if has_grid and row[4]:
-        dur_grid[(short(names.get(kid, str(kid))), row[3] // row[4])].append((e - s) / 1000.0)
+    def short(name):
+        name = re.sub(r'\(.*$', '', name)
+        return name.replace('void ', '').replace('mb::', '')
 
-def load(path):
-    per = collections.defaultdict(dict)   # (kernel, dispatch) -> counter -> value
-    t = {}
-    for r in csv.DictReader(open(path)):
-        key = (short(r['Kernel_Name']), int(r['Dispatch_Id']))
-        per[key][r['Counter_Name']] = per[key].get(r['Counter_Name'], 0.0) + float(r['Counter_Value'])
-        t[key] = ((int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1000.0,
-                  int(r['Grid_Size']) // max(1, int(r['Workgroup_Size'])))
-    out = collections.defaultdict(list)
-    for key, cs in per.items():
-        out[key[0]].append((cs, t[key][0], t[key][1]))
-    return out
+    con = sqlite3.connect(a.db)
+    cur = con.cursor()
+    tab = [r[0] for r in cur.execute("select name from sqlite_master where name like 'rocpd_kernel_dispatch%'")][0]
+    stab = [r[0] for r in cur.execute("select name from sqlite_master where name like 'rocpd_info_kernel_symbol%'")][0]
+    scols = [r[1] for r in cur.execute(f"pragma table_info({stab})")]
+    names = {r[0]: r[1] for r in cur.execute(f"select id, {'display_name' if 'display_name' in scols else 'kernel_name'} from {stab}")}
+    dcols = [r[1] for r in cur.execute(f"pragma table_info({tab})")]
+    has_grid = 'grid_size_x' in dcols and 'workgroup_size_x' in dcols
+    dur = collections.defaultdict(list)
+    dur_grid = collections.defaultdict(list)   # (kernel, workgroups) -> durations
+    q = f"select kernel_id, start, end{', grid_size_x, workgroup_size_x' if has_grid else ''} from {tab}"
+    for row in cur.execute(q):
+        kid, s, e = row[:3]
+        dur[short(names.get(kid, str(kid)))].append((e - s) / 1000.0)
+        if has_grid and row[4]:
+            dur_grid[(short(names.get(kid, str(kid))), row[3] // row[4])].append((e - s) / 1000.0)
 
-F, Wr = load(a.fetch), load(a.write)
-Mf = load(a.mfma) if a.mfma else {}
-cf = max(c['FETCH_SIZE'] for c, *_ in F['k_stream_copy'])
-cw = max(c['WRITE_SIZE'] for c, *_ in Wr['k_stream_copy'])
-ff, fw = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
-print(f"calibration (1 GiB k_stream_copy): FETCH_SIZE {cf:.0f} KiB (factor {ff:.3f}), "
-      f"WRITE_SIZE {cw:.0f} KiB (factor {fw:.3f})")
-
-def busy(xs, key):
-    if not xs: return []
-    m = max(key(x) for x in xs)
-    return [x for x in xs if key(x) >= a.busy_frac * m]
-
-rows = []
-for k in sorted(set(dur) | set(F)):
-    if a.filter and not re.search(a.filter, k): continue
-    d = busy(dur.get(k, []), lambda x: x)
-    f = busy(F.get(k, []), lambda x: x[1])
-    w = busy(Wr.get(k, []), lambda x: x[1])
-    avg = statistics.mean(d) if d else float('nan')
-    fm = statistics.mean(c['FETCH_SIZE'] for c, *_ in f) * 1024 * ff / 1e6 if f else float('nan')
-    wm = statistics.mean(c['WRITE_SIZE'] for c, *_ in w) * 1024 * fw / 1e6 if w else float('nan')
-    extra = ""
-    if Mf.get(k):
-        m = busy(Mf[k], lambda x: x[1])
-        busyc = sum(c.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) for c, *_ in m)
-        gui = sum(c.get('GRBM_GUI_ACTIVE', 0) for c, *_ in m)
-        mops = {p: sum(c.get(f'SQ_INSTS_VALU_MFMA_MOPS_{p}', 0) for c, *_ in m) / len(m) for p in ('F64', 'F32', 'BF16')}
-        # GRBM_GUI_ACTIVE is counted on every XCD and summed
-        util = 100.0 * busyc / (gui / a.xcds * a.simds) if gui else float('nan')
-        mt = statistics.mean(t for _, t, _ in m)
-        fl = {p: v * 512 for p, v in mops.items() if v}
-        extra = f"  MFMA busy {util:5.1f}%" + "".join(f"  {p} {v/1e9:.1f} GFLOP/launch ({v/(mt*1e-6)/1e12:.1f} TFLOP/s)" for p, v in fl.items())
-    rows.append((sum(d), k, len(d), avg, fm, wm, extra))
-rows.sort(reverse=True)
-print(f"| kernel | launches | avg us | fetch MB/launch | write MB/launch | MFMA |")
-print("|---|---:|---:|---:|---:|---|")
-for tot, k, nl, avg, fm, wm, extra in rows[:a.top]:
-    print(f"| `{k[:80]}` | {nl} | {avg:.2f} | {fm:.1f} | {wm:.1f} | {extra.strip()} |")
-
-if a.record:
-    import hashlib, json, os
-    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-    srcs = [v for v in a.sources.split(",") if v]
-    h = hashlib.sha256()
-    for f in srcs:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-
-    def rkey(k, g):
-        m = re.match(r"k_spmm<BpShape<([\d, ]+)> >", k)
-        base = m.group(1).replace(" ", "") if m else k
-        return f"{base}@{g}"
-
-    def by_grid(xs):
+    def load(path):
+        per = collections.defaultdict(dict)   # (kernel, dispatch) -> counter -> value
+        t = {}
+        for r in csv.DictReader(open(path)):
+            key = (short(r['Kernel_Name']), int(r['Dispatch_Id']))
+            per[key][r['Counter_Name']] = per[key].get(r['Counter_Name'], 0.0) + float(r['Counter_Value'])
+            t[key] = ((int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1000.0,
+                      int(r['Grid_Size']) // max(1, int(r['Workgroup_Size'])))
         out = collections.defaultdict(list)
-        for x in xs:
-            out[x[2]].append(x)
+        for key, cs in per.items():
+            out[key[0]].append((cs, t[key][0], t[key][1]))
         return out
 
-    per_shape = {}
-    for k in sorted(F):
-        if not re.search(a.record_filter, k):
-            continue
-        fg, wg = by_grid(F[k]), by_grid(Wr.get(k, []))
-        for g, fx in fg.items():
-            f = busy(fx, lambda x: x[1])
-            w = busy(wg.get(g, []), lambda x: x[1])
-            if not f or not w:
+    F, Wr = load(a.fetch), load(a.write)
+    Mf = load(a.mfma) if a.mfma else {}
+    cf = max(c['FETCH_SIZE'] for c, *_ in F['k_stream_copy'])
+    cw = max(c['WRITE_SIZE'] for c, *_ in Wr['k_stream_copy'])
+    ff, fw = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
+    print(f"calibration (1 GiB k_stream_copy): FETCH_SIZE {cf:.0f} KiB (factor {ff:.3f}), "
+          f"WRITE_SIZE {cw:.0f} KiB (factor {fw:.3f})")
+
+    def busy(xs, key):
+        if not xs: return []
+        m = max(key(x) for x in xs)
+        return [x for x in xs if key(x) >= a.busy_frac * m]
+
+    rows = []
+    for k in sorted(set(dur) | set(F)):
+        if a.filter and not re.search(a.filter, k): continue
+        d = busy(dur.get(k, []), lambda x: x)
+        f = busy(F.get(k, []), lambda x: x[1])
+        w = busy(Wr.get(k, []), lambda x: x[1])
+        avg = statistics.mean(d) if d else float('nan')
+        fm = statistics.mean(c['FETCH_SIZE'] for c, *_ in f) * 1024 * ff / 1e6 if f else float('nan')
+        wm = statistics.mean(c['WRITE_SIZE'] for c, *_ in w) * 1024 * fw / 1e6 if w else float('nan')
+        extra = ""
+        if Mf.get(k):
+            m = busy(Mf[k], lambda x: x[1])
+            busyc = sum(c.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) for c, *_ in m)
+            gui = sum(c.get('GRBM_GUI_ACTIVE', 0) for c, *_ in m)
+            mops = {p: sum(c.get(f'SQ_INSTS_VALU_MFMA_MOPS_{p}', 0) for c, *_ in m) / len(m) for p in ('F64', 'F32', 'BF16')}
+            # GRBM_GUI_ACTIVE is counted on every XCD and summed
+            util = 100.0 * busyc / (gui / a.xcds * a.simds) if gui else float('nan')
+            mt = statistics.mean(t for _, t, _ in m)
+            fl = {p: v * 512 for p, v in mops.items() if v}
+            extra = f"  MFMA busy {util:5.1f}%" + "".join(f"  {p} {v/1e9:.1f} GFLOP/launch ({v/(mt*1e-6)/1e12:.1f} TFLOP/s)" for p, v in fl.items())
+        rows.append((sum(d), k, len(d), avg, fm, wm, extra))
+    rows.sort(reverse=True)
+    print(f"| kernel | launches | avg us | fetch MB/launch | write MB/launch | MFMA |")
+    print("|---|---:|---:|---:|---:|---|")
+    for tot, k, nl, avg, fm, wm, extra in rows[:a.top]:
+        print(f"| `{k[:80]}` | {nl} | {avg:.2f} | {fm:.1f} | {wm:.1f} | {extra.strip()} |")
+
+    if a.record:
+        import hashlib, json, os
+        csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+        srcs = [v for v in a.sources.split(",") if v]
+        h = hashlib.sha256()
+        for f in srcs:
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+
+        def rkey(k, g):
+            m = re.match(r"k_spmm<BpShape<([\d, ]+)> >", k)
+            base = m.group(1).replace(" ", "") if m else k
+            return f"{base}@{g}"
+
+        def by_grid(xs):
+            out = collections.defaultdict(list)
+            for x in xs:
+                out[x[2]].append(x)
+            return out
+
+        per_shape = {}
+        for k in sorted(F):
+            if not re.search(a.record_filter, k):
                 continue
-            fb = statistics.mean(c['FETCH_SIZE'] for c, *_ in f) * 1024 * ff
-            wb = statistics.mean(c['WRITE_SIZE'] for c, *_ in w) * 1024 * fw
-            d = busy(dur_grid.get((k, g), []), lambda x: x)
-            per_shape[rkey(k, g)] = {
-                "fetch_bytes": round(fb), "write_bytes": round(wb), "bytes_per_launch": round(fb + wb),
-                "launches": len(f), "avg_us": round(statistics.mean(d), 2) if d else None}
-    rec = {"kernel_hash": h.hexdigest()[:16],
-           "hashed_sources": [f"paper_2608_07327_amd/csrc/{f}" for f in srcs],
-           "workload": a.workload,
-           "calibration": {"fetch_factor": ff, "write_factor": fw, "copy_bytes": 1 << 30},
-           "per_shape": per_shape}
-    with open(a.record, "w") as fh:
-        json.dump(rec, fh, indent=1, sort_keys=True)
-    print(f"record: {len(per_shape)} (kernel, grid) entries -> {a.record}")
+            fg, wg = by_grid(F[k]), by_grid(Wr.get(k, []))
+            for g, fx in fg.items():
+                f = busy(fx, lambda x: x[1])
+                w = busy(wg.get(g, []), lambda x: x[1])
+                if not f or not w:
+                    continue
+                fb = statistics.mean(c['FETCH_SIZE'] for c, *_ in f) * 1024 * ff
+                wb = statistics.mean(c['WRITE_SIZE'] for c, *_ in w) * 1024 * fw
+                d = busy(dur_grid.get((k, g), []), lambda x: x)
+                per_shape[rkey(k, g)] = {
+                    "fetch_bytes": round(fb), "write_bytes": round(wb), "bytes_per_launch": round(fb + wb),
+                    "launches": len(f), "avg_us": round(statistics.mean(d), 2) if d else None}
+        rec = {"kernel_hash": h.hexdigest()[:16],
+               "hashed_sources": [f"paper_2608_07327_amd/csrc/{f}" for f in srcs],
+               "workload": a.workload,
+               "calibration": {"fetch_factor": ff, "write_factor": fw, "copy_bytes": 1 << 30},
+               "per_shape": per_shape}
+        with open(a.record, "w") as fh:
+            json.dump(rec, fh, indent=1, sort_keys=True)
+        print(f"record: {len(per_shape)} (kernel, grid) entries -> {a.record}")
+
+
+def main(argv=None):
+    argv = sys.argv[1:] if argv is None else argv
+    if "--counters" in argv:
+        counters_main(argv)
+    else:
+        summary(argv)
+
+
+if __name__ == "__main__":
+    main()
