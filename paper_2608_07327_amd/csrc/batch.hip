@@ -1415,7 +1415,10 @@ mbpcg_status batch_tune(BatchCtx& c, const mbpcg_params& p, mbpcg_batch_tuning* 
         const int keep = c.grid;
         c.grid = g;
         double t = 0.0;
-        if ((st = trial(&t)) != MBPCG_OK) return st;
+        if ((st = trial(&t)) != MBPCG_OK) {
+            c.grid = keep;   // the context stays on a grid that was tuned
+            return st;
+        }
         if (t < 0.99 * best) {
             best = t;
             best_grid = g;
