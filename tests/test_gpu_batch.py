@@ -64,6 +64,17 @@ def test_batch_of_graph_laplacians():
     assert st == 0
 
 
+def test_batch_padded_widths_against_oracle():
+    # s = 5, 6, 7 carried at the padded width 8, s = 2 at 2, beside each
+    # other in one launch
+    A = W.poisson2d(40)
+    B3 = W.diffusion3d(14)
+    sys_list = [W.BatchSystem(A, W.rhs(A.n, 51), 5), W.BatchSystem(B3, W.rhs(B3.n, 52), 6),
+                W.BatchSystem(A, W.rhs(A.n, 53), 7), W.BatchSystem(B3, W.rhs(B3.n, 54), 2)]
+    st, infos = check_batch(sys_list, seed=300)
+    assert st == 0
+
+
 def test_batch_mixes_stencils_widths_and_edge_cases():
     A = W.poisson2d(32)
     sys_list = [
