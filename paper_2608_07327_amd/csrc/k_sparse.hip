@@ -9,8 +9,10 @@
 // adjacent columns jv .. jv+V-1 of P (16-byte loads for V = 2, 4) over every
 // SL-th nonzero of the row, with U gathers in flight; for S > 2 the tile's own
 // rows of P are staged in LDS (the Gram's operand) and a nonzero whose
-// column falls inside the tile reads its P row from there.  Q leaves the
-// lanes' registers with coalesced non-temporal vector stores.
+// column falls inside the tile reads its P row from there.  Q leaves with
+// non-temporal vector stores: for S <= 2 from the lanes' registers, for
+// S > 2 from the tile's Q rows in LDS (the Gram's other operand), one
+// contiguous range, so that every store instruction fills whole lines.
 //
 // Gram epilogue, chosen by width so that it costs few registers (the kernel
 // lives on occupancy: its gathers' latency is hidden by other wavefronts):
@@ -302,8 +304,8 @@ void k_spmm(const int32_t* __restrict__ rowptr,
                 acc[i][q] = a;
             }
             if (slot == 0 && rl < T) {
-                if (rl < rows) store_cols<V>(Q + (r0 + rl) * S + jv, acc[i]);
                 if constexpr (REG) {
+                    if (rl < rows) store_cols<V>(Q + (r0 + rl) * S + jv, acc[i]);
 #pragma unroll
                     for (int c = 0; c < S; ++c)
 #pragma unroll
@@ -315,8 +317,11 @@ void k_spmm(const int32_t* __restrict__ rowptr,
             }
         }
         if constexpr (!REG) {
+            // the tile's Q rows are one contiguous range of rows * S values:
+            // they leave LDS with 16-byte stores that fill whole lines
+            __syncthreads();
+            for (int e = 2 * tid; e < rows * S; e += 2 * MB_BLOCK) store_cols<2>(Q + r0 * S + e, &sQ[e]);
             if (gram) {
-                __syncthreads();
                 if constexpr (MF)
                     gm.add_tile(rows, [&](int r, int c) { return sP[r * S + c]; },
                                 [&](int r, int c) { return sQ[r * S + c]; });
