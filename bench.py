@@ -87,6 +87,7 @@ def source_hash(files) -> str:
 
 
 SPMM_SOURCES = ("k_sparse.hip", "dev_common.hpp", "dev_spmm.hpp")
+DENSE_SOURCES = ("k_dense.hip", "dev_common.hpp")
 BATCH_SOURCES = ("batch.hip", "dev_common.hpp", "dev_spmm.hpp", "dev_sxs.hpp", "dev_dd.hpp")
 
 
@@ -105,10 +106,11 @@ def shape_key(S: int, t: dict) -> str:
         f"@{t['workgroups']}"
 
 
-def traffic_from_profiles(name: str, key: str, sources=SPMM_SOURCES):
+def traffic_from_profiles(name: str, key: str, sources=SPMM_SOURCES, any_grid=False):
     """HBM bytes per launch of `key` from the committed counter record
     profiles/<name>, if it was taken on the current source of `sources`;
-    else None."""
+    else None.  any_grid: `key` is a kernel name and the record's one entry
+    for it (on whatever grid it ran) is used."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -118,7 +120,12 @@ def traffic_from_profiles(name: str, key: str, sources=SPMM_SOURCES):
         return None
     if rec.get("kernel_hash") != source_hash(sources):
         return None
-    ent = rec.get("per_shape", {}).get(key)
+    ps = rec.get("per_shape", {})
+    if any_grid:
+        keys = [k for k in ps if k.split("@")[0] == key]
+        ent = ps[keys[0]] if len(keys) == 1 else None
+    else:
+        ent = ps.get(key)
     return None if ent is None else ent.get("bytes_per_launch")
 
 
@@ -495,8 +502,8 @@ def leg_dense(args, steps, warmup):
         "roofline": dense_product_roofline(
             info, n, S, "fp64",
             f"k_dense_f64 S={S} (v_mfma_f64_16x16x4f64, split over column ranges) + reduce/Gram",
-            traffic_from_profiles("dense_products_traffic.json", f"f64,{n},{S}",
-                                  ("k_dense.hip", "dev_common.hpp"))),
+            traffic_from_profiles("dense_8192_traffic.json", f"k_dense_f64<{S}>", DENSE_SOURCES,
+                                  any_grid=True) if n == 8192 else None),
         "cpu_baseline": cpu,
         "sweep": sweep,
     }
@@ -606,8 +613,8 @@ def leg_dense_mixed(args, steps, warmup):
         "roofline": dense_product_roofline(
             info, n, S, "fp32",
             f"k_dense_f32 S={S} (v_mfma_f32_16x16x4f32 on the tiled FP32 copy) + reduce/Gram",
-            traffic_from_profiles("dense_products_traffic.json", f"f32,{n},{S}",
-                                  ("k_dense.hip", "dev_common.hpp"))),
+            traffic_from_profiles("dense_mixed_16384_traffic.json", f"k_dense_f32<{S}>",
+                                  DENSE_SOURCES, any_grid=True) if n == 16384 else None),
         "cpu_baseline": cpu,
         "sweep": sweep,
     }

@@ -12,8 +12,9 @@
 //   FP64:  v_mfma_f64_16x16x4f64 on the caller's column-major A.
 //   FP32:  v_mfma_f32_16x16x4f32 on a tiled FP32 copy of A.
 //   BF16:  v_mfma_f32_16x16x32_bf16 on a tiled BF16 copy of A.
-// Low-precision kinds accumulate in FP32 inside a workgroup; partials are
-// stored and added in FP64.
+// Low-precision kinds accumulate in FP32 inside a workgroup; their partials
+// are stored as FP32 (the accumulators' values, half the bytes of FP64) and
+// added in FP64.
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double*
             const int64_t k = k0 + 4 * q + lk;
             const bool kin = k < kend;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[q][t] = (kin && rok[t]) ? A[k * lda + row[t]] : 0.0;
+            for (int t = 0; t < 4; ++t) a[q][t] = (kin && rok[t]) ? stream_load(A + k * lda + row[t]) : 0.0;
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 const int j = 16 * c + li;
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double*
 template <int S>
 __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* __restrict__ A,
                                                         const float* __restrict__ P,
-                                                        double* __restrict__ qpart, int ksplit,
+                                                        float* __restrict__ qpart, int ksplit,
                                                         const DevState* __restrict__ st) {
     if (st && st->done) return;
     constexpr int CT = S >= 16 ? S / 16 : 1;
@@ -152,14 +153,19 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* 
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+    // k-step kc (kc0 <= kc < kc1) with no branches: a row tile past the
+    // matrix and a column past S read an in-range tile or column instead,
+    // whose products land only in rows and columns that are never stored
+    int64_t rtc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) rtc[t] = rok[t] ? rt[t] : RT - 1;
     auto load = [&](int64_t kc, f4* a, f4* bv) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            a[t] = (rok[t] && kc < kc1) ? A4[(rt[t] * NK + kc) * 64 + l] : f4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < 4; ++t) a[t] = stream_load(A4 + (rtc[t] * NK + kc) * 64 + l);
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int j = 16 * c + li;
-            bv[c] = (j < S && kc < kc1) ? P4[(4 * kc + lk) * S + j] : f4{0.f, 0.f, 0.f, 0.f};
+            bv[c] = P4[(4 * kc + lk) * S + (j < S ? j : S - 1)];
         }
     };
     auto mma = [&](const f4* a, const f4* bv) {
@@ -172,15 +178,41 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* 
                     acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bv[c][u], acc[t][c],
                                                                      0, 0, 0);
     };
-    // two k-steps per trip: both steps' loads are issued before either's MFMAs
-    for (int64_t kc = kc0; kc < kc1; kc += 2) {
-        f4 a0[4], b0[CT], a1[4], b1[CT];
-        load(kc, a0, b0);
+    // k-steps in pairs, one register set per step, two sets in turn: the next
+    // step's loads go out before this step's MFMAs, so a wavefront keeps a
+    // step of A in flight while its matrix-core work runs.  The last prefetch
+    // re-reads the final step (an in-range address, no branch: the waits
+    // before each MFMA then count only the loads they need).  An odd count
+    // ends with the last step and an all-zero step, the same MFMAs in the
+    // same order as a pair whose second step is past the range.
+    const f4 z4 = {0.f, 0.f, 0.f, 0.f};
+    const int64_t kp = kc0 + ((kc1 - kc0) & ~(int64_t)1);
+    f4 a0[4], b0[CT], a1[4], b1[CT];
+    int64_t kc = kc0;
+    if (kc < kp) load(kc, a0, b0);
+    for (; kc < kp; kc += 2) {
         load(kc + 1, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);   // the loads stay ahead of the MFMAs
+        mma(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(kc + 2 < kp ? kc + 2 : kp - 1, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (kc < kc1) {
+        load(kc, a0, b0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a1[t] = z4;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b1[c] = z4;
         mma(a0, b0);
         mma(a1, b1);
     }
-    double* out = qpart + (int64_t)ks * n * S;
+    // D layout of the FP32-accumulating MFMAs: lane l, element v -> row
+    // 4 (l/16) + v, column l % 16.  The partials are the FP32 accumulators
+    // themselves, stored as FP32 (half the bytes of FP64, the same values)
+    float* out = qpart + (int64_t)ks * n * S;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -189,14 +221,14 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* 
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = rt[t] * 16 + 4 * lk + v;
                 const int j = 16 * c + li;
-                if (r < n && j < S) out[r * S + j] = (double)acc[t][c][v];
+                if (r < n && j < S) out[r * S + j] = acc[t][c][v];
             }
 }
 
 template <int S>
 __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16* __restrict__ A,
                                                          const __bf16* __restrict__ P,
-                                                         double* __restrict__ qpart, int ksplit,
+                                                         float* __restrict__ qpart, int ksplit,
                                                          const DevState* __restrict__ st) {
     if (st && st->done) return;
     constexpr int CT = S >= 16 ? S / 16 : 1;
@@ -223,14 +255,17 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+    // k-step kc (kc0 <= kc < kc1) with no branches, as in the FP32 kernel
+    int64_t rtc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) rtc[t] = rok[t] ? rt[t] : RT - 1;
     auto load = [&](int64_t kc, bf8* a, bf8* bv) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            a[t] = (rok[t] && kc < kc1) ? A8[(rt[t] * NK + kc) * 64 + l] : zero8;
+        for (int t = 0; t < 4; ++t) a[t] = stream_load(A8 + (rtc[t] * NK + kc) * 64 + l);
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int j = 16 * c + li;
-            bv[c] = (j < S && kc < kc1) ? P8[(4 * kc + lk) * S + j] : zero8;
+            bv[c] = P8[(4 * kc + lk) * S + (j < S ? j : S - 1)];
         }
     };
     auto mma = [&](const bf8* a, const bf8* bv) {
@@ -240,15 +275,34 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16
             for (int t = 0; t < 4; ++t)
                 acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bv[c], acc[t][c], 0, 0, 0);
     };
-    // two k-steps per trip: both steps' loads are issued before either's MFMAs
-    for (int64_t kc = kc0; kc < kc1; kc += 2) {
-        bf8 a0[4], b0[CT], a1[4], b1[CT];
-        load(kc, a0, b0);
+    // the FP32 kernel's step order and prefetch
+    const int64_t kp = kc0 + ((kc1 - kc0) & ~(int64_t)1);
+    bf8 a0[4], b0[CT], a1[4], b1[CT];
+    int64_t kc = kc0;
+    if (kc < kp) load(kc, a0, b0);
+    for (; kc < kp; kc += 2) {
         load(kc + 1, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);   // the loads stay ahead of the MFMAs
+        mma(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(kc + 2 < kp ? kc + 2 : kp - 1, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (kc < kc1) {
+        load(kc, a0, b0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a1[t] = zero8;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b1[c] = zero8;
         mma(a0, b0);
         mma(a1, b1);
     }
-    double* out = qpart + (int64_t)ks * n * S;
+    // D layout of the FP32-accumulating MFMAs: lane l, element v -> row
+    // 4 (l/16) + v, column l % 16.  The partials are the FP32 accumulators
+    // themselves, stored as FP32 (half the bytes of FP64, the same values)
+    float* out = qpart + (int64_t)ks * n * S;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -257,15 +311,15 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = rt[t] * 16 + 4 * lk + v;
                 const int j = 16 * c + li;
-                if (r < n && j < S) out[r * S + j] = (double)acc[t][c][v];
+                if (r < n && j < S) out[r * S + j] = acc[t][c][v];
             }
 }
 
 // Q = sum over k-ranges of the partials (fixed order) and the lower triangle
 // of P^T Q per workgroup, as the sparse block product's epilogue.
-template <int S>
+template <int S, class PT>
 __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit,
-                                                           const double* __restrict__ qpart,
+                                                           const PT* __restrict__ qpart,
                                                            const double* __restrict__ P,
                                                            double* __restrict__ Q,
                                                            double* __restrict__ part,
@@ -315,7 +369,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit
 #pragma unroll
             for (int q = 0; q < EPT; ++q)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[q][u] = qpart[(k + u) * nS + gq[q]];
+                for (int u = 0; u < 4; ++u) v[q][u] = (double)qpart[(k + u) * nS + gq[q]];
 #pragma unroll
             for (int q = 0; q < EPT; ++q)
 #pragma unroll
@@ -323,7 +377,7 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_reduce(int64_t n, int ksplit
         }
         for (int u = 0; k < ksplit; ++k, ++u)
 #pragma unroll
-            for (int q = 0; q < EPT; ++q) q4[q][u] += qpart[k * nS + gq[q]];
+            for (int q = 0; q < EPT; ++q) q4[q][u] += (double)qpart[k * nS + gq[q]];
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             const int e = t + q * MB_BLOCK;
@@ -452,20 +506,24 @@ hipError_t launch_dense_ap(int S, DenseKind kind, int64_t n, const void* A, int6
                                (const double*)A, lda, P, qpart, ksplit, st);
         else if (kind == DENSE_F32)
             hipLaunchKernelGGL(k_dense_f32<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n,
-                               (const float*)A, (const float*)Plo, qpart, ksplit, st);
+                               (const float*)A, (const float*)Plo, (float*)qpart, ksplit, st);
         else
             hipLaunchKernelGGL(k_dense_bf16<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n,
-                               (const __bf16*)A, (const __bf16*)Plo, qpart, ksplit, st);
+                               (const __bf16*)A, (const __bf16*)Plo, (float*)qpart, ksplit, st);
         return hipGetLastError();
     })
 }
 
-hipError_t launch_dense_reduce(int S, int64_t n, int ksplit, const double* qpart, const double* P,
-                               double* Q, double* part, int nwg, const DevState* st,
-                               hipStream_t stream) {
+hipError_t launch_dense_reduce(int S, DenseKind kind, int64_t n, int ksplit, const double* qpart,
+                               const double* P, double* Q, double* part, int nwg,
+                               const DevState* st, hipStream_t stream) {
     MB_DENSE_S(S, {
-        hipLaunchKernelGGL(k_dense_reduce<SS>, dim3(nwg), dim3(MB_BLOCK), 0, stream, n, ksplit,
-                           qpart, P, Q, part, st);
+        if (kind == DENSE_F64)
+            hipLaunchKernelGGL((k_dense_reduce<SS, double>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
+                               n, ksplit, qpart, P, Q, part, st);
+        else
+            hipLaunchKernelGGL((k_dense_reduce<SS, float>), dim3(nwg), dim3(MB_BLOCK), 0, stream,
+                               n, ksplit, (const float*)qpart, P, Q, part, st);
         return hipGetLastError();
     })
 }

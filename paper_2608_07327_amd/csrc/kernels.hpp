@@ -55,9 +55,11 @@ hipError_t launch_dense_ap(int S, DenseKind kind, int64_t n, const void* A, int6
                            const DevState* st, hipStream_t stream);
 int dense_ksplit(int64_t n);
 int dense_nwg_rows(int64_t n);
-hipError_t launch_dense_reduce(int S, int64_t n, int ksplit, const double* qpart, const double* P,
-                               double* Q, double* part, int nwg, const DevState* st,
-                               hipStream_t stream);
+// qpart holds FP64 partials for DENSE_F64 and FP32 partials (the matrix
+// cores' FP32 accumulators) for the low-precision kinds
+hipError_t launch_dense_reduce(int S, DenseKind kind, int64_t n, int ksplit, const double* qpart,
+                               const double* P, double* Q, double* part, int nwg,
+                               const DevState* st, hipStream_t stream);
 // Low-precision operands of the dense product, stored in the matrix cores'
 // operand order so that every wavefront load is one contiguous 1 KiB run:
 //  A: 16-row x KS-column tiles (KS = 16 for FP32, 32 for BF16), tile (rt, kc)

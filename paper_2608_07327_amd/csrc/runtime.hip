@@ -220,7 +220,8 @@ static hipError_t launch_product(Ctx& c, const Plan& pl, const double* P, double
     hipError_t e = launch_dense_ap(S, pl.kind, c.n, A, c.n, c.Plo, P, c.qpart, pl.ksplit, st,
                                    c.stream);
     if (e != hipSuccess) return e;
-    return launch_dense_reduce(S, c.n, pl.ksplit, c.qpart, P, Q, part, pl.nwg_dred, st, c.stream);
+    return launch_dense_reduce(S, pl.kind, c.n, pl.ksplit, c.qpart, P, Q, part, pl.nwg_dred, st,
+                               c.stream);
 }
 
 // one iteration of Alg. 1's loop, from Xi to the new Sigma

@@ -30,3 +30,20 @@ def test_traffic_lookup_refuses_other_sources():
     assert B.traffic_from_profiles("spmm_diffusion3d_128_traffic.json", key,
                                    ("k_dense.hip",)) is None
     assert B.traffic_from_profiles("missing.json", key) is None
+
+
+def test_traffic_lookup_by_kernel_name_on_any_grid():
+    # the dense records are looked up by kernel name: the one entry of that
+    # kernel, whatever grid it ran on
+    rec = json.load(open(os.path.join(ROOT, "profiles", "dense_8192_traffic.json")))
+    current = rec["kernel_hash"] == B.source_hash(B.DENSE_SOURCES)
+    for key, ent in rec["per_shape"].items():
+        name = key.split("@")[0]
+        got = B.traffic_from_profiles("dense_8192_traffic.json", name, B.DENSE_SOURCES,
+                                      any_grid=True)
+        assert got == (ent["bytes_per_launch"] if current else None)
+    assert B.traffic_from_profiles("dense_8192_traffic.json", "k_dense_f64<3>", B.DENSE_SOURCES,
+                                   any_grid=True) is None
+    # a name is not a key: without any_grid it matches nothing
+    assert B.traffic_from_profiles("dense_8192_traffic.json", "k_dense_f64<1>",
+                                   B.DENSE_SOURCES) is None
