@@ -14,7 +14,10 @@
 //   BF16:  v_mfma_f32_16x16x32_bf16 on a tiled BF16 copy of A.
 // Low-precision kinds accumulate in FP32 inside a workgroup; their partials
 // are stored as FP32 (the accumulators' values, half the bytes of FP64) and
-// added in FP64.
+// added in FP64.  Every kernel reads A with non-temporal loads (A is not read
+// again before the next product and does not fit the last-level cache); the
+// partials of S >= 16 columns are stored non-temporally as well (measured
+// faster there, slower for narrower blocks).
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -114,7 +117,10 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f64(int64_t n, const double*
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = rbase + 16 * t + lk + 4 * v;
                 const int j = 16 * c + li;
-                if (r < n && j < S) out[r * S + j] = acc[t][c][v];
+                if (r < n && j < S) {
+                    if constexpr (S >= 16) stream_store(out + r * S + j, acc[t][c][v]);
+                    else out[r * S + j] = acc[t][c][v];
+                }
             }
 }
 
@@ -221,7 +227,10 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_f32(int64_t n, const float* 
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = rt[t] * 16 + 4 * lk + v;
                 const int j = 16 * c + li;
-                if (r < n && j < S) out[r * S + j] = acc[t][c][v];
+                if (r < n && j < S) {
+                    if constexpr (S >= 16) stream_store(out + r * S + j, acc[t][c][v]);
+                    else out[r * S + j] = acc[t][c][v];
+                }
             }
 }
 
@@ -311,7 +320,10 @@ __global__ __launch_bounds__(MB_BLOCK) void k_dense_bf16(int64_t n, const __bf16
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = rt[t] * 16 + 4 * lk + v;
                 const int j = 16 * c + li;
-                if (r < n && j < S) out[r * S + j] = acc[t][c][v];
+                if (r < n && j < S) {
+                    if constexpr (S >= 16) stream_store(out + r * S + j, acc[t][c][v]);
+                    else out[r * S + j] = acc[t][c][v];
+                }
             }
 }
 
