@@ -641,6 +641,30 @@ def test_bf16_iterative_refinement_against_the_oracle():
     solver.close()
 
 
+@pytest.mark.parametrize("prec,n", [("fp32", 613), ("bf16", 600)])
+def test_low_precision_refinement_odd_k_steps_against_the_oracle(prec, n):
+    # orders whose column ranges hold an odd number of k-steps (FP32: 39
+    # steps of 16 over two ranges, 20 + 19; BF16: 19 steps of 32, 10 + 9)
+    # and a ragged last row tile: the products' final single step and the
+    # clamped operand rows, against the oracle's refinement with products
+    # rounded the same way
+    A = W.tiny_spd(n, 20.0, tag=(4, 64, n))
+    b = W.rng_for((4, 65, n)).standard_normal(n)
+    say("low-precision IR vs oracle, odd k-steps", prec, n)
+    lo = O.LO_FP32 if prec == "fp32" else O.LO_BF16
+    xo, io = O.ir_solve(A, b, 8, lo, ir_tol=1e-10, seed=8)
+    solver = M.Solver.from_matrix(A)
+    x, info = solver.solve(dev(b), s=8, precision=M.FP32_IR if prec == "fp32" else M.BF16_IR,
+                           precond=M.PRECOND_NONE, ir_tol=1e-10, seed=8)
+    x = x.cpu().numpy()
+    assert info["status"] == io["status"] == 0, (info, io)
+    assert abs(info["outer_iterations"] - io["outer_iterations"]) <= (0 if prec == "fp32" else 1)
+    band = 0.05 if prec == "fp32" else 0.10
+    assert abs(info["iterations"] - io["iterations"]) <= np.ceil(band * io["iterations"]), (info, io)
+    assert rel(x, xo) <= 2 * np.linalg.cond(A) * 1e-10
+    solver.close()
+
+
 def test_bf16_iterative_refinement_reports_honestly():
     n = 256
     A = W.dense_spd(n, tag=(4, 52))
