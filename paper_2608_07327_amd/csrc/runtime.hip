@@ -89,8 +89,11 @@ mbpcg_status ctx_init_common(Ctx& c, hipStream_t user_stream) {
     CK(hipEventCreateWithFlags(&c.ev_poll[0], hipEventDisableTiming));
     CK(hipEventCreateWithFlags(&c.ev_poll[1], hipEventDisableTiming));
     CK(hipEventCreateWithFlags(&c.ev_user, hipEventDisableTiming));
-    CK(hipEventCreate(&c.ev_a));
-    CK(hipEventCreate(&c.ev_b));
+    // timing-only events (the tuner's and the profile's) record without a
+    // system-scope fence: a fence writes back and invalidates the caches
+    // around the timed kernel, which the solve never does between kernels
+    CK(hipEventCreateWithFlags(&c.ev_a, hipEventDisableSystemFence));
+    CK(hipEventCreateWithFlags(&c.ev_b, hipEventDisableSystemFence));
     CK(hipHostMalloc((void**)&c.pinned, 4 * sizeof(int32_t), hipHostMallocDefault));
     CK(hipHostMalloc((void**)&c.st_host, sizeof(DevState), hipHostMallocDefault));
     DALLOC(c.st, sizeof(DevState));
@@ -399,7 +402,7 @@ static mbpcg_status run_loop(Ctx& c, const Plan& pl, const mbpcg_params& p, int 
             for (int i = 0; i < m && issued < max_it; ++i, ++issued) {
                 while ((int64_t)c.pev.size() < (issued + 1) * EV) {
                     hipEvent_t e;
-                    CK(hipEventCreate(&e));
+                    CK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
                     c.pev.push_back(e);
                 }
                 const hipEvent_t* ev = &c.pev[issued * EV];
