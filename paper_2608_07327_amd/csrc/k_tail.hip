@@ -7,6 +7,8 @@
 #include "dev_sxs.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace mb {
 
 // First stage of a two-stage fixed-order sum of per-workgroup partials:
@@ -237,18 +239,31 @@ hipError_t launch_part_reduce(int nwg, int E, const double* part, double* out, i
     return hipGetLastError();
 }
 
+// Threads of a one-workgroup tail over nwg partials of E entries: four
+// wavefronts when each thread then adds at most 32 partials (fewer
+// wavefronts to start and to hold at each barrier; the S = 16 inverse still
+// has one thread per entry), else TAIL_THREADS.
+static int tail_threads(int S, int E, int nwg) {
+    constexpr int SMALL = 256;
+    if (S > 16) return TAIL_THREADS;
+    int tpe = 1;
+    while (tpe * 2 * E <= SMALL) tpe *= 2;
+    return nwg <= 32 * tpe ? SMALL : TAIL_THREADS;
+}
+
 hipError_t launch_tail_xi(int S, int nwg, const double* part, DevState* st, hipStream_t s) {
+    const int nt = tail_threads(S, tri_count(S), nwg);
     MB_TAIL_S(S, {
-        hipLaunchKernelGGL(k_tail_xi<SS>, dim3(1), dim3(TAIL_THREADS), 0, s, part, nwg, st);
+        hipLaunchKernelGGL(k_tail_xi<SS>, dim3(1), dim3(nt), 0, s, part, nwg, st);
         return hipGetLastError();
     })
 }
 
 hipError_t launch_tail_qr(int S, int nwg, const double* part, DevState* st, double* hist, int setup,
                           hipStream_t s) {
+    const int nt = tail_threads(S, tri_count(S) + S, nwg);
     MB_TAIL_S(S, {
-        hipLaunchKernelGGL(k_tail_qr<SS>, dim3(1), dim3(TAIL_THREADS), 0, s, part, nwg, st, hist,
-                           setup);
+        hipLaunchKernelGGL(k_tail_qr<SS>, dim3(1), dim3(nt), 0, s, part, nwg, st, hist, setup);
         return hipGetLastError();
     })
 }
@@ -292,8 +307,8 @@ hipError_t launch_tail_cg0(int nwg_b, const double* part_b, int nwg_s, const dou
 
 hipError_t launch_tail_cg(int nwg_u, const double* part_u, int nwg_s, const double* part_s,
                           DevState* st, double* hist, hipStream_t s) {
-    hipLaunchKernelGGL(k_tail_cg, dim3(1), dim3(TAIL_THREADS), 0, s, part_u, nwg_u, part_s, nwg_s,
-                       st, hist);
+    const int nt = std::max(tail_threads(1, 2, nwg_u), tail_threads(1, 1, nwg_s));
+    hipLaunchKernelGGL(k_tail_cg, dim3(1), dim3(nt), 0, s, part_u, nwg_u, part_s, nwg_s, st, hist);
     return hipGetLastError();
 }
 
