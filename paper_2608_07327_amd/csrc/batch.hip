@@ -88,7 +88,15 @@ __constant__ BArgs g_bargs;
 // software grid barrier (sense by generation counter), bounded wait
 // ---------------------------------------------------------------------------
 __device__ bool grid_sync(BCtl* ctl, long long spin_limit, int* flag) {
-    __threadfence();
+    // One thread per workgroup publishes and acquires for the whole
+    // workgroup (the workgroup barrier orders its other threads' accesses
+    // around it): a device-scope release before it counts in and an acquire
+    // after it sees the new generation.  A device-scope fence writes back or
+    // invalidates the XCD's L2, so the counting and the polling use relaxed
+    // atomics and the fences are issued once each, not per thread, per
+    // atomic or per poll (an acquiring poll would invalidate the L2 under the
+    // workgroups still at work); the last arriver of a group, and the last
+    // group, acquire what the others released before they count on.
     __syncthreads();
     if (threadIdx.x == 0) {
         // two levels of arrival: workgroup b counts on its group's counter
@@ -100,23 +108,26 @@ __device__ bool grid_sync(BCtl* ctl, long long spin_limit, int* flag) {
         const unsigned groups = nb < (unsigned)BAR_GROUPS ? nb : (unsigned)BAR_GROUPS;
         const unsigned g = blockIdx.x % groups;
         const unsigned ng = (nb - g + groups - 1) / groups;   // workgroups of group g
-        const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         bool last = false;
         const unsigned a1 =
-            __hip_atomic_fetch_add(&ctl->sub[32 * g], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctl->sub[32 * g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (a1 == ng - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_store(&ctl->sub[32 * g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned a2 =
-                __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (a2 == groups - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
                 __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 last = true;
             }
         }
         if (!last) {
             long long spins = 0;
-            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(8);
                 if (++spins > spin_limit) {
                     __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -125,10 +136,10 @@ __device__ bool grid_sync(BCtl* ctl, long long spin_limit, int* flag) {
                 if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *flag = __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    __threadfence();
     const int ab = *flag;
     __syncthreads();
     return ab == 0;
