@@ -86,7 +86,7 @@ def source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-SPMM_SOURCES = ("k_sparse.hip", "dev_common.hpp", "dev_spmm.hpp")
+SPMM_SOURCES = ("k_sparse.hip", "dev_common.hpp")
 DENSE_SOURCES = ("k_dense.hip", "dev_common.hpp")
 BATCH_SOURCES = ("batch.hip", "dev_common.hpp", "dev_spmm.hpp", "dev_sxs.hpp", "dev_dd.hpp")
 

@@ -27,7 +27,6 @@
 #include <algorithm>
 #include <tuple>
 
-#include "dev_spmm.hpp"
 
 namespace mb {
 
