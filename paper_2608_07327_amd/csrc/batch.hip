@@ -714,8 +714,9 @@ __device__ double sys_sum(const BSys& y, int slot, double* sm) {
 // ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
-// one body for every phase: the register cap (168) keeps three waves per SIMD
-__global__ __launch_bounds__(MB_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_batch() {
+// one body for every phase: the register cap (128) keeps four waves per SIMD,
+// four workgroups per CU, as many as its 32 KB of LDS allows
+__global__ __launch_bounds__(MB_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_batch() {
     const BArgs& a = g_bargs;
     __shared__ double sm[BSM];
     __shared__ int smi[48];
