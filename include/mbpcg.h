@@ -242,7 +242,12 @@ mbpcg_status mbpcg_batch_create(mbpcg_batch* batch, int32_t nsys, const mbpcg_sy
 
 /* Solve every system of the batch with parameters `common` (as in
  * mbpcg_solve_batch), writing x through the pointers given at create and
- * per_system[nsys] (may be NULL).  Returns when the batch has finished. */
+ * per_system[nsys] (may be NULL).  Returns when the batch has finished.
+ * The persistent kernel's grid barrier waits at most 2^24 polls (the
+ * environment variable MBPCG_BATCH_SPIN_LIMIT, a positive integer, lowers
+ * the bound; tests use it to reach this path): a longer wait makes every
+ * workgroup exit and the call return MBPCG_ERR_HIP with mbpcg_last_error
+ * set, and the next solve starts afresh. */
 mbpcg_status mbpcg_batch_solve(mbpcg_batch batch, const mbpcg_params* common,
                                mbpcg_info* per_system, void* hip_stream);
 

@@ -11,6 +11,7 @@
 // none is active.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -143,6 +144,19 @@ __device__ bool grid_sync(BCtl* ctl, long long spin_limit, int* flag) {
     const int ab = *flag;
     __syncthreads();
     return ab == 0;
+}
+
+// Polls a workgroup makes at a grid barrier before it gives up and ends the
+// launch (all co-resident workgroups arrive long before).  The environment
+// variable MBPCG_BATCH_SPIN_LIMIT (a positive integer) lowers the bound, so
+// that a test reaches the error path with every workgroup exiting normally.
+static long long batch_spin_limit() {
+    if (const char* e = getenv("MBPCG_BATCH_SPIN_LIMIT")) {
+        char* end = nullptr;
+        const long long v = strtoll(e, &end, 10);
+        if (end != e && *end == 0 && v > 0) return v;
+    }
+    return 1ll << 24;
 }
 
 // block-wide fixed-order sum of one value per thread, by a pairwise tree
@@ -1149,7 +1163,7 @@ mbpcg_status batch_create(BatchCtx& c, int32_t nsys, const mbpcg_system* systems
     a.total_pitems = pitems;
     a.pitem_sys = d_pitems;
     a.ppart = d_ppart;
-    a.spin_limit = 1ll << 24;
+    a.spin_limit = batch_spin_limit();
     a.sys = c.d_sys;
     a.st = d_st;
     a.ctl = d_ctl;
@@ -1221,6 +1235,7 @@ mbpcg_status batch_solve(BatchCtx& c, const mbpcg_params& p, mbpcg_info* per_sys
     a.tau = p.tau > 0 ? p.tau : 1e-12;
     a.seed = p.seed;
     a.tstamp = p.profile ? c.d_ts : nullptr;
+    a.spin_limit = batch_spin_limit();
     BCK(hipMemsetAsync(a.ctl, 0, sizeof(BCtl), c.stream));
     hipLaunchKernelGGL(k_batch_state_init, dim3(nsys), dim3(MB_BLOCK), 0, c.stream, nsys, a.st,
                        c.d_sys, (int)p.max_iter, p.tol, a.tau);

@@ -166,3 +166,27 @@ def test_width_selector_measures_on_the_gpu():
         for s in ("2", "4"):
             m = r["mbpcg"][s]
             assert m["status"] == 0 and m["rel_res_true"] < 2e-8 and m["seconds"] > 0
+
+
+def test_barrier_bound_ends_the_launch_and_the_next_solve_recovers(monkeypatch):
+    # a wait beyond the grid barrier's bound (lowered from the host to one
+    # poll) makes every workgroup exit and the call report it; the context's
+    # next solve starts afresh and is bitwise the one-call solve
+    systems = W.graph_laplacian_batch(count=6, n_lo=300, n_hi=4000, tag=(5, 6))
+    items = to_items(systems)
+    say("batch barrier bound")
+    st0, i0 = M.solve_batch(items, seed=51)
+    x0 = [it["x"].clone() for it in items]
+    with M.Batch(items) as bt:
+        monkeypatch.setenv("MBPCG_BATCH_SPIN_LIMIT", "1")
+        with pytest.raises(M.MbpcgError) as err:
+            bt.solve(seed=51)
+        assert "grid barrier" in str(err.value)
+        monkeypatch.delenv("MBPCG_BATCH_SPIN_LIMIT")
+        for it in items:
+            it["x"].zero_()
+        st, infos = bt.solve(seed=51)
+        assert st == st0
+        for a, b2, ia, ib in zip(items, x0, infos, i0):
+            assert ia["iterations"] == ib["iterations"]
+            assert torch.equal(a["x"], b2)
